@@ -1,0 +1,194 @@
+/* ars.h -- C ABI of the MI355X (gfx950) all-regime, well-balanced
+ * finite-volume step of Padioleau, Tremblin, Audit, Kestener and Kokh,
+ * "A high performance and portable all-Mach regime flow solver code with
+ * well-balanced gravity", arXiv 1903.09043.
+ *
+ * The library advances the compressible Navier-Stokes equations with gravity
+ * (Sec. 1, eq. navier_stokes_gravity_nc, ideal gas of Sec. 4) on a uniform
+ * Cartesian grid with the explicit scheme of Sec. 2: acoustic / transport
+ * splitting with a relaxation Riemann solver (Sec. 2.1.2-2.1.3), the
+ * relaxation of the gravitational potential (Sec. 2.1.4) that makes the
+ * total energy rho e + rho u^2/2 + rho Phi conservative (eq.
+ * conservation_of_energy, eq. all_regime_scheme), the low-Mach correction
+ * theta = min(Ma, 1) (eq. low_mach_correction), the well-balanced gravity
+ * source (eq. well_balanced_formula) and first-order viscous and heat
+ * fluxes (Sec. 2.2).  The multi-dimensional update is unsplit: every face is
+ * evaluated from U^n with one time step.
+ *
+ * Conventions
+ *  - All arithmetic is IEEE FP64.  Gravity points along -e_z where z is the
+ *    LAST active axis (y in 2D, z in 3D); Phi = g z at cell centres.
+ *  - State: caller-owned device array of ars_state_len() doubles, SoA,
+ *    variable-major: [rho][m_0]..[m_{D-1}][E], each variable a
+ *    contiguous n_0 x n_1 x n_2 array with axis 0 fastest.
+ *    E = rho e + rho |u|^2 / 2 (gravity excluded).
+ *  - Every device buffer (state, scratch state, workspace, t, dt, schedules,
+ *    adjoint fields) is owned by the caller and passed as a raw device
+ *    pointer; the library never allocates device memory in the step,
+ *    adjoint or batch calls, which are therefore safe to capture in a graph.
+ *  - `stream` is a hipStream_t passed as void* (NULL = default stream).
+ *  - A context is not thread-safe; calls on one context must be ordered.
+ *  - Every function returns an ars_status; launches are asynchronous and a
+ *    numerical fault found by a kernel (rho <= 0, p <= 0, L <= 0 or a
+ *    non-finite value) is latched in the workspace and reported by the next
+ *    call that synchronises (ars_diagnostics, ars_fault).
+ */
+#ifndef ARS_H
+#define ARS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  ARS_OK = 0,
+  ARS_EINVAL = -1,        /* bad argument or configuration */
+  ARS_ENOMEM = -2,        /* host allocation failed */
+  ARS_EDEVICE = -3,       /* HIP runtime / launch error */
+  ARS_ENONPHYS = -4,      /* latched numerical fault (see ars_diag.fault_cell) */
+  ARS_EUNSUPPORTED = -5   /* valid configuration this build does not run */
+} ars_status;
+
+enum { ARS_BC_PERIODIC = 0, ARS_BC_WALL = 1, ARS_BC_OUTFLOW = 2 };
+enum { ARS_T_ADIABATIC = 0, ARS_T_FIXED = 1 };
+enum {
+  ARS_PROB_UNIFORM = 0,     /* params: rho, u0, u1, u2, p */
+  ARS_PROB_RB = 1,          /* params: T_bottom, T_top, rho of bottom cell (<= 0: its T), amp */
+  ARS_PROB_GRESHO = 2,      /* params: Ma                     (Sec. 4.2) */
+  ARS_PROB_SOD = 3,         /* no params                       (Sec. 4.1) */
+  ARS_PROB_ISOTHERMAL = 4   /* no params: p = rho, T = 1       (Sec. 4.3) */
+};
+
+/* Problem description (Sec. 1 closures and Sec. 4 set-ups).
+ *  dim        2 or 3 on the GPU (1 is accepted by ars_validate).
+ *  n[a], L[a] cells and box length along axis a (unused axes: 1, 1.0).
+ *  gamma      ideal-gas adiabatic index (> 1); R = 1 so T = p / rho.
+ *  g          gravity magnitude along -z (Phi = g z); 0 allowed.
+ *  mu, kappa  constant dynamic viscosity and heat conductivity (>= 0);
+ *             Stokes bulk viscosity eta = -2 mu / 3.
+ *  K          sub-characteristic factor: a_{i+1/2} = K max(rho_i c_i,
+ *             rho_{i+1} c_{i+1}), K >= 1 (the paper only requires >=).
+ *  cfl        dt = cfl / max_i lambda_i (see dt_mode).
+ *  low_mach   1: theta = min(|u*| / max(c_L, c_R), 1); 0: theta = 1.
+ *  dt_mode    0: lambda_i = sum_d (|u_d| + c)/dx_d + 2 D_i sum_d dx_d^-2
+ *                with D_i = max(4 mu/3, kappa (gamma-1)) / rho_i;
+ *             1: hyperbolic part only.
+ *  bc[a][s]   per axis a, side s (0 low, 1 high): periodic / wall / outflow.
+ *             Walls only on the gravity axis; gravity needs walls on it;
+ *             periodic must be set on both sides.
+ *  wall_noslip 1: ghost velocity -u (no-slip); 0: only the normal component
+ *             flips (free slip).
+ *  thermal[s], T_wall[s]  bottom / top wall: adiabatic (T_ghost = T) or
+ *             fixed temperature (T_ghost = 2 T_wall - T).
+ */
+typedef struct ars_config {
+  int32_t dim;
+  int32_t n[3];
+  double L[3];
+  double gamma, g, mu, kappa, K, cfl;
+  int32_t low_mach;
+  int32_t dt_mode;
+  int32_t bc[3][2];
+  int32_t wall_noslip;
+  int32_t thermal[2];
+  double T_wall[2];
+} ars_config;
+
+/* Diagnostics of a state (Sec. 4 reports max velocity, mean absolute
+ * velocity, local Mach number and kinetic energy).  Sums are volume
+ * integrals (cell volume dV); e_total = sum (E + rho Phi) dV.
+ * nu_bot / nu_top: horizontal mean of the wall conductive heat flux over
+ * the conductive-profile flux (T_bottom - T_top)/depth (fixed-T walls).
+ * fault / fault_cell: the latched numerical fault (1, smallest cell index),
+ * cleared by the call that reports it. */
+typedef struct ars_diag {
+  double mass, mom[3], e_total, e_kin, e_int, e_grav;
+  double max_u, mean_u, max_mach, nu_bot, nu_top;
+  int64_t fault_cell;
+  int32_t fault;
+  int32_t pad_;
+} ars_diag;
+
+typedef struct ars_ctx ars_ctx;
+
+/* Host-only check of a configuration (no device needed). */
+int ars_validate(const ars_config* cfg);
+
+/* Create / destroy a context (host memory only; no device allocation).
+ * Returns ARS_EUNSUPPORTED for dim == 1. */
+int ars_create(const ars_config* cfg, ars_ctx** out);
+void ars_destroy(ars_ctx* ctx);
+
+/* Number of doubles of one state: (dim + 2) * n_0 * n_1 * n_2. */
+size_t ars_state_len(const ars_ctx* ctx);
+/* Bytes of the caller-owned workspace every device call takes (256-byte
+ * aligned device memory; contents managed by the library). */
+size_t ars_workspace_bytes(const ars_ctx* ctx);
+/* Prepare a freshly allocated workspace (clears the rate slots and the
+ * fault latch).  Call once before its first use.  Asynchronous. */
+int ars_workspace_init(ars_ctx* ctx, void* d_work, void* stream);
+
+/* Launch shape of the fused step: number of planes one workgroup marches
+ * through along the vertical axis (results do not depend on it). */
+int ars_set_zchunk(ars_ctx* ctx, int zchunk);
+int ars_get_zchunk(const ars_ctx* ctx);
+
+/* Build an initial state (Sec. 4 problems; hydrostatic bases from the
+ * discrete equilibrium eq. well_balanced_formula, Sec. 4.3/4.5) on the
+ * host and copy it to d_state (synchronous on `stream`).  RB perturbation:
+ * p = rho (T + amp (2 U_i - 1)), U_i the i-th SplitMix64 output of `seed`
+ * scaled to [0,1) by its top 53 bits, i the linear cell index. */
+int ars_init_state(ars_ctx* ctx, int problem, const double* params, int n_params, uint64_t seed,
+                   double* d_state, void* stream);
+/* Same, into a host array of ars_state_len() doubles (no device use). */
+int ars_init_state_host(const ars_ctx* ctx, int problem, const double* params, int n_params, uint64_t seed,
+                        double* h_state);
+
+/* dt = cfl / max_i lambda_i of d_state (time-step kernel, Sec. 3.2),
+ * written to the device double *d_dt.  Also prepares the workspace for
+ * ars_step.  Asynchronous. */
+int ars_compute_dt(ars_ctx* ctx, const double* d_state, void* d_work, double* d_dt, void* stream);
+
+/* Advance n_steps explicit steps (eq. all_regime_scheme + dissipative
+ * fluxes + relaxation, Sec. 2).  Step s uses dt = cfl / max lambda of its
+ * own input state; the first dt is read from *d_dt (as left by
+ * ars_compute_dt or a previous ars_step), and on return *d_dt holds the
+ * next step's dt and *d_t has been advanced by the sum of the dts used.
+ * d_tmp: caller scratch state of the same size.  The result is in d_state.
+ * d_dt_log (nullable): receives the dt of every step (n_steps doubles).
+ * Asynchronous; numerical faults are latched. */
+int ars_step(ars_ctx* ctx, double* d_state, double* d_tmp, void* d_work, int n_steps, double* d_t, double* d_dt,
+             double* d_dt_log, void* stream);
+
+/* Same with a prescribed per-step dt schedule d_dt_sched[n_steps] (device);
+ * used with a frozen schedule by the adjoint and finite-difference checks.
+ * *d_t advanced; *d_dt untouched. */
+int ars_step_sched(ars_ctx* ctx, double* d_state, double* d_tmp, void* d_work, int n_steps,
+                   const double* d_dt_sched, double* d_t, void* stream);
+
+/* Reference path: the same step as separate phase kernels (ghosts and
+ * primitives, faces, acoustic cell values, fluxes, update) with their
+ * intermediate arrays in a second caller-owned buffer d_work_ref of
+ * ars_workspace_bytes_ref bytes; kept to check the fused kernel bit for
+ * bit.  dt of step s is d_dt_sched[s]. */
+size_t ars_workspace_bytes_ref(const ars_ctx* ctx);
+int ars_step_ref(ars_ctx* ctx, double* d_state, double* d_tmp, void* d_work, void* d_work_ref, int n_steps,
+                 const double* d_dt_sched, void* stream);
+
+/* Diagnostics of d_state into *h_out (synchronises `stream`).  Returns
+ * ARS_ENONPHYS (and clears the latch) if a fault was latched. */
+int ars_diagnostics(ars_ctx* ctx, const double* d_state, void* d_work, ars_diag* h_out, void* stream);
+
+/* Read (and clear) the fault latch without diagnostics (synchronises). */
+int ars_fault(ars_ctx* ctx, void* d_work, int64_t* fault_cell, void* stream);
+
+const char* ars_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ARS_H */

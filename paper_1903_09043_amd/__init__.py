@@ -1,0 +1,257 @@
+"""MI355X (gfx950) all-regime, well-balanced finite-volume step of
+arXiv 1903.09043 -- thin Python binding of ``include/ars.h``.
+
+Every step of the method runs in the HIP library ``libars.so`` built in this
+directory (``python -m paper_1903_09043_amd.build``); this module only
+marshals arguments.  PyTorch provides device memory and the stream.  There is
+no CPU fallback: if the library is missing, importing the binding raises.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import workloads  # noqa: F401  (problem set-ups)
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libars.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, ENONPHYS, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+BC_PERIODIC, BC_WALL, BC_OUTFLOW = 0, 1, 2
+
+
+class ArsError(RuntimeError):
+    def __init__(self, status, what=""):
+        self.status = status
+        super().__init__(f"{what}: {lib().ars_strerror(status).decode()} ({status})")
+
+
+class ArsConfig(C.Structure):
+    _fields_ = [
+        ("dim", C.c_int32),
+        ("n", C.c_int32 * 3),
+        ("L", C.c_double * 3),
+        ("gamma", C.c_double), ("g", C.c_double), ("mu", C.c_double),
+        ("kappa", C.c_double), ("K", C.c_double), ("cfl", C.c_double),
+        ("low_mach", C.c_int32),
+        ("dt_mode", C.c_int32),
+        ("bc", (C.c_int32 * 2) * 3),
+        ("wall_noslip", C.c_int32),
+        ("thermal", C.c_int32 * 2),
+        ("T_wall", C.c_double * 2),
+    ]
+
+
+class ArsDiag(C.Structure):
+    _fields_ = [
+        ("mass", C.c_double), ("mom", C.c_double * 3), ("e_total", C.c_double), ("e_kin", C.c_double),
+        ("e_int", C.c_double), ("e_grav", C.c_double), ("max_u", C.c_double), ("mean_u", C.c_double),
+        ("max_mach", C.c_double), ("nu_bot", C.c_double), ("nu_top", C.c_double),
+        ("fault_cell", C.c_int64), ("fault", C.c_int32), ("pad_", C.c_int32),
+    ]
+
+
+# (name, restype, argtypes) of every exported entry point of include/ars.h
+_VP, _DP, _CP = C.c_void_p, C.POINTER(C.c_double), C.POINTER(ArsConfig)
+SIGNATURES = [
+    ("ars_validate", C.c_int, [_CP]),
+    ("ars_create", C.c_int, [_CP, C.POINTER(_VP)]),
+    ("ars_destroy", None, [_VP]),
+    ("ars_state_len", C.c_size_t, [_VP]),
+    ("ars_workspace_bytes", C.c_size_t, [_VP]),
+    ("ars_workspace_init", C.c_int, [_VP, _VP, _VP]),
+    ("ars_set_zchunk", C.c_int, [_VP, C.c_int]),
+    ("ars_get_zchunk", C.c_int, [_VP]),
+    ("ars_init_state", C.c_int, [_VP, C.c_int, _DP, C.c_int, C.c_uint64, _VP, _VP]),
+    ("ars_init_state_host", C.c_int, [_VP, C.c_int, _DP, C.c_int, C.c_uint64, _DP]),
+    ("ars_compute_dt", C.c_int, [_VP, _VP, _VP, _VP, _VP]),
+    ("ars_step", C.c_int, [_VP, _VP, _VP, _VP, C.c_int, _VP, _VP, _VP, _VP]),
+    ("ars_step_sched", C.c_int, [_VP, _VP, _VP, _VP, C.c_int, _VP, _VP, _VP]),
+    ("ars_workspace_bytes_ref", C.c_size_t, [_VP]),
+    ("ars_step_ref", C.c_int, [_VP, _VP, _VP, _VP, _VP, C.c_int, _VP, _VP]),
+    ("ars_diagnostics", C.c_int, [_VP, _VP, _VP, C.POINTER(ArsDiag), _VP]),
+    ("ars_fault", C.c_int, [_VP, _VP, C.POINTER(C.c_int64), _VP]),
+    ("ars_strerror", C.c_char_p, [C.c_int]),
+]
+
+_lib = None
+
+
+def lib():
+    """Load libars.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1903_09043_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        for name, res, args in SIGNATURES:
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def make_config(cfg: dict) -> ArsConfig:
+    c = ArsConfig()
+    c.dim = int(cfg["dim"])
+    n = list(cfg["n"]) + [1] * (3 - len(cfg["n"]))
+    Ls = list(cfg["L"]) + [1.0] * (3 - len(cfg["L"]))
+    for a in range(3):
+        c.n[a] = int(n[a])
+        c.L[a] = float(Ls[a])
+    c.gamma = float(cfg.get("gamma", 5.0 / 3.0))
+    c.g = float(cfg.get("g", 0.0))
+    c.mu = float(cfg.get("mu", 0.0))
+    c.kappa = float(cfg.get("kappa", 0.0))
+    c.K = float(cfg.get("K", 1.1))
+    c.cfl = float(cfg.get("cfl", 0.4))
+    c.low_mach = int(cfg.get("low_mach", 1))
+    c.dt_mode = int(cfg.get("dt_mode", 0))
+    bc = cfg.get("bc", [[BC_PERIODIC, BC_PERIODIC]] * 3)
+    for a in range(3):
+        for s in range(2):
+            c.bc[a][s] = int(bc[a][s]) if a < len(bc) else BC_PERIODIC
+    c.wall_noslip = int(cfg.get("wall_noslip", 1))
+    th = cfg.get("thermal", [0, 0])
+    c.thermal[0], c.thermal[1] = int(th[0]), int(th[1])
+    tw = cfg.get("T_wall", [1.0, 1.0])
+    c.T_wall[0], c.T_wall[1] = float(tw[0]), float(tw[1])
+    return c
+
+
+def validate(cfg: dict) -> int:
+    c = make_config(cfg)
+    return lib().ars_validate(C.byref(c))
+
+
+def _check(rc, what):
+    if rc != OK:
+        raise ArsError(rc, what)
+
+
+def state_shape(cfg: dict):
+    return (int(cfg["dim"]) + 2,) + tuple(int(cfg["n"][a]) for a in reversed(range(cfg["dim"])))
+
+
+class Context:
+    """Owns an ars_ctx (host memory only)."""
+
+    def __init__(self, cfg: dict):
+        self.cfg = dict(cfg)
+        self._c = make_config(cfg)
+        h = C.c_void_p()
+        _check(lib().ars_create(C.byref(self._c), C.byref(h)), "ars_create")
+        self.h = h
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.ars_destroy(self.h)
+            self.h = None
+
+    @property
+    def state_len(self):
+        return lib().ars_state_len(self.h)
+
+    @property
+    def workspace_bytes(self):
+        return lib().ars_workspace_bytes(self.h)
+
+    def init_host(self, problem: int, params=(), seed: int = 0) -> np.ndarray:
+        out = np.zeros(state_shape(self.cfg), dtype=np.float64)
+        p = np.asarray(list(params) + [0.0], dtype=np.float64)
+        _check(lib().ars_init_state_host(self.h, int(problem), p.ctypes.data_as(_DP), len(params),
+                                         C.c_uint64(seed), out.ctypes.data_as(_DP)), "ars_init_state_host")
+        return out
+
+    def set_zchunk(self, z: int):
+        _check(lib().ars_set_zchunk(self.h, int(z)), "ars_set_zchunk")
+
+    def zchunk(self) -> int:
+        return lib().ars_get_zchunk(self.h)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+class Solver:
+    """Device state + workspace for one problem; every call goes through the
+    C ABI on torch's current stream."""
+
+    def __init__(self, cfg: dict, device="cuda"):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("ars.Solver needs a GPU (no CPU fallback)")
+        self.torch = torch
+        self.ctx = Context(cfg)
+        self.cfg = self.ctx.cfg
+        self.device = torch.device(device)
+        shape = state_shape(cfg)
+        self.U = torch.zeros(shape, dtype=torch.float64, device=self.device)
+        self.tmp = torch.empty_like(self.U)
+        self.work = torch.zeros(self.ctx.workspace_bytes, dtype=torch.uint8, device=self.device)
+        self.t = torch.zeros(1, dtype=torch.float64, device=self.device)
+        self.dt = torch.zeros(1, dtype=torch.float64, device=self.device)
+        self._wref = None
+        _check(lib().ars_workspace_init(self.ctx.h, _ptr(self.work), self.stream), "ars_workspace_init")
+
+    @property
+    def stream(self):
+        return C.c_void_p(self.torch.cuda.current_stream(self.device).cuda_stream)
+
+    def init(self, problem: int, params=(), seed: int = 0):
+        p = np.asarray(list(params) + [0.0], dtype=np.float64)
+        _check(lib().ars_init_state(self.ctx.h, int(problem), p.ctypes.data_as(_DP), len(params),
+                                    C.c_uint64(seed), _ptr(self.U), self.stream), "ars_init_state")
+        self.t.zero_()
+        self.compute_dt()
+        return self
+
+    def set_state(self, U):
+        self.U.copy_(self.torch.as_tensor(U, dtype=self.torch.float64).to(self.device))
+        self.compute_dt()
+        return self
+
+    def compute_dt(self):
+        _check(lib().ars_compute_dt(self.ctx.h, _ptr(self.U), _ptr(self.work), _ptr(self.dt), self.stream),
+               "ars_compute_dt")
+        return self.dt
+
+    def step(self, n: int = 1, dt_log=None):
+        _check(lib().ars_step(self.ctx.h, _ptr(self.U), _ptr(self.tmp), _ptr(self.work), int(n), _ptr(self.t),
+                              _ptr(self.dt), _ptr(dt_log) if dt_log is not None else None, self.stream),
+               "ars_step")
+        return self
+
+    def step_sched(self, dt_sched):
+        dt_sched = dt_sched.to(self.device, self.torch.float64).contiguous()
+        _check(lib().ars_step_sched(self.ctx.h, _ptr(self.U), _ptr(self.tmp), _ptr(self.work), dt_sched.numel(),
+                                    _ptr(dt_sched), _ptr(self.t), self.stream), "ars_step_sched")
+        return self
+
+    def step_ref(self, dt_sched):
+        if self._wref is None:
+            nb = lib().ars_workspace_bytes_ref(self.ctx.h)
+            self._wref = self.torch.empty(nb, dtype=self.torch.uint8, device=self.device)
+        dt_sched = dt_sched.to(self.device, self.torch.float64).contiguous()
+        _check(lib().ars_step_ref(self.ctx.h, _ptr(self.U), _ptr(self.tmp), _ptr(self.work), _ptr(self._wref),
+                                  dt_sched.numel(), _ptr(dt_sched), self.stream), "ars_step_ref")
+        return self
+
+    def diagnostics(self, raise_on_fault=True) -> dict:
+        d = ArsDiag()
+        rc = lib().ars_diagnostics(self.ctx.h, _ptr(self.U), _ptr(self.work), C.byref(d), self.stream)
+        if rc not in (OK, ENONPHYS) or (rc == ENONPHYS and raise_on_fault):
+            raise ArsError(rc, f"ars_diagnostics (fault cell {d.fault_cell})")
+        return dict(mass=d.mass, mom=list(d.mom), e_total=d.e_total, e_kin=d.e_kin, e_int=d.e_int,
+                    e_grav=d.e_grav, max_u=d.max_u, mean_u=d.mean_u, max_mach=d.max_mach, nu_bot=d.nu_bot,
+                    nu_top=d.nu_top, fault=d.fault, fault_cell=d.fault_cell)
+
+    def fault(self):
+        fc = C.c_int64(-1)
+        rc = lib().ars_fault(self.ctx.h, _ptr(self.work), C.byref(fc), self.stream)
+        return rc, fc.value
+
+    def numpy(self):
+        return self.U.detach().cpu().numpy()

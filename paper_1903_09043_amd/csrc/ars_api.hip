@@ -1,0 +1,468 @@
+// ars_api.hip -- the C ABI of include/ars.h: configuration checks, context,
+// host-side initial states, and the launch sequences of the step,
+// reductions and diagnostics.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/ars.h"
+#include "ars_dev.h"
+#include "ars_internal.h"
+
+struct ars_ctx {
+  ars_config cfg;
+  ars::Params P;
+  ars::TileShape ts;
+  size_t len;
+};
+
+namespace {
+
+constexpr size_t CTL_BYTES = 256;
+
+int check(hipError_t e) { return e == hipSuccess ? ARS_OK : ARS_EDEVICE; }
+
+bool lateral_ok(const ars_config* c, int a) {
+  for (int s = 0; s < 2; ++s) {
+    const int b = c->bc[a][s];
+    if (b != ARS_BC_PERIODIC && b != ARS_BC_OUTFLOW) return false;
+  }
+  return (c->bc[a][0] == ARS_BC_PERIODIC) == (c->bc[a][1] == ARS_BC_PERIODIC);
+}
+
+// SplitMix64 generator (Steele, Lea and Flood 2014), one output per call.
+uint64_t splitmix_out(uint64_t* s) {
+  *s += 0x9E3779B97F4A7C15ULL;
+  uint64_t v = *s;
+  v ^= v >> 30;
+  v *= 0xBF58476D1CE4E5B9ULL;
+  v ^= v >> 27;
+  v *= 0x94D049BB133111EBULL;
+  v ^= v >> 31;
+  return v;
+}
+
+ars::Params derive(const ars_config* c) {
+  ars::Params P{};
+  P.dim = c->dim;
+  const int z = c->dim - 1;
+  P.nx = c->n[0];
+  P.ny = (c->dim == 3) ? c->n[1] : 1;
+  P.nz = c->n[z];
+  for (int s = 0; s < 2; ++s) {
+    P.bcx[s] = c->bc[0][s];
+    P.bcy[s] = (c->dim == 3) ? c->bc[1][s] : ars::BC_PERIODIC;
+    P.bcz[s] = c->bc[z][s];
+  }
+  P.ncell = (long long)P.nx * P.ny * P.nz;
+  const double hx = c->L[0] / (double)c->n[0];
+  const double hy = (c->dim == 3) ? c->L[1] / (double)c->n[1] : 1.0;
+  const double hz = c->L[z] / (double)c->n[z];
+  const double h[3] = {hx, hy, hz};
+  for (int a = 0; a < 3; ++a) {
+    P.dx[a] = h[a];
+    P.idx[a] = 1.0 / h[a];
+    P.qidx[a] = 0.25 * P.idx[a];
+  }
+  P.gamma = c->gamma;
+  P.gm1 = c->gamma - 1.0;
+  P.g = c->g;
+  P.K = c->K;
+  P.cfl = c->cfl;
+  P.mu = c->mu;
+  P.kappa = c->kappa;
+  P.eta = (-2.0 * c->mu) / 3.0;
+  const double dv = (4.0 * c->mu) / 3.0, dk = c->kappa * P.gm1;
+  P.dmax = (dv < dk) ? dk : dv;
+  double s2 = P.idx[0] * P.idx[0];
+  if (c->dim == 3) s2 = s2 + P.idx[1] * P.idx[1];
+  s2 = s2 + P.idx[2] * P.idx[2];
+  P.sumidx2 = s2;
+  for (int s = 0; s < 2; ++s) {
+    P.Tw2[s] = 2.0 * c->T_wall[s];
+    P.thermal[s] = c->thermal[s];
+  }
+  P.noslip = c->wall_noslip;
+  P.dt_mode = c->dt_mode;
+  P.low_mach = c->low_mach;
+  P.diss = (c->mu > 0.0 || c->kappa > 0.0) ? 1 : 0;
+  return P;
+}
+
+ars::Control* ctl_of(void* w) { return (ars::Control*)w; }
+
+}  // namespace
+
+extern "C" {
+
+const char* ars_strerror(int s) {
+  switch (s) {
+    case ARS_OK: return "ok";
+    case ARS_EINVAL: return "invalid argument or configuration";
+    case ARS_ENOMEM: return "host allocation failed";
+    case ARS_EDEVICE: return "HIP runtime or launch error";
+    case ARS_ENONPHYS: return "non-physical state (rho, p or L not positive, or non-finite)";
+    case ARS_EUNSUPPORTED: return "configuration not supported by this build";
+    default: return "unknown status";
+  }
+}
+
+int ars_validate(const ars_config* c) {
+  if (!c) return ARS_EINVAL;
+  if (c->dim < 1 || c->dim > 3) return ARS_EINVAL;
+  const int z = c->dim - 1;
+  for (int a = 0; a < c->dim; ++a) {
+    if (c->n[a] < 1 || !(c->L[a] > 0.0) || !std::isfinite(c->L[a])) return ARS_EINVAL;
+    if (a != z && !lateral_ok(c, a)) return ARS_EINVAL;
+  }
+  for (int s = 0; s < 2; ++s) {
+    const int b = c->bc[z][s];
+    if (b != ARS_BC_PERIODIC && b != ARS_BC_WALL && b != ARS_BC_OUTFLOW) return ARS_EINVAL;
+  }
+  if ((c->bc[z][0] == ARS_BC_PERIODIC) != (c->bc[z][1] == ARS_BC_PERIODIC)) return ARS_EINVAL;
+  if (c->g != 0.0 && !(c->bc[z][0] == ARS_BC_WALL && c->bc[z][1] == ARS_BC_WALL)) return ARS_EINVAL;
+  if (!(c->gamma > 1.0) || !(c->mu >= 0.0) || !(c->kappa >= 0.0) || !(c->K >= 1.0) || !(c->cfl > 0.0))
+    return ARS_EINVAL;
+  if (!std::isfinite(c->g) || !std::isfinite(c->mu) || !std::isfinite(c->kappa) || !std::isfinite(c->K) ||
+      !std::isfinite(c->cfl) || !std::isfinite(c->gamma))
+    return ARS_EINVAL;
+  if (c->dt_mode != 0 && c->dt_mode != 1) return ARS_EINVAL;
+  if (c->low_mach != 0 && c->low_mach != 1) return ARS_EINVAL;
+  for (int s = 0; s < 2; ++s)
+    if (c->thermal[s] != ARS_T_ADIABATIC && c->thermal[s] != ARS_T_FIXED) return ARS_EINVAL;
+  long long cells = 1;
+  for (int a = 0; a < c->dim; ++a) cells *= c->n[a];
+  if (cells > (1ll << 31)) return ARS_EINVAL;
+  return ARS_OK;
+}
+
+int ars_create(const ars_config* cfg, ars_ctx** out) {
+  if (!out) return ARS_EINVAL;
+  *out = nullptr;
+  int rc = ars_validate(cfg);
+  if (rc != ARS_OK) return rc;
+  if (cfg->dim == 1) return ARS_EUNSUPPORTED;
+  ars_ctx* c = new (std::nothrow) ars_ctx;
+  if (!c) return ARS_ENOMEM;
+  c->cfg = *cfg;
+  c->P = derive(cfg);
+  // vertical chunk: enough workgroups to fill 256 CUs several times over
+  const long long cols = (long long)c->P.nx * c->P.ny;
+  int zc;
+  if (cfg->dim == 3) {
+    const long long tiles = ((c->P.nx + 27) / 28) * (long long)((c->P.ny + 11) / 12);
+    const long long want = 1536;
+    long long nch = std::max(1ll, std::min((long long)c->P.nz, want / std::max(1ll, tiles)));
+    zc = (int)((c->P.nz + nch - 1) / nch);
+  } else {
+    const long long tiles = (c->P.nx + 59) / 60;
+    const long long want = 2048;
+    long long nch = std::max(1ll, std::min((long long)c->P.nz / 4 + 1, want / std::max(1ll, tiles)));
+    zc = (int)((c->P.nz + nch - 1) / nch);
+  }
+  (void)cols;
+  c->ts.zchunk = std::max(1, zc);
+  c->len = (size_t)(cfg->dim + 2) * (size_t)c->P.ncell;
+  *out = c;
+  return ARS_OK;
+}
+
+void ars_destroy(ars_ctx* c) { delete c; }
+
+size_t ars_state_len(const ars_ctx* c) { return c ? c->len : 0; }
+
+size_t ars_workspace_bytes(const ars_ctx* c) {
+  if (!c) return 0;
+  return CTL_BYTES + ars::diag_partial_bytes(c->P) + 32 * sizeof(double);
+}
+
+size_t ars_workspace_bytes_ref(const ars_ctx* c) { return c ? ars::ref_workspace_bytes(c->P) : 0; }
+
+int ars_set_zchunk(ars_ctx* c, int zchunk) {
+  if (!c || zchunk < 1) return ARS_EINVAL;
+  c->ts.zchunk = zchunk;
+  return ARS_OK;
+}
+
+int ars_get_zchunk(const ars_ctx* c) { return c ? c->ts.zchunk : -1; }
+
+int ars_workspace_init(ars_ctx* c, void* d_work, void* stream) {
+  if (!c || !d_work) return ARS_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  if (ars::launch_ctl_prep(ctl_of(d_work), 0, s) != hipSuccess) return ARS_EDEVICE;
+  return check(ars::launch_ctl_prep(ctl_of(d_work), 2, s));
+}
+
+// -------------------------------------------------------------- init states
+int ars_init_state_host(const ars_ctx* ctx, int problem, const double* prm, int nprm, uint64_t seed,
+                        double* h) {
+  if (!ctx || !h || (nprm > 0 && !prm) || nprm < 0) return ARS_EINVAL;
+  const ars_config& c = ctx->cfg;
+  const ars::Params& P = ctx->P;
+  const int D = c.dim;
+  const long long N = P.ncell;
+  const double gm1 = c.gamma - 1.0;
+  auto param = [&](int i, double d) { return i < nprm ? prm[i] : d; };
+  std::fill(h, h + (size_t)(D + 2) * N, 0.0);
+  const double dz = P.dx[2];
+  auto phi = [&](int k) { return c.g * (((double)k + 0.5) * dz); };
+  switch (problem) {
+    case ARS_PROB_UNIFORM: {
+      const double rho = param(0, 1.0), p = param(4, 1.0);
+      const double u[3] = {param(1, 0.0), param(2, 0.0), param(3, 0.0)};
+      double kin = 0.0;
+      for (int k = 0; k < D; ++k) kin = kin + u[k] * u[k];
+      const double E = p / gm1 + 0.5 * rho * kin;
+      for (long long i = 0; i < N; ++i) {
+        h[i] = rho;
+        for (int k = 0; k < D; ++k) h[(1 + k) * N + i] = rho * u[k];
+        h[(D + 1) * N + i] = E;
+      }
+      return ARS_OK;
+    }
+    case ARS_PROB_RB:
+    case ARS_PROB_ISOTHERMAL: {
+      // Column profile of the discrete hydrostatic equilibrium: linear T
+      // (or T = 1), densities by the recursion of eq. well_balanced_formula
+      // with p = rho T.
+      const bool iso = problem == ARS_PROB_ISOTHERMAL;
+      const double Tb = iso ? 1.0 : param(0, 1.0);
+      const double Tt = iso ? 1.0 : param(1, 0.5);
+      const double amp = iso ? 0.0 : param(3, 0.0);
+      const double Lz = c.L[D - 1];
+      std::vector<double> Tcol(P.nz), rcol(P.nz);
+      for (int k = 0; k < P.nz; ++k) {
+        const double zk = ((double)k + 0.5) * dz;
+        Tcol[k] = Tb + (Tt - Tb) * (zk / Lz);
+      }
+      double r0 = iso ? std::exp(-(c.g * (0.5 * dz))) : param(2, -1.0);
+      if (!(r0 > 0.0)) r0 = Tcol[0];
+      rcol[0] = r0;
+      for (int k = 1; k < P.nz; ++k) {
+        const double delta = phi(k) - phi(k - 1);
+        rcol[k] = (rcol[k - 1] * (Tcol[k - 1] - 0.5 * delta)) / (Tcol[k] + 0.5 * delta);
+      }
+      uint64_t st = seed;
+      const long long plane = (long long)P.nx * P.ny;
+      for (long long i = 0; i < N; ++i) {
+        const int k = (int)(i / plane);
+        const uint64_t bits = splitmix_out(&st) >> 11;
+        const double u01 = (double)bits * 0x1.0p-53;
+        const double dT = amp * (2.0 * u01 - 1.0);
+        h[i] = rcol[k];
+        h[(D + 1) * N + i] = (rcol[k] * (Tcol[k] + dT)) / gm1;
+      }
+      return ARS_OK;
+    }
+    case ARS_PROB_GRESHO: {
+      if (D != 2) return ARS_EINVAL;
+      const double Ma = param(0, 1e-3);
+      const double p0 = 1.0 / (c.gamma * Ma * Ma);
+      const double xc = 0.5 * c.L[0], yc = 0.5 * c.L[1];
+      const double hx = P.dx[0], hy = P.dx[2];
+      for (int j = 0; j < P.nz; ++j) {
+        const double y = ((double)j + 0.5) * hy - yc;
+        for (int i = 0; i < P.nx; ++i) {
+          const double x = ((double)i + 0.5) * hx - xc;
+          const double r = std::sqrt(x * x + y * y);
+          double ut, p;
+          if (r < 0.2) {
+            ut = 5.0 * r;
+            p = p0 + 12.5 * r * r;
+          } else if (r < 0.4) {
+            ut = 2.0 - 5.0 * r;
+            p = p0 + 12.5 * r * r + 4.0 - 20.0 * r + 4.0 * std::log(5.0 * r);
+          } else {
+            ut = 0.0;
+            p = p0 - 2.0 + 4.0 * std::log(2.0);
+          }
+          const double ux = -(ut * y) / r, uy = (ut * x) / r;
+          const long long cidx = i + (long long)P.nx * j;
+          h[cidx] = 1.0;
+          h[N + cidx] = 1.0 * ux;
+          h[2 * N + cidx] = 1.0 * uy;
+          h[3 * N + cidx] = p / gm1 + 0.5 * 1.0 * (ux * ux + uy * uy);
+        }
+      }
+      return ARS_OK;
+    }
+    case ARS_PROB_SOD: {
+      const double hx = P.dx[0];
+      for (long long i = 0; i < N; ++i) {
+        const int ix = (int)(i % P.nx);
+        const double x = ((double)ix + 0.5) * hx;
+        const bool left = x < 0.5 * c.L[0];
+        h[i] = left ? 1.0 : 0.125;
+        h[(D + 1) * N + i] = (left ? 1.0 : 0.1) / gm1;
+      }
+      return ARS_OK;
+    }
+    default:
+      return ARS_EINVAL;
+  }
+}
+
+int ars_init_state(ars_ctx* ctx, int problem, const double* prm, int nprm, uint64_t seed, double* d_state,
+                   void* stream) {
+  if (!ctx || !d_state) return ARS_EINVAL;
+  std::vector<double> h;
+  try {
+    h.resize(ctx->len);
+  } catch (...) {
+    return ARS_ENOMEM;
+  }
+  int rc = ars_init_state_host(ctx, problem, prm, nprm, seed, h.data());
+  if (rc != ARS_OK) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  if (hipMemcpyAsync(d_state, h.data(), ctx->len * sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess)
+    return ARS_EDEVICE;
+  return check(hipStreamSynchronize(s));
+}
+
+// ---------------------------------------------------------------- stepping
+int ars_compute_dt(ars_ctx* ctx, const double* d_state, void* d_work, double* d_dt, void* stream) {
+  if (!ctx || !d_state || !d_work || !d_dt) return ARS_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  ars::Control* ctl = ctl_of(d_work);
+  if (ars::launch_ctl_prep(ctl, 0, s) != hipSuccess) return ARS_EDEVICE;
+  if (ars::launch_rate_reduce(ctx->P, d_state, &ctl->lammax[0], s) != hipSuccess) return ARS_EDEVICE;
+  return check(ars::launch_dt_finish(ctx->P, ctl, 0, d_dt, s));
+}
+
+int ars_step(ars_ctx* ctx, double* d_state, double* d_tmp, void* d_work, int n, double* d_t, double* d_dt,
+             double* d_dt_log, void* stream) {
+  if (!ctx || !d_state || !d_tmp || !d_work || !d_dt || n < 0 || d_state == d_tmp) return ARS_EINVAL;
+  if (n == 0) return ARS_OK;
+  hipStream_t s = (hipStream_t)stream;
+  ars::Control* ctl = ctl_of(d_work);
+  if (ars::launch_ctl_prep(ctl, 1, s) != hipSuccess) return ARS_EDEVICE;
+  double* src = d_state;
+  double* dst = d_tmp;
+  for (int st = 0; st < n; ++st) {
+    ars::StepIO io{};
+    io.rate_in = st == 0 ? nullptr : &ctl->lammax[st % 3];
+    io.dt_in = d_dt;
+    io.rate_out = &ctl->lammax[(st + 1) % 3];
+    io.clear_slot = &ctl->lammax[(st + 2) % 3];
+    io.t = d_t;
+    io.dt_log = d_dt_log ? d_dt_log + st : nullptr;
+    io.ctl = ctl;
+    if (ars::launch_step_fused(ctx->P, src, dst, io, ctx->ts, s) != hipSuccess) return ARS_EDEVICE;
+    std::swap(src, dst);
+  }
+  if (src != d_state) {
+    if (hipMemcpyAsync(d_state, src, ctx->len * sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess)
+      return ARS_EDEVICE;
+  }
+  return check(ars::launch_dt_finish(ctx->P, ctl, n % 3, d_dt, s));
+}
+
+int ars_step_sched(ars_ctx* ctx, double* d_state, double* d_tmp, void* d_work, int n, const double* d_dt_sched,
+                   double* d_t, void* stream) {
+  if (!ctx || !d_state || !d_tmp || !d_work || !d_dt_sched || n < 0 || d_state == d_tmp) return ARS_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  ars::Control* ctl = ctl_of(d_work);
+  double* src = d_state;
+  double* dst = d_tmp;
+  for (int st = 0; st < n; ++st) {
+    ars::StepIO io{};
+    io.rate_in = nullptr;
+    io.dt_in = d_dt_sched + st;
+    io.rate_out = nullptr;
+    io.clear_slot = nullptr;
+    io.t = d_t;
+    io.dt_log = nullptr;
+    io.ctl = ctl;
+    if (ars::launch_step_fused(ctx->P, src, dst, io, ctx->ts, s) != hipSuccess) return ARS_EDEVICE;
+    std::swap(src, dst);
+  }
+  if (src != d_state) {
+    if (hipMemcpyAsync(d_state, src, ctx->len * sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess)
+      return ARS_EDEVICE;
+  }
+  return ARS_OK;
+}
+
+int ars_step_ref(ars_ctx* ctx, double* d_state, double* d_tmp, void* d_work, void* d_work_ref, int n,
+                 const double* d_dt_sched, void* stream) {
+  if (!ctx || !d_state || !d_tmp || !d_work || !d_work_ref || !d_dt_sched || n < 0 || d_state == d_tmp)
+    return ARS_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  ars::Control* ctl = ctl_of(d_work);
+  double* src = d_state;
+  double* dst = d_tmp;
+  for (int st = 0; st < n; ++st) {
+    if (ars::launch_step_ref(ctx->P, src, dst, d_work_ref, d_dt_sched + st, ctl, s) != hipSuccess)
+      return ARS_EDEVICE;
+    std::swap(src, dst);
+  }
+  if (src != d_state) {
+    if (hipMemcpyAsync(d_state, src, ctx->len * sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess)
+      return ARS_EDEVICE;
+  }
+  return ARS_OK;
+}
+
+int ars_fault(ars_ctx* ctx, void* d_work, int64_t* fault_cell, void* stream) {
+  if (!ctx || !d_work) return ARS_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  ars::Control h{};
+  if (hipMemcpyAsync(&h, d_work, sizeof(ars::Control), hipMemcpyDeviceToHost, s) != hipSuccess) return ARS_EDEVICE;
+  if (hipStreamSynchronize(s) != hipSuccess) return ARS_EDEVICE;
+  if (fault_cell) *fault_cell = h.fault ? (int64_t)h.fault_cell : -1;
+  if (h.fault) {
+    if (ars::launch_ctl_prep(ctl_of(d_work), 2, s) != hipSuccess) return ARS_EDEVICE;
+    return ARS_ENONPHYS;
+  }
+  return ARS_OK;
+}
+
+int ars_diagnostics(ars_ctx* ctx, const double* d_state, void* d_work, ars_diag* out, void* stream) {
+  if (!ctx || !d_state || !d_work || !out) return ARS_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  char* w = (char*)d_work;
+  double* partials = (double*)(w + CTL_BYTES);
+  double* res = (double*)(w + CTL_BYTES + ars::diag_partial_bytes(ctx->P));
+  if (ars::launch_diag(ctx->P, d_state, partials, res, s) != hipSuccess) return ARS_EDEVICE;
+  double r[16];
+  if (hipMemcpyAsync(r, res, 13 * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess) return ARS_EDEVICE;
+  int64_t fc = -1;
+  const int frc = ars_fault(ctx, d_work, &fc, stream);
+  if (frc == ARS_EDEVICE) return frc;
+  const ars::Params& P = ctx->P;
+  double dV = P.dx[0] * P.dx[2];
+  if (P.dim == 3) dV = P.dx[0] * P.dx[1] * P.dx[2];
+  std::memset(out, 0, sizeof(*out));
+  out->mass = r[0] * dV;
+  out->mom[0] = r[1] * dV;
+  out->mom[1] = r[2] * dV;
+  out->mom[2] = r[3] * dV;
+  out->e_total = r[4] * dV;
+  out->e_kin = r[5] * dV;
+  out->e_int = r[6] * dV;
+  out->e_grav = r[7] * dV;
+  out->mean_u = r[8] / (double)P.ncell;
+  out->max_u = r[9];
+  out->max_mach = r[10];
+  const ars_config& c = ctx->cfg;
+  const int z = c.dim - 1;
+  if (c.bc[z][0] == ARS_BC_WALL && c.bc[z][1] == ARS_BC_WALL) {
+    const double dT = c.T_wall[0] - c.T_wall[1];
+    const double ncol = (double)P.nx * (double)P.ny;
+    if (dT != 0.0) {
+      out->nu_bot = (r[11] / ncol) * c.L[z] / dT;
+      out->nu_top = (r[12] / ncol) * c.L[z] / dT;
+    }
+  }
+  out->fault = (frc == ARS_ENONPHYS) ? 1 : 0;
+  out->fault_cell = fc;
+  return frc;
+}
+
+}  // extern "C"

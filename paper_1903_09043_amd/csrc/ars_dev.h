@@ -1,0 +1,167 @@
+// ars_dev.h -- device-side building blocks of the all-regime, well-balanced
+// step (arXiv 1903.09043, Sec. 2) for gfx950, shared by the fused kernels,
+// the phase-by-phase reference kernels, the batched kernel and the adjoint.
+//
+// Every function fixes one expression tree (operation order, no FMA
+// contraction: the library is built with -ffp-contract=off) so that all GPU
+// paths produce the same bits.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ars {
+
+enum { BC_PERIODIC = 0, BC_WALL = 1, BC_OUTFLOW = 2 };
+enum { TH_ADIABATIC = 0, TH_FIXED = 1 };
+
+// Scalar problem constants, derived once on the host.
+struct Params {
+  int dim;              // 2 or 3
+  int nx, ny, nz;       // lateral x, lateral y (1 in 2D), vertical (gravity axis)
+  int bcx[2], bcy[2], bcz[2];
+  long long ncell;
+  double dx[3], idx[3], qidx[3];  // per physical axis (x, y, z); 2D uses [0],[2]
+  double gamma, gm1, g, K, cfl, mu, kappa, eta, dmax, sumidx2;
+  double Tw2[2];        // 2 T_wall (bottom, top)
+  int thermal[2];
+  int noslip;
+  int dt_mode;
+  int low_mach;
+  int diss;             // mu > 0 || kappa > 0
+};
+
+// Workspace control block (first 256 bytes of the workspace).
+struct Control {
+  unsigned long long lammax[4];   // max rate slots (FP64 bits; rates are >= 0)
+  unsigned long long fault_cell;  // min faulting cell (ULLONG_MAX = none)
+  unsigned int fault;             // latched flag
+  unsigned int pad0;
+  double t_scratch;
+  unsigned long long pad1[25];
+};
+
+__device__ __forceinline__ double dmax2(double a, double b) { return a >= b ? a : b; }
+__device__ __forceinline__ double dmin2(double a, double b) { return a <= b ? a : b; }
+
+// Gravitational potential at the centre of the cell with vertical index kz
+// (Phi = g z, z = (kz + 1/2) dz); every Delta Phi is a difference of two such
+// values.
+__device__ __forceinline__ double phi_at(const Params& P, int kz) {
+  return P.g * (((double)kz + 0.5) * P.dx[2]);
+}
+
+// Primitive values of one cell (Sec. 4 ideal gas; R = 1 so T = p / rho).
+template <int DIM>
+struct Prim {
+  double rho, r, u[DIM], p, c, rc, T;
+};
+
+// Conservative -> primitive (b = rho, m_0..m_{DIM-1}, E).
+template <int DIM>
+__device__ __forceinline__ Prim<DIM> cons_to_prim(const Params& P, const double* b) {
+  Prim<DIM> q;
+  q.rho = b[0];
+  q.r = 1.0 / q.rho;
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) q.u[k] = b[1 + k] * q.r;
+  double kin = b[1] * q.u[0];
+#pragma unroll
+  for (int k = 1; k < DIM; ++k) kin = kin + b[1 + k] * q.u[k];
+  kin = 0.5 * kin;
+  q.p = P.gm1 * (b[DIM + 1] - kin);
+  q.c = sqrt((P.gamma * q.p) * q.r);
+  q.rc = q.rho * q.c;
+  q.T = q.p * q.r;
+  return q;
+}
+
+// Wall ghost from the adjacent interior cell (Sec. 4.3 hydrostatic
+// extrapolation through eq. well_balanced_formula solved for the ghost
+// density; reflexive velocity; ghost temperature 2 T_wall - T for a fixed-T
+// wall, T for an adiabatic one).  delta = Phi_ghost - Phi_interior.
+template <int DIM>
+__device__ __forceinline__ Prim<DIM> wall_ghost(const Params& P, const Prim<DIM>& in, int side, double delta) {
+  Prim<DIM> g;
+  const double Ti = in.T;
+  const double Tg = (P.thermal[side] == TH_FIXED) ? P.Tw2[side] - Ti : Ti;
+  const double hd = 0.5 * delta;
+  g.rho = (in.rho * (Ti - hd)) / (Tg + hd);
+  g.r = 1.0 / g.rho;
+  g.p = g.rho * Tg;
+  g.T = Tg;
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) {
+    const bool flip = P.noslip ? true : (k == DIM - 1);
+    g.u[k] = flip ? -in.u[k] : in.u[k];
+  }
+  g.c = sqrt((P.gamma * g.p) * g.r);
+  g.rc = g.rho * g.c;
+  return g;
+}
+
+// Acoustic interface solver (Sec. 2.1.2 + eq. low_mach_correction) between L
+// and R along a LATERAL axis (no gravity source).  Outputs u*, Pi*, P = Pi* u*.
+template <bool LM>
+__device__ __forceinline__ void face_lat(const Params& P, double rcL, double cL, double pL, double uL, double rcR,
+                                         double cR, double pR, double uR, double& ustar, double& pistar,
+                                         double& Pf) {
+  const double a = P.K * dmax2(rcL, rcR);
+  ustar = 0.5 * (uL + uR) - (pR - pL) / (2.0 * a);
+  double theta = 1.0;
+  if (LM) {
+    const double cm = dmax2(cL, cR);
+    const double Ma = fabs(ustar) / cm;
+    theta = dmin2(Ma, 1.0);
+  }
+  pistar = 0.5 * (pL + pR) - ((0.5 * a) * theta) * (uR - uL);
+  Pf = pistar * ustar;
+}
+
+// Same along the vertical (gravity) axis, with the interface source
+// S_{i+1/2} = -(rho_L + rho_R)/2 (Phi_R - Phi_L); at a wall face u* = 0.
+template <bool LM>
+__device__ __forceinline__ void face_vert(const Params& P, double rhoL, double rcL, double cL, double pL, double uL,
+                                          double rhoR, double rcR, double cR, double pR, double uR, double dphi,
+                                          bool wall, double& ustar, double& pistar, double& Pf, double& S) {
+  const double a = P.K * dmax2(rcL, rcR);
+  S = (-0.5 * (rhoL + rhoR)) * dphi;
+  ustar = wall ? 0.0 : 0.5 * (uL + uR) - ((pR - pL) - S) / (2.0 * a);
+  double theta = 1.0;
+  if (LM) {
+    const double cm = dmax2(cL, cR);
+    const double Ma = fabs(ustar) / cm;
+    theta = dmin2(Ma, 1.0);
+  }
+  pistar = 0.5 * (pL + pR) - ((0.5 * a) * theta) * (uR - uL);
+  Pf = pistar * ustar;
+}
+
+// Largest local rate of a cell for the CFL reduction (time-step kernel):
+// sum_d (|u_d| + c)/dx_d, plus 2 D sum_d dx_d^-2 with D = dmax / rho when
+// dt_mode == 0.  Non-finite rates count as +inf.
+template <int DIM>
+__device__ __forceinline__ double cell_rate(const Params& P, const Prim<DIM>& q) {
+  double h = (fabs(q.u[0]) + q.c) * P.idx[0];
+  if (DIM == 3) h = h + (fabs(q.u[1]) + q.c) * P.idx[1];
+  h = h + (fabs(q.u[DIM - 1]) + q.c) * P.idx[2];
+  double l = h;
+  if (P.dt_mode == 0) l = h + (2.0 * (P.dmax * q.r)) * P.sumidx2;
+  if (!(l < __builtin_huge_val())) l = __builtin_huge_val();
+  return l;
+}
+
+// Periodic wrap / outflow clamp of a lateral index r along an axis of n cells.
+__device__ __forceinline__ int resolve_lat(int r, int n, const int* bc) {
+  if (r >= 0 && r < n) return r;
+  if (bc[0] == BC_PERIODIC) {
+    int m = r % n;
+    return m < 0 ? m + n : m;
+  }
+  return r < 0 ? 0 : n - 1;
+}
+
+__device__ __forceinline__ void atomic_max_rate(unsigned long long* slot, double v) {
+  atomicMax(slot, (unsigned long long)__double_as_longlong(v));
+}
+
+}  // namespace ars

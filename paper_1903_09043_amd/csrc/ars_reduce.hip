@@ -1,0 +1,172 @@
+// ars_reduce.hip -- reductions around the step: the CFL rate of a state
+// (time-step kernel), control-block preparation, dt finalisation and the
+// diagnostics of Sec. 4 (deterministic two-level sums).
+#include "ars_dev.h"
+#include "ars_internal.h"
+
+namespace ars {
+
+template <int DIM>
+__global__ void __launch_bounds__(256) k_rate(Params P, const double* __restrict__ U, unsigned long long* slot) {
+  constexpr int NV = DIM + 2;
+  __shared__ double red[4];
+  double m = 0.0;
+  for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < P.ncell;
+       c += (long long)gridDim.x * blockDim.x) {
+    double b[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) b[v] = U[c + v * P.ncell];
+    const Prim<DIM> q = cons_to_prim<DIM>(P, b);
+    const double l = cell_rate<DIM>(P, q);
+    m = l > m ? l : m;
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    const double o = __shfl_xor(m, off, 64);
+    m = o > m ? o : m;
+  }
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double mm = red[0];
+    for (int w = 1; w < 4; ++w) mm = red[w] > mm ? red[w] : mm;
+    atomic_max_rate(slot, mm);
+  }
+}
+
+hipError_t launch_rate_reduce(const Params& P, const double* U, unsigned long long* slot, hipStream_t s) {
+  long long nb = (P.ncell + 255) / 256;
+  if (nb > 2048) nb = 2048;
+  if (P.dim == 3)
+    hipLaunchKernelGGL(k_rate<3>, dim3((unsigned)nb), dim3(256), 0, s, P, U, slot);
+  else
+    hipLaunchKernelGGL(k_rate<2>, dim3((unsigned)nb), dim3(256), 0, s, P, U, slot);
+  return hipGetLastError();
+}
+
+// mode 0: clear rate slots 0..3; mode 1: clear slots 1..3 (keep slot 0);
+// mode 2: clear the fault latch.  A kernel, not a memset, so the call can
+// sit inside a captured graph.
+__global__ void k_ctl_prep(Control* ctl, int mode) {
+  if (threadIdx.x == 0) {
+    if (mode == 0 || mode == 1) {
+      for (int i = (mode == 0 ? 0 : 1); i < 4; ++i) ctl->lammax[i] = 0ull;
+    }
+    if (mode == 2) {
+      ctl->fault = 0u;
+      ctl->fault_cell = ~0ull;
+    }
+  }
+}
+
+hipError_t launch_ctl_prep(Control* ctl, int mode, hipStream_t s) {
+  hipLaunchKernelGGL(k_ctl_prep, dim3(1), dim3(64), 0, s, ctl, mode);
+  return hipGetLastError();
+}
+
+__global__ void k_dt_finish(double cfl, const Control* ctl, int slot, double* d_dt) {
+  if (threadIdx.x == 0) *d_dt = cfl / __longlong_as_double((long long)ctl->lammax[slot]);
+}
+
+hipError_t launch_dt_finish(const Params& P, Control* ctl, int slot, double* d_dt, hipStream_t s) {
+  hipLaunchKernelGGL(k_dt_finish, dim3(1), dim3(64), 0, s, P.cfl, ctl, slot, d_dt);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- diagnostics
+// partial layout per block (16 doubles):
+//  0 mass, 1-3 mom, 4 e_total, 5 e_kin, 6 e_int, 7 e_grav, 8 sum|u|,
+//  9 max|u|, 10 max Mach, 11 bottom wall flux sum, 12 top wall flux sum
+constexpr int DIAG_NB = 1024;
+constexpr int DIAG_NF = 16;
+
+size_t diag_partial_bytes(const Params&) { return (size_t)DIAG_NB * DIAG_NF * sizeof(double); }
+
+template <int DIM>
+__global__ void __launch_bounds__(256) k_diag_partial(Params P, const double* __restrict__ U, double* partials) {
+  constexpr int NV = DIM + 2;
+  __shared__ double sh[256];
+  double acc[DIAG_NF];
+#pragma unroll
+  for (int i = 0; i < DIAG_NF; ++i) acc[i] = 0.0;
+  const long long plane = (long long)P.nx * P.ny;
+  for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < P.ncell;
+       c += (long long)gridDim.x * blockDim.x) {
+    double b[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) b[v] = U[c + v * P.ncell];
+    const Prim<DIM> q = cons_to_prim<DIM>(P, b);
+    const int kz = (int)(c / plane);
+    const double phi = phi_at(P, kz);
+    double kin = 0.0, uu = 0.0;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+      kin += 0.5 * b[1 + k] * q.u[k];
+      uu += q.u[k] * q.u[k];
+    }
+    const double um = sqrt(uu);
+    acc[0] += b[0];
+    acc[1] += b[1];
+    acc[2] += b[2];
+    if (DIM == 3) acc[3] += b[3];
+    acc[4] += b[NV - 1] + b[0] * phi;
+    acc[5] += kin;
+    acc[6] += b[NV - 1] - kin;
+    acc[7] += b[0] * phi;
+    acc[8] += um;
+    acc[9] = um > acc[9] ? um : acc[9];
+    const double ma = um / q.c;
+    acc[10] = ma > acc[10] ? ma : acc[10];
+    if (kz == 0) acc[11] += 2.0 * (0.5 * P.Tw2[0] - q.T) / P.dx[2];
+    if (kz == P.nz - 1) acc[12] += 2.0 * (q.T - 0.5 * P.Tw2[1]) / P.dx[2];
+  }
+  // block reduction, fixed order
+  for (int f = 0; f < 13; ++f) {
+    sh[threadIdx.x] = acc[f];
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+      if ((int)threadIdx.x < w) {
+        const double a = sh[threadIdx.x], bb = sh[threadIdx.x + w];
+        sh[threadIdx.x] = (f == 9 || f == 10) ? (bb > a ? bb : a) : a + bb;
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) partials[blockIdx.x * DIAG_NF + f] = sh[0];
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(256) k_diag_final(int nblocks, const double* partials, double* out) {
+  __shared__ double sh[256];
+  for (int f = 0; f < 13; ++f) {
+    double a = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
+      const double x = partials[b * DIAG_NF + f];
+      a = (f == 9 || f == 10) ? (x > a ? x : a) : a + x;
+    }
+    sh[threadIdx.x] = a;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+      if ((int)threadIdx.x < w) {
+        const double x = sh[threadIdx.x], y = sh[threadIdx.x + w];
+        sh[threadIdx.x] = (f == 9 || f == 10) ? (y > x ? y : x) : x + y;
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[f] = sh[0];
+    __syncthreads();
+  }
+}
+
+hipError_t launch_diag(const Params& P, const double* U, double* partials, double* out, hipStream_t s) {
+  long long nb = (P.ncell + 255) / 256;
+  if (nb > DIAG_NB) nb = DIAG_NB;
+  if (P.dim == 3)
+    hipLaunchKernelGGL(k_diag_partial<3>, dim3((unsigned)nb), dim3(256), 0, s, P, U, partials);
+  else
+    hipLaunchKernelGGL(k_diag_partial<2>, dim3((unsigned)nb), dim3(256), 0, s, P, U, partials);
+  hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(256), 0, s, (int)nb, partials, out);
+  return hipGetLastError();
+}
+
+}  // namespace ars

@@ -1,0 +1,344 @@
+// ars_ref.hip -- the same explicit step as separate phase kernels on padded
+// arrays (two ghost layers), each phase one thread per cell or face:
+//   ghosts + primitives -> acoustic faces -> acoustic cell values (L, b~)
+//   -> total face fluxes -> update (+ relaxation E = calE - rho Phi).
+// It stores every intermediate in the workspace and exists to check the
+// fused kernels bit for bit (and to expose the intermediates to tests).
+#include "ars_dev.h"
+#include "ars_internal.h"
+
+namespace ars {
+
+struct RefGrid {
+  int D;
+  int Px, Py, Pz;      // padded extents (Py = 1 in 2D)
+  long long npad;
+  __host__ __device__ long long pad(int qx, int qy, int qz) const {
+    return qx + (long long)Px * (qy + (long long)Py * qz);
+  }
+};
+
+// Field offsets (in units of npad doubles) inside the reference workspace.
+enum {
+  R_RHO = 0, R_R, R_UX, R_UY, R_UZ, R_P, R_C, R_RC, R_T,          // primitives (9)
+  R_CONS = 9,                                                     // 5 conserved
+  R_FACE = 14,                                                    // 3 axes x (us, pi, P, S)
+  R_WALL = 26,                                                    // 3 axes wall flags (as doubles)
+  R_L = 29, R_SB = 30, R_BT = 31,                                 // L, S-bar, 5 b~
+  R_G = 36,                                                       // 3 axes x 5 fluxes
+  R_NFIELD = 51
+};
+
+static RefGrid make_grid(const Params& P) {
+  RefGrid G;
+  G.D = P.dim;
+  G.Px = P.nx + 4;
+  G.Py = (P.dim == 3) ? P.ny + 4 : 1;
+  G.Pz = P.nz + 4;
+  G.npad = (long long)G.Px * G.Py * G.Pz;
+  return G;
+}
+
+size_t ref_workspace_bytes(const Params& P) {
+  RefGrid G = make_grid(P);
+  return (size_t)R_NFIELD * (size_t)G.npad * sizeof(double);
+}
+
+__device__ __forceinline__ void decode(const RefGrid& G, long long i, int& qx, int& qy, int& qz) {
+  qx = (int)(i % G.Px);
+  long long r = i / G.Px;
+  qy = (int)(r % G.Py);
+  qz = (int)(r / G.Py);
+}
+
+// axis helpers: a = 0 (x), 1 (y, 3D only), 2 (vertical)
+__device__ __forceinline__ long long astride(const RefGrid& G, int a) {
+  return a == 0 ? 1 : (a == 1 ? (long long)G.Px : (long long)G.Px * G.Py);
+}
+
+template <int DIM>
+__global__ void k_ref_prim(Params P, RefGrid G, const double* __restrict__ U, double* __restrict__ W) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= G.npad) return;
+  constexpr int NV = DIM + 2;
+  int qx, qy, qz;
+  decode(G, i, qx, qy, qz);
+  const int cx = resolve_lat(qx - 2, P.nx, P.bcx);
+  const int cy = (DIM == 3) ? resolve_lat(qy - 2, P.ny, P.bcy) : 0;
+  int kz = qz - 2;
+  int ghost = -1;
+  if (kz < 0 || kz >= P.nz) {
+    const int side = kz < 0 ? 0 : 1;
+    if (P.bcz[side] == BC_WALL) {
+      ghost = side;
+      kz = side == 0 ? 0 : P.nz - 1;
+    } else {
+      kz = resolve_lat(kz, P.nz, P.bcz);
+    }
+  }
+  const long long cell = cx + (long long)P.nx * (cy + (long long)P.ny * kz);
+  double b[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) b[v] = U[cell + v * P.ncell];
+  Prim<DIM> q = cons_to_prim<DIM>(P, b);
+  if (ghost >= 0) {
+    const int kg = ghost == 0 ? -1 : P.nz;
+    q = wall_ghost<DIM>(P, q, ghost, phi_at(P, kg) - phi_at(P, kz));
+  }
+  const long long n = G.npad;
+  W[R_RHO * n + i] = q.rho;
+  W[R_R * n + i] = q.r;
+  W[R_UX * n + i] = q.u[0];
+  W[R_UY * n + i] = (DIM == 3) ? q.u[1] : 0.0;
+  W[R_UZ * n + i] = q.u[DIM - 1];
+  W[R_P * n + i] = q.p;
+  W[R_C * n + i] = q.c;
+  W[R_RC * n + i] = q.rc;
+  W[R_T * n + i] = q.T;
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    double x = 0.0;
+    if (ghost < 0 && v < NV) x = b[v];
+    W[(R_CONS + v) * n + i] = x;
+  }
+}
+
+// velocity component k (0..DIM-1) -> field
+__device__ __forceinline__ int ufield(int DIM, int k) { return k == DIM - 1 ? R_UZ : (k == 0 ? R_UX : R_UY); }
+
+template <int DIM, bool LM>
+__global__ void k_ref_face(Params P, RefGrid G, int a, double* __restrict__ W) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= G.npad) return;
+  int qx, qy, qz;
+  decode(G, i, qx, qy, qz);
+  const int qa = a == 0 ? qx : (a == 1 ? qy : qz);
+  const int Pa = a == 0 ? G.Px : (a == 1 ? G.Py : G.Pz);
+  if (qa + 1 >= Pa) return;
+  const long long n = G.npad;
+  const long long j = i + astride(G, a);
+  const int k = (a == 2) ? DIM - 1 : a;  // normal velocity component
+  const int uf = ufield(DIM, k);
+  double us, pi, Pf, S = 0.0;
+  int wall = 0;
+  if (a == 2) {
+    wall = (qz == 1 && P.bcz[0] == BC_WALL) || (qz == P.nz + 1 && P.bcz[1] == BC_WALL);
+    face_vert<LM>(P, W[R_RHO * n + i], W[R_RC * n + i], W[R_C * n + i], W[R_P * n + i], W[uf * n + i],
+                  W[R_RHO * n + j], W[R_RC * n + j], W[R_C * n + j], W[R_P * n + j], W[uf * n + j],
+                  phi_at(P, qz + 1 - 2) - phi_at(P, qz - 2), wall != 0, us, pi, Pf, S);
+  } else {
+    face_lat<LM>(P, W[R_RC * n + i], W[R_C * n + i], W[R_P * n + i], W[uf * n + i], W[R_RC * n + j],
+                 W[R_C * n + j], W[R_P * n + j], W[uf * n + j], us, pi, Pf);
+  }
+  const int f = R_FACE + 4 * a;
+  W[(f + 0) * n + i] = us;
+  W[(f + 1) * n + i] = pi;
+  W[(f + 2) * n + i] = Pf;
+  W[(f + 3) * n + i] = S;
+  W[(R_WALL + a) * n + i] = (double)wall;
+}
+
+template <int DIM>
+__global__ void k_ref_cell(Params P, RefGrid G, const double* __restrict__ d_dt, double* __restrict__ W) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= G.npad) return;
+  constexpr int NV = DIM + 2;
+  int qx, qy, qz;
+  decode(G, i, qx, qy, qz);
+  if (qx < 1 || qx >= G.Px - 1 || qz < 1 || qz >= G.Pz - 1) return;
+  if (DIM == 3 && (qy < 1 || qy >= G.Py - 1)) return;
+  const long long n = G.npad;
+  const double dt = *d_dt;
+  const double lam[3] = {dt / P.dx[0], DIM == 3 ? dt / P.dx[1] : 0.0, dt / P.dx[2]};
+  // active axes in order: x, (y), z
+  const int axes[3] = {0, DIM == 3 ? 1 : 2, 2};
+  double Lc = 1.0;
+  for (int t = 0; t < DIM; ++t) {
+    const int a = axes[t];
+    const long long m = i - astride(G, a);
+    const int f = R_FACE + 4 * a;
+    Lc = Lc + lam[a] * (W[(f + 0) * n + i] - W[(f + 0) * n + m]);
+  }
+  const long long mz = i - astride(G, 2);
+  const double sb = 0.5 * (W[(R_FACE + 8 + 3) * n + i] + W[(R_FACE + 8 + 3) * n + mz]);
+  double Am[3];
+  for (int t = 0; t < DIM; ++t) {
+    const int a = axes[t];
+    const long long m = i - astride(G, a);
+    const int f = R_FACE + 4 * a;
+    double dpi = W[(f + 1) * n + i] - W[(f + 1) * n + m];
+    if (a == 2) dpi = dpi - sb;
+    Am[t] = lam[a] * dpi;
+  }
+  double AE = 0.0;
+  for (int t = 0; t < DIM; ++t) {
+    const int a = axes[t];
+    const long long m = i - astride(G, a);
+    const int f = R_FACE + 4 * a;
+    const double term = lam[a] * (W[(f + 2) * n + i] - W[(f + 2) * n + m]);
+    AE = (t == 0) ? term : AE + term;
+  }
+  const double rho = W[R_CONS * n + i];
+  const double calE = W[(R_CONS + NV - 1) * n + i] + rho * phi_at(P, qz - 2);
+  const double iL = 1.0 / Lc;
+  W[R_L * n + i] = Lc;
+  W[R_SB * n + i] = sb;
+  W[R_BT * n + i] = rho * iL;
+  for (int k = 0; k < DIM; ++k) W[(R_BT + 1 + k) * n + i] = (W[(R_CONS + 1 + k) * n + i] - Am[k]) * iL;
+  W[(R_BT + NV - 1) * n + i] = (calE - AE) * iL;
+}
+
+template <int DIM, bool DISS>
+__global__ void k_ref_flux(Params P, RefGrid G, int a, double* __restrict__ W) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= G.npad) return;
+  constexpr int NV = DIM + 2;
+  int qx, qy, qz;
+  decode(G, i, qx, qy, qz);
+  const int q[3] = {qx, qy, qz};
+  const int Pd[3] = {G.Px, G.Py, G.Pz};
+  // face axis a: q_a in [1, P_a - 2); other active axes interior [2, P - 2)
+  for (int b = 0; b < 3; ++b) {
+    if (DIM == 2 && b == 1) continue;
+    if (b == a) {
+      if (q[b] < 1 || q[b] >= Pd[b] - 2) return;
+    } else {
+      if (q[b] < 2 || q[b] >= Pd[b] - 2) return;
+    }
+  }
+  const long long n = G.npad;
+  const long long j = i + astride(G, a);
+  const int f = R_FACE + 4 * a;
+  const double us = W[(f + 0) * n + i];
+  const double pi = W[(f + 1) * n + i];
+  const bool wall = W[(R_WALL + a) * n + i] != 0.0;
+  const int dn = (a == 2) ? DIM - 1 : a;  // normal velocity component index
+  double tr[NV];
+  if (wall) {
+    for (int v = 0; v < NV; ++v) tr[v] = 0.0;
+  } else {
+    const long long up = us >= 0.0 ? i : j;
+    tr[0] = W[R_BT * n + up] * us;
+    for (int k = 0; k < DIM; ++k) tr[1 + k] = W[(R_BT + 1 + k) * n + up] * us;
+    tr[NV - 1] = (W[(R_BT + NV - 1) * n + up] + pi) * us;
+  }
+  double Gv[NV];
+  Gv[0] = tr[0];
+  for (int k = 0; k < DIM; ++k) Gv[1 + k] = (k == dn) ? tr[1 + k] + pi : tr[1 + k];
+  Gv[NV - 1] = tr[NV - 1];
+  if (DISS) {
+    // physical axis of velocity component k
+    int axk[3];
+    for (int k = 0; k < DIM; ++k) axk[k] = (k == DIM - 1) ? 2 : k;
+    double g[3][3];  // g[t][k]: derivative along active axis index t of u_k
+    int tn = (a == 2) ? DIM - 1 : a;
+    const double idn = P.idx[a];
+    for (int k = 0; k < DIM; ++k) {
+      const int uf = ufield(DIM, k);
+      g[tn][k] = (W[uf * n + j] - W[uf * n + i]) * idn;
+    }
+    for (int t = 0; t < DIM; ++t) {
+      if (t == tn) continue;
+      const int b = axk[t];
+      const long long sb_ = astride(G, b);
+      const double qb = P.qidx[b];
+      for (int k = 0; k < DIM; ++k) {
+        const int uf = ufield(DIM, k);
+        g[t][k] = ((W[uf * n + i + sb_] - W[uf * n + i - sb_]) + (W[uf * n + j + sb_] - W[uf * n + j - sb_])) * qb;
+      }
+    }
+    double div = g[0][0];
+    for (int t = 1; t < DIM; ++t) div = div + g[t][t];
+    double Wk = 0.0;
+    for (int k = 0; k < DIM; ++k) {
+      double t = P.mu * (g[tn][k] + g[k][tn]);
+      if (k == tn) t = t + P.eta * div;
+      const int uf = ufield(DIM, k);
+      const double ufc = 0.5 * (W[uf * n + i] + W[uf * n + j]);
+      Wk = (k == 0) ? t * ufc : Wk + t * ufc;
+      Gv[1 + k] = Gv[1 + k] - t;
+    }
+    const double Q = -(P.kappa * ((W[R_T * n + j] - W[R_T * n + i]) * idn));
+    Gv[NV - 1] = (Gv[NV - 1] - Wk) + Q;
+  }
+  for (int v = 0; v < NV; ++v) W[(R_G + 5 * a + v) * n + i] = Gv[v];
+}
+
+template <int DIM>
+__global__ void k_ref_update(Params P, RefGrid G, const double* __restrict__ d_dt, const double* __restrict__ W,
+                             double* __restrict__ Uout, Control* ctl) {
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= P.ncell) return;
+  constexpr int NV = DIM + 2;
+  const int x = (int)(c % P.nx);
+  const long long r = c / P.nx;
+  const int y = (int)(r % P.ny);
+  const int z = (int)(r / P.ny);
+  const long long i = G.pad(x + 2, DIM == 3 ? y + 2 : 0, z + 2);
+  const long long n = G.npad;
+  const double dt = *d_dt;
+  const double lam[3] = {dt / P.dx[0], DIM == 3 ? dt / P.dx[1] : 0.0, dt / P.dx[2]};
+  const int axes[3] = {0, DIM == 3 ? 1 : 2, 2};
+  const double phic = phi_at(P, z);
+  double nb[NV];
+  for (int v = 0; v < NV; ++v) {
+    double s = W[(R_CONS + v) * n + i];
+    if (v == NV - 1) s = s + W[R_CONS * n + i] * phic;
+    for (int t = 0; t < DIM; ++t) {
+      const int a = axes[t];
+      const long long m = i - astride(G, a);
+      s = s - lam[a] * (W[(R_G + 5 * a + v) * n + i] - W[(R_G + 5 * a + v) * n + m]);
+    }
+    if (v == DIM) s = s + lam[2] * W[R_SB * n + i];
+    nb[v] = s;
+  }
+  nb[NV - 1] = nb[NV - 1] - nb[0] * phic;
+  for (int v = 0; v < NV; ++v) Uout[c + v * P.ncell] = nb[v];
+  const Prim<DIM> qn = cons_to_prim<DIM>(P, nb);
+  double kin = nb[1] * qn.u[0];
+  for (int k = 1; k < DIM; ++k) kin = kin + nb[1 + k] * qn.u[k];
+  const bool ok = (W[R_L * n + i] > 0.0) && (nb[0] > 0.0) && (qn.p > 0.0) && isfinite(nb[0]) && isfinite(qn.p) &&
+                  isfinite(kin);
+  if (!ok) {
+    atomicOr(&ctl->fault, 1u);
+    atomicMin(&ctl->fault_cell, (unsigned long long)c);
+  }
+}
+
+template <int DIM>
+static hipError_t ref_t(const Params& P, const double* Uin, double* Uout, void* wref, const double* d_dt,
+                        Control* ctl, hipStream_t s) {
+  RefGrid G = make_grid(P);
+  double* W = (double*)wref;
+  const int bs = 256;
+  const unsigned nb = (unsigned)((G.npad + bs - 1) / bs);
+  hipLaunchKernelGGL(k_ref_prim<DIM>, dim3(nb), dim3(bs), 0, s, P, G, Uin, W);
+  const int axes[3] = {0, 1, 2};
+  for (int t = 0; t < 3; ++t) {
+    const int a = axes[t];
+    if (DIM == 2 && a == 1) continue;
+    if (P.low_mach)
+      hipLaunchKernelGGL((k_ref_face<DIM, true>), dim3(nb), dim3(bs), 0, s, P, G, a, W);
+    else
+      hipLaunchKernelGGL((k_ref_face<DIM, false>), dim3(nb), dim3(bs), 0, s, P, G, a, W);
+  }
+  hipLaunchKernelGGL(k_ref_cell<DIM>, dim3(nb), dim3(bs), 0, s, P, G, d_dt, W);
+  for (int t = 0; t < 3; ++t) {
+    const int a = axes[t];
+    if (DIM == 2 && a == 1) continue;
+    if (P.diss)
+      hipLaunchKernelGGL((k_ref_flux<DIM, true>), dim3(nb), dim3(bs), 0, s, P, G, a, W);
+    else
+      hipLaunchKernelGGL((k_ref_flux<DIM, false>), dim3(nb), dim3(bs), 0, s, P, G, a, W);
+  }
+  const unsigned nc = (unsigned)((P.ncell + bs - 1) / bs);
+  hipLaunchKernelGGL(k_ref_update<DIM>, dim3(nc), dim3(bs), 0, s, P, G, d_dt, W, Uout, ctl);
+  return hipGetLastError();
+}
+
+hipError_t launch_step_ref(const Params& P, const double* Uin, double* Uout, void* wref, const double* d_dt,
+                           Control* ctl, hipStream_t s) {
+  return P.dim == 3 ? ref_t<3>(P, Uin, Uout, wref, d_dt, ctl, s) : ref_t<2>(P, Uin, Uout, wref, d_dt, ctl, s);
+}
+
+}  // namespace ars

@@ -1,0 +1,249 @@
+"""GPU parity of the HIP step against the CPU oracle (run on an MI355X).
+
+Acceptance (FP64): |gpu - oracle| <= 1e-12 * max(|oracle|, s_v) cell-wise,
+s_v = max |oracle| of that variable; the kernels are written to reproduce
+the oracle's expression trees, so most cases are also checked bit for bit.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1903_09043_amd import workloads as W
+from tests import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def A():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1903_09043_amd as A
+    A.lib()
+    return A
+
+
+def close(g, o, tol=1e-12):
+    g = np.asarray(g)
+    o = np.asarray(o)
+    assert g.shape == o.shape
+    s = np.max(np.abs(o.reshape(o.shape[0], -1)), axis=1).reshape((-1,) + (1,) * (o.ndim - 1))
+    s = np.maximum(s, np.finfo(np.float64).tiny)  # a variable that is zero everywhere
+    err = np.abs(g - o) / np.maximum(np.abs(o), s)
+    return float(err.max())
+
+
+def bitwise(g, o):
+    return np.array_equal(np.asarray(g), np.asarray(o))
+
+
+def gpu_run(A, cfg, U0, nsteps, zchunk=None):
+    import torch
+    S = A.Solver(cfg)
+    if zchunk:
+        S.ctx.set_zchunk(zchunk)
+    S.set_state(U0)
+    log = torch.zeros(max(nsteps, 1), dtype=torch.float64, device="cuda")
+    S.step(nsteps, dt_log=log)
+    torch.cuda.synchronize()
+    rc, fc = S.fault()
+    return S.numpy(), log.cpu().numpy()[:nsteps], S.t.item(), rc, fc
+
+
+def test_init_and_dt_bitwise(A):
+    import torch
+    for make in (W.config1, lambda: W.rb([20, 12, 10], [1.0, 1.0, 1.0], Ra=1e5, seed=3),
+                 lambda: W.gresho(n=64)):
+        cfg, prob, prm, seed = make()
+        say("init/dt", cfg["n"])
+        S = A.Solver(cfg).init(prob, prm, seed)
+        torch.cuda.synchronize()
+        U = S.numpy()
+        Uo = O.init(cfg, prob, prm, seed)
+        assert bitwise(U, Uo)
+        assert S.dt.item() == O.dt(cfg, Uo)
+
+
+def test_config1_1000_steps(A):
+    """2D RB 64x32, Ra = 1e4, theta on, 1000 steps: the workload of the
+    parity requirement."""
+    cfg, prob, prm, seed = W.config1()
+    Uo0 = O.init(cfg, prob, prm, seed)
+    say("config1 gpu")
+    U, log, t, rc, fc = gpu_run(A, cfg, Uo0, 1000)
+    assert rc == 0
+    say("config1 oracle")
+    r = O.run(cfg, Uo0, 1000)
+    err = close(U, r["U"])
+    say("config1 max rel err", err, "bitwise", bitwise(U, r["U"]))
+    assert err <= 1e-12
+    np.testing.assert_allclose(log, r["dt_log"], rtol=1e-13)
+    assert abs(t - r["t"]) <= 1e-12 * r["t"]
+
+
+CASES = {
+    # name: (cfg, U0-builder, steps, zchunk)
+    "rb2d_ragged": (lambda: W.rb([100, 37], [2.0, 1.0], Ra=3e3, seed=11, amp=1e-2), 60, 7),
+    "rb2d_thetaoff": (lambda: W.rb([64, 32], [2.0, 1.0], Ra=1e4, seed=1, amp=1e-2, low_mach=0), 60, None),
+    "rb3d_ragged": (lambda: W.rb([37, 29, 23], [1.3, 1.0, 1.0], Ra=1e5, seed=4, amp=1e-2), 25, 6),
+    "rb3d_thetaoff": (lambda: W.rb([20, 16, 12], [1.0, 1.0, 1.0], Ra=1e5, seed=2, amp=1e-2, low_mach=0), 25, None),
+    "gresho_on": (lambda: W.gresho(n=128, Ma=1e-2, low_mach=1), 100, None),
+    "gresho_off": (lambda: W.gresho(n=96, Ma=1e-2, low_mach=0), 100, 13),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_step_vs_oracle(A, name):
+    make, nsteps, zc = CASES[name]
+    cfg, prob, prm, seed = make()
+    Uo0 = O.init(cfg, prob, prm, seed)
+    if cfg["g"] != 0.0:
+        # add a velocity field so every flux term is exercised
+        rng = np.random.default_rng(7)
+        D = cfg["dim"]
+        for k in range(D):
+            Uo0[1 + k] = 1e-2 * rng.standard_normal(Uo0[0].shape) * Uo0[0]
+        Uo0[-1] += 0.5 * sum(Uo0[1 + k] ** 2 for k in range(D)) / Uo0[0]
+    say(name, "gpu", cfg["n"])
+    U, log, t, rc, fc = gpu_run(A, cfg, Uo0, nsteps, zc)
+    assert rc == 0, fc
+    say(name, "oracle")
+    r = O.run(cfg, Uo0, nsteps)
+    err = close(U, r["U"])
+    say(name, "max rel err", err, "bitwise", bitwise(U, r["U"]))
+    assert err <= 1e-12
+
+
+def _periodic3d_cfg(bc):
+    return dict(dim=3, n=[33, 26, 19], L=[1.0, 0.8, 0.6], gamma=5.0 / 3.0, g=0.0, mu=2e-3, kappa=3e-3, K=1.1,
+                cfl=0.4, low_mach=1, dt_mode=0, bc=bc, wall_noslip=1, thermal=[0, 0], T_wall=[1.0, 1.0])
+
+
+@pytest.mark.parametrize("bc", ["periodic", "outflow"])
+def test_3d_random_state(A, bc):
+    b = [[0, 0]] * 3 if bc == "periodic" else [[2, 2], [0, 0], [2, 2]]
+    cfg = _periodic3d_cfg(b)
+    U0 = I.smooth_random(cfg, seed=21)
+    say("3d", bc)
+    U, log, t, rc, fc = gpu_run(A, cfg, U0, 20, zchunk=5)
+    assert rc == 0
+    r = O.run(cfg, U0, 20)
+    err = close(U, r["U"])
+    say("3d", bc, "max rel err", err, "bitwise", bitwise(U, r["U"]))
+    assert err <= 1e-12
+
+
+def test_sod_2d_outflow(A):
+    cfg = dict(dim=2, n=[100, 3], L=[1.0, 1.0], gamma=1.4, g=0.0, mu=0.0, kappa=0.0, K=1.1, cfl=0.4, low_mach=1,
+               dt_mode=0, bc=[[2, 2], [0, 0]], wall_noslip=1, thermal=[0, 0], T_wall=[1.0, 1.0])
+    U0 = O.init(cfg, W.PROB_SOD)
+    say("sod")
+    U, log, t, rc, fc = gpu_run(A, cfg, U0, 120)
+    r = O.run(cfg, U0, 120)
+    err = close(U, r["U"])
+    say("sod max rel err", err, "bitwise", bitwise(U, r["U"]))
+    assert err <= 1e-12
+
+
+def test_isothermal_column_2d(A):
+    """Sec. 4.3 column in 2D (periodic x, walls in y): stays at rest to the
+    round-off level of Table 1, and matches the oracle."""
+    for lm in (0, 1):
+        cfg = dict(dim=2, n=[4, 128], L=[1.0, 3.0], gamma=5.0 / 3.0, g=1.0, mu=0.0, kappa=0.0, K=1.1, cfl=0.4,
+                   low_mach=lm, dt_mode=0, bc=[[0, 0], [1, 1]], wall_noslip=1, thermal=[0, 0], T_wall=[1.0, 1.0])
+        U0 = O.init(cfg, W.PROB_ISOTHERMAL)
+        say("iso", lm)
+        U, log, t, rc, fc = gpu_run(A, cfg, U0, 500)
+        r = O.run(cfg, U0, 500)
+        assert close(U, r["U"]) <= 1e-12
+        assert np.max(np.abs(U[1:3] / U[0])) < 1e-12
+
+
+def test_fused_equals_reference_path(A):
+    """The fused z-march kernel and the phase-by-phase reference kernels give
+    the same bits, for several tile/boundary/variant combinations."""
+    import torch
+    cases = [W.rb([70, 33], [2.0, 1.0], Ra=2e3, seed=5, amp=1e-2),
+             W.rb([30, 27, 14], [1.0, 1.0, 1.0], Ra=1e5, seed=6, amp=1e-2),
+             W.gresho(n=80, Ma=1e-1, low_mach=0)]
+    for cfg, prob, prm, seed in cases:
+        say("fused vs ref", cfg["n"])
+        S1 = A.Solver(cfg).init(prob, prm, seed)
+        S2 = A.Solver(cfg).init(prob, prm, seed)
+        sched = torch.full((12,), float(S1.dt.item()), dtype=torch.float64, device="cuda")
+        S1.ctx.set_zchunk(5)
+        S1.step_sched(sched)
+        S2.step_ref(sched)
+        torch.cuda.synchronize()
+        assert bitwise(S1.numpy(), S2.numpy())
+
+
+def test_result_independent_of_zchunk(A):
+    cfg, prob, prm, seed = W.rb([40, 24, 30], [1.0, 1.0, 1.0], Ra=1e5, seed=9, amp=1e-2)
+    outs = []
+    for zc in (30, 7, 1):
+        S = A.Solver(cfg).init(prob, prm, seed)
+        S.ctx.set_zchunk(zc)
+        S.step(6)
+        outs.append(S.numpy())
+    assert bitwise(outs[0], outs[1]) and bitwise(outs[0], outs[2])
+
+
+def test_diagnostics_match_oracle(A):
+    cfg, prob, prm, seed = W.config1()
+    S = A.Solver(cfg).init(prob, prm, seed)
+    S.step(50)
+    d = S.diagnostics()
+    o = O.diag(cfg, S.numpy())
+    for k in ("mass", "e_total", "e_kin", "e_int", "e_grav", "max_u", "mean_u", "max_mach", "nu_bot", "nu_top"):
+        assert abs(d[k] - o[k]) <= 1e-12 * max(abs(o[k]), 1e-300) + 1e-300, k
+    assert abs(d["mom"][0] - o["mom0"]) <= 1e-12 * o["mass"]
+
+
+def test_fault_latch(A):
+    import torch
+    cfg = dict(dim=2, n=[16, 12], L=[1.0, 1.0], gamma=5.0 / 3.0, bc=[[0, 0], [0, 0]])
+    U0 = O.init(cfg, W.PROB_UNIFORM, [1.0, 0.0, 0.0, 0.0, 1.0])
+    U0[0, 5, 9] = -1.0
+    S = A.Solver(cfg)
+    S.U.copy_(torch.as_tensor(U0).cuda())
+    S.dt.fill_(1e-3)
+    S.step(1)
+    rc, fc = S.fault()
+    r = O.run(cfg, U0, 1, dt_sched=[1e-3])
+    assert rc == A.ENONPHYS and r["status"] == O.ENONPHYS
+    assert fc == r["fault_cell"]
+    rc2, _ = S.fault()
+    assert rc2 == 0  # latch cleared by the read
+
+
+def test_full_size_256cubed_one_step(A):
+    """3D RB 256^3 (the benchmark workload) in the benchmark's launch
+    configuration: after two GPU steps, one more GPU step equals one oracle
+    step on the whole grid."""
+    import torch
+    cfg, prob, prm, seed = W.config2()
+    say("256^3 init")
+    S = A.Solver(cfg).init(prob, prm, seed)
+    S.step(2)
+    torch.cuda.synchronize()
+    U2 = S.numpy()
+    dt = S.dt.item()
+    S.step(1)
+    torch.cuda.synchronize()
+    U3 = S.numpy()
+    say("256^3 oracle step (threads=%d)" % O.num_threads())
+    Uo, rc, _ = O.step_dt(cfg, U2, dt)
+    assert rc == 0
+    assert dt == O.dt(cfg, U2)
+    err = close(U3, Uo)
+    say("256^3 max rel err", err, "bitwise", bitwise(U3, Uo))
+    assert err <= 1e-12
