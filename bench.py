@@ -75,6 +75,8 @@ def main():
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--zchunk", type=int, default=0)
+    ap.add_argument("--mode", choices=["step", "copy"], default="step",
+                    help="copy: device-to-device copies of one state (calibrates the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
@@ -86,6 +88,21 @@ def main():
 
     cfg, prob, prm, seed = W.config2(n=args.n)
     ncell = args.n ** 3
+    if args.mode == "copy":
+        # plain copy of one state (5 FP64 fields): reads and writes 40 B per cell
+        a = torch.ones(5 * ncell, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(args.warmup):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        print(json.dumps({"mode": "copy", "bytes_per_copy_each_way": a.numel() * 8,
+                          "GBps_read_plus_write": 2 * a.numel() * 8 * args.steps / el / 1e9}), flush=True)
+        return
     S = A.Solver(cfg).init(prob, prm, seed)
     if args.zchunk:
         S.ctx.set_zchunk(args.zchunk)

@@ -146,6 +146,7 @@ struct Grid {
 template <class S>
 struct Prim {
   S rho, r, u[3], p, c, rc, T;
+  S ic, irc;  // 1/c and 1/(rho c): the face solver divides by max(c) and by 2 K max(rho c)
 };
 
 // O2: conservative -> primitive for one cell.
@@ -169,6 +170,8 @@ Prim<S> cons_to_prim(const orc_config& c, const Grid& G, const S* U, long cell) 
   q.c = sqrt_((S(c.gamma) * q.p) * q.r);
   q.rc = q.rho * q.c;
   q.T = q.p * q.r;
+  q.ic = S(1.0) / q.c;
+  q.irc = q.r * q.ic;
   return q;
 }
 
@@ -241,6 +244,8 @@ void build_padded(const orc_config& c, const Grid& G, const S* U, State<S>& st) 
         }
         gq.c = sqrt_((S(c.gamma) * gq.p) * gq.r);
         gq.rc = gq.rho * gq.c;
+        gq.ic = S(1.0) / gq.c;
+        gq.irc = gq.r * gq.ic;
         st.prim[dst] = gq;
         // conserved values of wall ghosts are never used (zero wall flux)
       }
@@ -252,6 +257,9 @@ struct Face {
 };
 
 // O4: acoustic solver at the face between L and R = L + e_d.
+// a = K max(rho c); u* divides by 2a and Ma by max(c): both are written as
+// products with the smaller of the two cells' reciprocals,
+//   1/(2a) = (1/(2K)) min(1/(rho c)_L, 1/(rho c)_R),  1/max(c) = min(1/c_L, 1/c_R).
 template <class S>
 Face<S> acoustic_face(const orc_config& c, const Grid& G, const Prim<S>& L, const Prim<S>& R,
                       int d, double phiL, double phiR, bool wall) {
@@ -261,13 +269,13 @@ Face<S> acoustic_face(const orc_config& c, const Grid& G, const Prim<S>& L, cons
     f.S_ = (S(-0.5) * (L.rho + R.rho)) * S(phiR - phiL);
   else
     f.S_ = S(0.0);
+  const double hK = 0.5 / c.K;
   if (wall)
     f.ustar = S(0.0);
   else
-    f.ustar = S(0.5) * (L.u[d] + R.u[d]) - ((R.p - L.p) - f.S_) / (S(2.0) * f.a);
+    f.ustar = S(0.5) * (L.u[d] + R.u[d]) - ((R.p - L.p) - f.S_) * (S(hK) * smin(L.irc, R.irc));
   if (c.low_mach) {
-    S cm = smax(L.c, R.c);
-    S Ma = sabs(f.ustar) / cm;
+    S Ma = sabs(f.ustar) * smin(L.ic, R.ic);
     f.theta = smin(Ma, S(1.0));
   } else {
     f.theta = S(1.0);
@@ -718,8 +726,10 @@ void orc_face(const orc_config* c, int d, double rhoL, double uL, double pL, dou
   Prim<double> L{}, R{};
   L.rho = rhoL; L.r = 1.0 / rhoL; L.u[d] = uL; L.p = pL;
   L.c = std::sqrt((c->gamma * pL) * L.r); L.rc = rhoL * L.c; L.T = pL * L.r;
+  L.ic = 1.0 / L.c; L.irc = L.r * L.ic;
   R.rho = rhoR; R.r = 1.0 / rhoR; R.u[d] = uR; R.p = pR;
   R.c = std::sqrt((c->gamma * pR) * R.r); R.rc = rhoR * R.c; R.T = pR * R.r;
+  R.ic = 1.0 / R.c; R.irc = R.r * R.ic;
   Face<double> f = acoustic_face(*c, G, L, R, d, phiL, phiR, wall != 0);
   out[0] = f.a; out[1] = f.S_; out[2] = f.ustar; out[3] = f.theta; out[4] = f.pistar; out[5] = f.P;
 }

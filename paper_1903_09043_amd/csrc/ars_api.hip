@@ -74,6 +74,7 @@ ars::Params derive(const ars_config* c) {
   P.gm1 = c->gamma - 1.0;
   P.g = c->g;
   P.K = c->K;
+  P.hK = 0.5 / c->K;
   P.cfl = c->cfl;
   P.mu = c->mu;
   P.kappa = c->kappa;
@@ -168,6 +169,8 @@ int ars_create(const ars_config* cfg, ars_ctx** out) {
   }
   (void)cols;
   c->ts.zchunk = std::max(1, zc);
+  c->ts.num_cu = 0;
+  c->ts.wg_per_cu = 0;
   c->len = (size_t)(cfg->dim + 2) * (size_t)c->P.ncell;
   *out = c;
   return ARS_OK;

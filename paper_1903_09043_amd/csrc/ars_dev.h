@@ -21,7 +21,7 @@ struct Params {
   int bcx[2], bcy[2], bcz[2];
   long long ncell;
   double dx[3], idx[3], qidx[3];  // per physical axis (x, y, z); 2D uses [0],[2]
-  double gamma, gm1, g, K, cfl, mu, kappa, eta, dmax, sumidx2;
+  double gamma, gm1, g, K, hK, cfl, mu, kappa, eta, dmax, sumidx2;  // hK = 0.5 / K
   double Tw2[2];        // 2 T_wall (bottom, top)
   int thermal[2];
   int noslip;
@@ -54,6 +54,7 @@ __device__ __forceinline__ double phi_at(const Params& P, int kz) {
 template <int DIM>
 struct Prim {
   double rho, r, u[DIM], p, c, rc, T;
+  double ic, irc;  // 1/c, 1/(rho c)
 };
 
 // Conservative -> primitive (b = rho, m_0..m_{DIM-1}, E).
@@ -72,6 +73,8 @@ __device__ __forceinline__ Prim<DIM> cons_to_prim(const Params& P, const double*
   q.c = sqrt((P.gamma * q.p) * q.r);
   q.rc = q.rho * q.c;
   q.T = q.p * q.r;
+  q.ic = 1.0 / q.c;
+  q.irc = q.r * q.ic;
   return q;
 }
 
@@ -96,21 +99,24 @@ __device__ __forceinline__ Prim<DIM> wall_ghost(const Params& P, const Prim<DIM>
   }
   g.c = sqrt((P.gamma * g.p) * g.r);
   g.rc = g.rho * g.c;
+  g.ic = 1.0 / g.c;
+  g.irc = g.r * g.ic;
   return g;
 }
 
 // Acoustic interface solver (Sec. 2.1.2 + eq. low_mach_correction) between L
-// and R along a LATERAL axis (no gravity source).  Outputs u*, Pi*, P = Pi* u*.
+// and R along a LATERAL axis (no gravity source).  a = K max(rho c);
+// 1/(2a) = (0.5/K) min(1/(rho c)) and 1/max(c) = min(1/c), so the face needs
+// no division.  Outputs u*, Pi*, P = Pi* u*.
 template <bool LM>
-__device__ __forceinline__ void face_lat(const Params& P, double rcL, double cL, double pL, double uL, double rcR,
-                                         double cR, double pR, double uR, double& ustar, double& pistar,
-                                         double& Pf) {
+__device__ __forceinline__ void face_lat(const Params& P, double rcL, double ircL, double icL, double pL, double uL,
+                                         double rcR, double ircR, double icR, double pR, double uR, double& ustar,
+                                         double& pistar, double& Pf) {
   const double a = P.K * dmax2(rcL, rcR);
-  ustar = 0.5 * (uL + uR) - (pR - pL) / (2.0 * a);
+  ustar = 0.5 * (uL + uR) - (pR - pL) * (P.hK * dmin2(ircL, ircR));
   double theta = 1.0;
   if (LM) {
-    const double cm = dmax2(cL, cR);
-    const double Ma = fabs(ustar) / cm;
+    const double Ma = fabs(ustar) * dmin2(icL, icR);
     theta = dmin2(Ma, 1.0);
   }
   pistar = 0.5 * (pL + pR) - ((0.5 * a) * theta) * (uR - uL);
@@ -119,20 +125,19 @@ __device__ __forceinline__ void face_lat(const Params& P, double rcL, double cL,
 
 // Same along the vertical (gravity) axis, with the interface source
 // S_{i+1/2} = -(rho_L + rho_R)/2 (Phi_R - Phi_L); at a wall face u* = 0.
-template <bool LM>
-__device__ __forceinline__ void face_vert(const Params& P, double rhoL, double rcL, double cL, double pL, double uL,
-                                          double rhoR, double rcR, double cR, double pR, double uR, double dphi,
+template <bool LM, int DIM>
+__device__ __forceinline__ void face_vert(const Params& P, const Prim<DIM>& L, const Prim<DIM>& R, double dphi,
                                           bool wall, double& ustar, double& pistar, double& Pf, double& S) {
-  const double a = P.K * dmax2(rcL, rcR);
-  S = (-0.5 * (rhoL + rhoR)) * dphi;
-  ustar = wall ? 0.0 : 0.5 * (uL + uR) - ((pR - pL) - S) / (2.0 * a);
+  constexpr int Z = DIM - 1;
+  const double a = P.K * dmax2(L.rc, R.rc);
+  S = (-0.5 * (L.rho + R.rho)) * dphi;
+  ustar = wall ? 0.0 : 0.5 * (L.u[Z] + R.u[Z]) - ((R.p - L.p) - S) * (P.hK * dmin2(L.irc, R.irc));
   double theta = 1.0;
   if (LM) {
-    const double cm = dmax2(cL, cR);
-    const double Ma = fabs(ustar) / cm;
+    const double Ma = fabs(ustar) * dmin2(L.ic, R.ic);
     theta = dmin2(Ma, 1.0);
   }
-  pistar = 0.5 * (pL + pR) - ((0.5 * a) * theta) * (uR - uL);
+  pistar = 0.5 * (L.p + R.p) - ((0.5 * a) * theta) * (R.u[Z] - L.u[Z]);
   Pf = pistar * ustar;
 }
 

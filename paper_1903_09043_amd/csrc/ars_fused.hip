@@ -31,23 +31,23 @@ template <int DIM>
 struct FusedLayout;
 template <>
 struct FusedLayout<3> {
-  static constexpr int XA = 0, NXA = 5;   // rc, c, p, ux, uy
-  static constexpr int V = 5, NVV = 4;    // ux, uy, uz, T
-  static constexpr int DZ = 9, NDZ = 3;   // dz ux, dz uy, dz uz
-  static constexpr int F = 12, NF = 6;    // x: us, pi, P ; y: us, pi, P
-  static constexpr int B = 18, NB = 5;
-  static constexpr int GX = 23, NG = 10;  // x: 5 ; y: 5
-  static constexpr int TOTAL = 33;
+  static constexpr int XA = 0, NXA = 6;   // rc, 1/rc, 1/c, p, ux, uy
+  static constexpr int V = 6, NVV = 4;    // ux, uy, uz, T
+  static constexpr int DZ = 10, NDZ = 3;  // dz ux, dz uy, dz uz
+  static constexpr int F = 13, NF = 6;    // x: us, pi, P ; y: us, pi, P
+  static constexpr int B = 19, NB = 5;
+  static constexpr int GX = 24, NG = 10;  // x: 5 ; y: 5
+  static constexpr int TOTAL = 34;
 };
 template <>
 struct FusedLayout<2> {
-  static constexpr int XA = 0, NXA = 4;   // rc, c, p, ux
-  static constexpr int V = 4, NVV = 3;    // ux, uy, T
-  static constexpr int DZ = 7, NDZ = 2;   // dy ux, dy uy
-  static constexpr int F = 9, NF = 3;
-  static constexpr int B = 12, NB = 4;
-  static constexpr int GX = 16, NG = 4;
-  static constexpr int TOTAL = 20;
+  static constexpr int XA = 0, NXA = 5;   // rc, 1/rc, 1/c, p, ux
+  static constexpr int V = 5, NVV = 3;    // ux, uy, T
+  static constexpr int DZ = 8, NDZ = 2;   // dy ux, dy uy
+  static constexpr int F = 10, NF = 3;
+  static constexpr int B = 13, NB = 4;
+  static constexpr int GX = 17, NG = 4;
+  static constexpr int TOTAL = 21;
 };
 
 // Vertical plane resolution: which plane to load and whether it is a wall
@@ -88,18 +88,6 @@ __global__ void __launch_bounds__(EX* EY) k_step_fused(Params P, const double* _
   const int tid = threadIdx.x;
   const int px = tid % EX;
   const int py = (DIM == 3) ? tid / EX : 0;
-  const int tile = blockIdx.x;
-  const int tx = tile % io.ntx;
-  const int ty = tile / io.ntx;
-  const int x0 = tx * TX;
-  const int y0 = ty * TY;
-  const int gx = x0 + px - 2;
-  const int gy = (DIM == 3) ? y0 + py - 2 : 0;
-  const int cx = resolve_lat(gx, P.nx, P.bcx);
-  const int cy = (DIM == 3) ? resolve_lat(gy, P.ny, P.bcy) : 0;
-  const bool lat_out = (px >= 2 && px < EX - 2 && gx < P.nx) &&
-                       (DIM == 2 || (py >= 2 && py < EY - 2 && gy < P.ny));
-  const long long col = (long long)cx + (long long)P.nx * cy;
   const long long plane_stride = (long long)P.nx * P.ny;
   const long long N = P.ncell;
 
@@ -112,7 +100,16 @@ __global__ void __launch_bounds__(EX* EY) k_step_fused(Params P, const double* _
   const int pxpyp = (DIM == 3 && px + 1 < EX && py + 1 < EY) ? tid + EX + 1 : tid;
   const int pxpym = (DIM == 3 && px + 1 < EX && py > 0) ? tid - EX + 1 : tid;
   const int pxmyp = (DIM == 3 && px > 0 && py + 1 < EY) ? tid + EX - 1 : tid;
-  (void)pxmyp;
+  // Positions that own a lateral face some output cell needs, and positions
+  // of output cells (tile interior); with 2 rows of 32 per wave the halo
+  // rows form whole waves, which then skip those stages.
+  const bool inx1 = px >= 1 && px <= EX - 3;
+  const bool inx2 = px >= 2 && px <= EX - 3;
+  const bool iny1 = (DIM == 2) || (py >= 1 && py <= EY - 3);
+  const bool iny2 = (DIM == 2) || (py >= 2 && py <= EY - 3);
+  const bool needGx = inx1 && iny2;
+  const bool needGy = (DIM == 3) && inx2 && iny1;
+  const bool needL = px >= 1 && px <= EX - 2 && (DIM == 2 || (py >= 1 && py <= EY - 2));
 
   // time step of this step
   double dt;
@@ -129,8 +126,34 @@ __global__ void __launch_bounds__(EX* EY) k_step_fused(Params P, const double* _
     if (io.dt_log) *io.dt_log = dt;
   }
 
-  const int z0 = blockIdx.y * io.zchunk;
-  const int z1 = min(z0 + io.zchunk, P.nz);
+  // Persistent balanced schedule: the (tile, plane) pairs are laid end to
+  // end (tile-major) and every workgroup takes one contiguous share; shares
+  // of neighbouring workgroups on one XCD are neighbours in space, so halo
+  // re-reads hit that XCD's L2.
+  const long long total = (long long)io.ntx * io.nty * P.nz;
+  const int G = gridDim.x;
+  const int b = blockIdx.x;
+  const int lw = (G % 8 == 0) ? (b % 8) * (G / 8) + b / 8 : b;
+  long long cur = total * lw / G;
+  const long long stop = total * (lw + 1) / G;
+  double lmax = 0.0;
+  unsigned long long badcell = ~0ull;
+  while (cur < stop) {
+  const int tile = (int)(cur / P.nz);
+  const int z0 = (int)(cur % P.nz);
+  const int z1 = (int)min((long long)P.nz, (long long)z0 + (stop - cur));
+  cur += z1 - z0;
+  const int tx = tile % io.ntx;
+  const int ty = tile / io.ntx;
+  const int x0 = tx * TX;
+  const int y0 = ty * TY;
+  const int gx = x0 + px - 2;
+  const int gy = (DIM == 3) ? y0 + py - 2 : 0;
+  const int cx = resolve_lat(gx, P.nx, P.bcx);
+  const int cy = (DIM == 3) ? resolve_lat(gy, P.ny, P.bcy) : 0;
+  const bool lat_out = (px >= 2 && px < EX - 2 && gx < P.nx) &&
+                       (DIM == 2 || (py >= 2 && py < EY - 2 && gy < P.ny));
+  const long long col = (long long)cx + (long long)P.nx * cy;
 
   // ---- rolling registers ---------------------------------------------------
   double Unx[NV];                 // conserved values of the next plane to use
@@ -144,8 +167,6 @@ __global__ void __launch_bounds__(EX* EY) k_step_fused(Params P, const double* _
   double GzLo[NV];                // z-face flux (p-3|p-2)
   double Fo1[3 * (DIM - 1)];      // own lateral acoustic faces of plane p-1
   double dX2[4];                  // tangential differences at plane p-2
-  double lmax = 0.0;
-  unsigned long long badcell = ~0ull;
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
     U1[v] = U2[v] = bt1[v] = bt2[v] = GzLo[v] = 0.0;
@@ -189,15 +210,15 @@ __global__ void __launch_bounds__(EX* EY) k_step_fused(Params P, const double* _
     const double phi2 = phi_at(P, p - 2);
     // z face (p-1 | p)
     if (p >= z0 - 1) {
-      face_vert<LM>(P, q1.rho, q1.rc, q1.c, q1.p, q1.u[Z], q0.rho, q0.rc, q0.c, q0.p, q0.u[Z], phip - phi1,
-                    wall_face_below(P, p - 1), zBus, zBpi, zBP, zBS);
+      face_vert<LM, DIM>(P, q1, q0, phip - phi1, wall_face_below(P, p - 1), zBus, zBpi, zBP, zBS);
     }
     // LDS: acoustic fields of plane p; viscous fields of plane p-1
     sm[(Ly::XA + 0) * NPOS + tid] = q0.rc;
-    sm[(Ly::XA + 1) * NPOS + tid] = q0.c;
-    sm[(Ly::XA + 2) * NPOS + tid] = q0.p;
-    sm[(Ly::XA + 3) * NPOS + tid] = q0.u[0];
-    if (DIM == 3) sm[(Ly::XA + 4) * NPOS + tid] = q0.u[1];
+    sm[(Ly::XA + 1) * NPOS + tid] = q0.irc;
+    sm[(Ly::XA + 2) * NPOS + tid] = q0.ic;
+    sm[(Ly::XA + 3) * NPOS + tid] = q0.p;
+    sm[(Ly::XA + 4) * NPOS + tid] = q0.u[0];
+    if (DIM == 3) sm[(Ly::XA + 5) * NPOS + tid] = q0.u[1];
     if (DISS) {
 #pragma unroll
       for (int k = 0; k < DIM; ++k) sm[(Ly::V + k) * NPOS + tid] = q1.u[k];
@@ -208,7 +229,7 @@ __global__ void __launch_bounds__(EX* EY) k_step_fused(Params P, const double* _
     __syncthreads();  // ---------------------------------------------- bar 1
 
     // ================= step 2a: acoustic cell values of plane p-1 ===========
-    const bool doL = (p - 1 >= z0 - 1) && (p - 1 <= z1);
+    const bool doL = (p - 1 >= z0 - 1) && (p - 1 <= z1) && needL;
     if (doL) {
       double Lc = 1.0;
       // x faces: +x own (registers), -x from the left neighbour
@@ -256,11 +277,13 @@ __global__ void __launch_bounds__(EX* EY) k_step_fused(Params P, const double* _
     double Fn[3 * (DIM - 1)];
     const bool doA = (p >= z0 - 1) && (p <= z1);
     if (doA) {
-      face_lat<LM>(P, q0.rc, q0.c, q0.p, q0.u[0], sm[(Ly::XA + 0) * NPOS + pxp], sm[(Ly::XA + 1) * NPOS + pxp],
-                   sm[(Ly::XA + 2) * NPOS + pxp], sm[(Ly::XA + 3) * NPOS + pxp], Fn[0], Fn[1], Fn[2]);
+      face_lat<LM>(P, q0.rc, q0.irc, q0.ic, q0.p, q0.u[0], sm[(Ly::XA + 0) * NPOS + pxp],
+                   sm[(Ly::XA + 1) * NPOS + pxp], sm[(Ly::XA + 2) * NPOS + pxp], sm[(Ly::XA + 3) * NPOS + pxp],
+                   sm[(Ly::XA + 4) * NPOS + pxp], Fn[0], Fn[1], Fn[2]);
       if (DIM == 3)
-        face_lat<LM>(P, q0.rc, q0.c, q0.p, q0.u[1], sm[(Ly::XA + 0) * NPOS + pyp], sm[(Ly::XA + 1) * NPOS + pyp],
-                     sm[(Ly::XA + 2) * NPOS + pyp], sm[(Ly::XA + 4) * NPOS + pyp], Fn[3], Fn[4], Fn[5]);
+        face_lat<LM>(P, q0.rc, q0.irc, q0.ic, q0.p, q0.u[1], sm[(Ly::XA + 0) * NPOS + pyp],
+                     sm[(Ly::XA + 1) * NPOS + pyp], sm[(Ly::XA + 2) * NPOS + pyp], sm[(Ly::XA + 3) * NPOS + pyp],
+                     sm[(Ly::XA + 5) * NPOS + pyp], Fn[3], Fn[4], Fn[5]);
     } else {
 #pragma unroll
       for (int i = 0; i < 3 * (DIM - 1); ++i) Fn[i] = 0.0;
@@ -273,7 +296,7 @@ __global__ void __launch_bounds__(EX* EY) k_step_fused(Params P, const double* _
 
     // tangential differences of plane p-1 (for vertical viscous faces)
     double dX1[4] = {0.0, 0.0, 0.0, 0.0};
-    if (DISS) {
+    if (DISS && lat_out) {
       // 3D: dx ux, dx uz, dy uy, dy uz ; 2D: dx ux, dx uy
       dX1[0] = sm[(Ly::V + 0) * NPOS + pxp] - sm[(Ly::V + 0) * NPOS + pxm];
       dX1[1] = sm[(Ly::V + Z) * NPOS + pxp] - sm[(Ly::V + Z) * NPOS + pxm];
@@ -288,9 +311,10 @@ __global__ void __launch_bounds__(EX* EY) k_step_fused(Params P, const double* _
 #pragma unroll
     for (int v = 0; v < NV; ++v) GXn[v] = GYn[v] = 0.0;
     const bool doG = (p - 1 >= z0) && (p - 1 < z1);
-    if (doG) {
+    if (doG && (needGx || needGy)) {
 #pragma unroll
       for (int dir = 0; dir < DIM - 1; ++dir) {
+        if (!(dir == 0 ? needGx : needGy)) continue;
         const int nb = dir == 0 ? pxp : pyp;
         const double us = Fo1[3 * dir + 0];
         const double pi = Fo1[3 * dir + 1];
@@ -367,7 +391,7 @@ __global__ void __launch_bounds__(EX* EY) k_step_fused(Params P, const double* _
     double Gz[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) Gz[v] = 0.0;
-    const bool doGz = (p - 1 >= z0) && (p - 1 <= z1);
+    const bool doGz = (p - 1 >= z0) && (p - 1 <= z1) && lat_out;
     if (doGz) {
       const bool wall = wall_face_below(P, p - 2);
       double tr[NV];
@@ -476,6 +500,8 @@ __global__ void __launch_bounds__(EX* EY) k_step_fused(Params P, const double* _
     for (int i = 0; i < 4; ++i) dX2[i] = dX1[i];
   }
 
+  }  // runs
+
   // ---- workgroup reduction of the new-state rate, fault latch --------------
   if (badcell != ~0ull) {
     atomicOr(&io.ctl->fault, 1u);
@@ -502,15 +528,38 @@ __global__ void __launch_bounds__(EX* EY) k_step_fused(Params P, const double* _
 // Host-side launch
 // --------------------------------------------------------------------------
 template <int DIM, bool LM, bool DISS, int EX, int EY>
-static hipError_t launch_fused_t(const Params& P, const double* Uin, double* Uout, StepIO io, int zchunk,
+static hipError_t launch_fused_t(const Params& P, const double* Uin, double* Uout, StepIO io, const TileShape& ts,
                                  hipStream_t s) {
   constexpr int TX = EX - 4;
   constexpr int TY = (DIM == 3) ? EY - 4 : 1;
   io.ntx = (P.nx + TX - 1) / TX;
   io.nty = (DIM == 3) ? (P.ny + TY - 1) / TY : 1;
-  io.zchunk = zchunk;
-  dim3 grid(io.ntx * io.nty, (P.nz + zchunk - 1) / zchunk);
-  hipLaunchKernelGGL((k_step_fused<DIM, LM, DISS, EX, EY>), grid, dim3(EX * EY), 0, s, P, Uin, Uout, io);
+  io.zchunk = ts.zchunk;
+  const long long total = (long long)io.ntx * io.nty * P.nz;
+  // one workgroup per (CU x resident blocks), each with an equal share of
+  // planes; never more workgroups than shares of at least zchunk planes
+  static int occ = 0;  // resident blocks per CU of this instance
+  if (occ == 0) {
+    int o = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, k_step_fused<DIM, LM, DISS, EX, EY>, EX * EY, 0) !=
+            hipSuccess ||
+        o < 1)
+      o = 1;
+    occ = o;
+  }
+  int ncu = ts.num_cu;
+  if (ncu <= 0) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1)
+      ncu = 256;
+  }
+  long long nwg = (long long)(ts.wg_per_cu > 0 ? ts.wg_per_cu : occ) * ncu;
+  const long long by_chunk = (total + ts.zchunk - 1) / ts.zchunk;
+  if (by_chunk < nwg) nwg = by_chunk;
+  if (nwg < 1) nwg = 1;
+  hipLaunchKernelGGL((k_step_fused<DIM, LM, DISS, EX, EY>), dim3((unsigned)nwg), dim3(EX * EY), 0, s, P, Uin, Uout,
+                     io);
   return hipGetLastError();
 }
 
@@ -518,15 +567,15 @@ hipError_t launch_step_fused(const Params& P, const double* Uin, double* Uout, S
                              hipStream_t s) {
   const bool lm = P.low_mach != 0, ds = P.diss != 0;
   if (P.dim == 2) {
-    if (lm && ds) return launch_fused_t<2, true, true, 64, 1>(P, Uin, Uout, io, ts.zchunk, s);
-    if (lm && !ds) return launch_fused_t<2, true, false, 64, 1>(P, Uin, Uout, io, ts.zchunk, s);
-    if (!lm && ds) return launch_fused_t<2, false, true, 64, 1>(P, Uin, Uout, io, ts.zchunk, s);
-    return launch_fused_t<2, false, false, 64, 1>(P, Uin, Uout, io, ts.zchunk, s);
+    if (lm && ds) return launch_fused_t<2, true, true, 64, 1>(P, Uin, Uout, io, ts, s);
+    if (lm && !ds) return launch_fused_t<2, true, false, 64, 1>(P, Uin, Uout, io, ts, s);
+    if (!lm && ds) return launch_fused_t<2, false, true, 64, 1>(P, Uin, Uout, io, ts, s);
+    return launch_fused_t<2, false, false, 64, 1>(P, Uin, Uout, io, ts, s);
   }
-  if (lm && ds) return launch_fused_t<3, true, true, 32, 16>(P, Uin, Uout, io, ts.zchunk, s);
-  if (lm && !ds) return launch_fused_t<3, true, false, 32, 16>(P, Uin, Uout, io, ts.zchunk, s);
-  if (!lm && ds) return launch_fused_t<3, false, true, 32, 16>(P, Uin, Uout, io, ts.zchunk, s);
-  return launch_fused_t<3, false, false, 32, 16>(P, Uin, Uout, io, ts.zchunk, s);
+  if (lm && ds) return launch_fused_t<3, true, true, 32, 16>(P, Uin, Uout, io, ts, s);
+  if (lm && !ds) return launch_fused_t<3, true, false, 32, 16>(P, Uin, Uout, io, ts, s);
+  if (!lm && ds) return launch_fused_t<3, false, true, 32, 16>(P, Uin, Uout, io, ts, s);
+  return launch_fused_t<3, false, false, 32, 16>(P, Uin, Uout, io, ts, s);
 }
 
 }  // namespace ars

@@ -19,7 +19,9 @@ struct StepIO {
 };
 
 struct TileShape {
-  int zchunk;
+  int zchunk;     // minimum share of planes per workgroup
+  int num_cu;     // compute units of the device (queried at first launch)
+  int wg_per_cu;  // resident workgroups per CU of the chosen kernel
 };
 
 hipError_t launch_step_fused(const Params& P, const double* Uin, double* Uout, StepIO io, const TileShape& ts,

@@ -20,13 +20,13 @@ struct RefGrid {
 
 // Field offsets (in units of npad doubles) inside the reference workspace.
 enum {
-  R_RHO = 0, R_R, R_UX, R_UY, R_UZ, R_P, R_C, R_RC, R_T,          // primitives (9)
-  R_CONS = 9,                                                     // 5 conserved
-  R_FACE = 14,                                                    // 3 axes x (us, pi, P, S)
-  R_WALL = 26,                                                    // 3 axes wall flags (as doubles)
-  R_L = 29, R_SB = 30, R_BT = 31,                                 // L, S-bar, 5 b~
-  R_G = 36,                                                       // 3 axes x 5 fluxes
-  R_NFIELD = 51
+  R_RHO = 0, R_R, R_UX, R_UY, R_UZ, R_P, R_C, R_RC, R_T, R_IC, R_IRC,  // primitives (11)
+  R_CONS = 11,                                                         // 5 conserved
+  R_FACE = 16,                                                         // 3 axes x (us, pi, P, S)
+  R_WALL = 28,                                                         // 3 axes wall flags (as doubles)
+  R_L = 31, R_SB = 32, R_BT = 33,                                      // L, S-bar, 5 b~
+  R_G = 38,                                                            // 3 axes x 5 fluxes
+  R_NFIELD = 53
 };
 
 static RefGrid make_grid(const Params& P) {
@@ -95,6 +95,8 @@ __global__ void k_ref_prim(Params P, RefGrid G, const double* __restrict__ U, do
   W[R_C * n + i] = q.c;
   W[R_RC * n + i] = q.rc;
   W[R_T * n + i] = q.T;
+  W[R_IC * n + i] = q.ic;
+  W[R_IRC * n + i] = q.irc;
 #pragma unroll
   for (int v = 0; v < 5; ++v) {
     double x = 0.0;
@@ -123,12 +125,15 @@ __global__ void k_ref_face(Params P, RefGrid G, int a, double* __restrict__ W) {
   int wall = 0;
   if (a == 2) {
     wall = (qz == 1 && P.bcz[0] == BC_WALL) || (qz == P.nz + 1 && P.bcz[1] == BC_WALL);
-    face_vert<LM>(P, W[R_RHO * n + i], W[R_RC * n + i], W[R_C * n + i], W[R_P * n + i], W[uf * n + i],
-                  W[R_RHO * n + j], W[R_RC * n + j], W[R_C * n + j], W[R_P * n + j], W[uf * n + j],
-                  phi_at(P, qz + 1 - 2) - phi_at(P, qz - 2), wall != 0, us, pi, Pf, S);
+    Prim<DIM> L, R;
+    L.rho = W[R_RHO * n + i]; L.rc = W[R_RC * n + i]; L.irc = W[R_IRC * n + i]; L.ic = W[R_IC * n + i];
+    L.p = W[R_P * n + i]; L.u[DIM - 1] = W[uf * n + i];
+    R.rho = W[R_RHO * n + j]; R.rc = W[R_RC * n + j]; R.irc = W[R_IRC * n + j]; R.ic = W[R_IC * n + j];
+    R.p = W[R_P * n + j]; R.u[DIM - 1] = W[uf * n + j];
+    face_vert<LM, DIM>(P, L, R, phi_at(P, qz + 1 - 2) - phi_at(P, qz - 2), wall != 0, us, pi, Pf, S);
   } else {
-    face_lat<LM>(P, W[R_RC * n + i], W[R_C * n + i], W[R_P * n + i], W[uf * n + i], W[R_RC * n + j],
-                 W[R_C * n + j], W[R_P * n + j], W[uf * n + j], us, pi, Pf);
+    face_lat<LM>(P, W[R_RC * n + i], W[R_IRC * n + i], W[R_IC * n + i], W[R_P * n + i], W[uf * n + i],
+                 W[R_RC * n + j], W[R_IRC * n + j], W[R_IC * n + j], W[R_P * n + j], W[uf * n + j], us, pi, Pf);
   }
   const int f = R_FACE + 4 * a;
   W[(f + 0) * n + i] = us;

@@ -94,12 +94,14 @@ def test_face_zero_velocity_at_discrete_equilibrium():
         rL = rng.uniform(0.1, 3.0)
         pL = rng.uniform(0.1, 3.0)
         phiL = rng.uniform(-1, 1)
-        phiR = phiL + rng.uniform(1e-4, 0.2)
+        # keep the right state physical: p_L - rho_L dPhi / 2 > 0
+        phiR = phiL + rng.uniform(1e-4, min(0.2, 0.9 * pL / rL))
         # p_R - p_L = -(rL + rR)/2 dPhi with p_R = rR T_R, T_R chosen freely
         TR = rng.uniform(0.3, 2.0)
         dphi = phiR - phiL
         rR = (pL - 0.5 * rL * dphi) / (TR + 0.5 * dphi)
         pR = rR * TR
+        assert rR > 0 and pR > 0
         f = O.face(cfg, 0, (rL, 0.0, pL), (rR, 0.0, pR), phiL, phiR)
         ulp = np.spacing(max(pL, pR))
         assert abs(f["ustar"]) <= 4 * ulp / f["a"]
