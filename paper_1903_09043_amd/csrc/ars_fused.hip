@@ -307,9 +307,9 @@ __global__ void __launch_bounds__(EX* EY) k_step_fused(Params P, const double* _
     }
 
     // lateral total fluxes of plane p-1 (own +x / +y faces)
+    // lateral fluxes are published only where computed; every reader of a
+    // GX slot (an output cell or its -x/-y neighbour) has it computed
     double GXn[NV], GYn[NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) GXn[v] = GYn[v] = 0.0;
     const bool doG = (p - 1 >= z0) && (p - 1 < z1);
     if (doG && (needGx || needGy)) {
 #pragma unroll
@@ -322,7 +322,12 @@ __global__ void __launch_bounds__(EX* EY) k_step_fused(Params P, const double* _
         const bool upL = us >= 0.0;
         double bu[NV];
 #pragma unroll
-        for (int v = 0; v < NV; ++v) bu[v] = upL ? bt1[v] : sm[(Ly::B + v) * NPOS + nb];
+        for (int v = 0; v < NV; ++v) {
+          // load the neighbour's value unconditionally and select: keeps the
+          // upwind choice a v_cndmask instead of a divergent branch per field
+          const double bn = sm[(Ly::B + v) * NPOS + nb];
+          bu[v] = upL ? bt1[v] : bn;
+        }
         G[0] = bu[0] * us;
 #pragma unroll
         for (int k = 0; k < DIM; ++k) {
@@ -475,10 +480,13 @@ __global__ void __launch_bounds__(EX* EY) k_step_fused(Params P, const double* _
     __syncthreads();  // ---------------------------------------------- bar 3
 
     // ================= step 4: publish lateral fluxes of plane p-1 ==========
+    if (doG && needGx) {
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      sm[(Ly::GX + v) * NPOS + tid] = GXn[v];
-      if (DIM == 3) sm[(Ly::GX + NV + v) * NPOS + tid] = GYn[v];
+      for (int v = 0; v < NV; ++v) sm[(Ly::GX + v) * NPOS + tid] = GXn[v];
+    }
+    if (DIM == 3 && doG && needGy) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) sm[(Ly::GX + NV + v) * NPOS + tid] = GYn[v];
     }
     // rotate the vertical window
 #pragma unroll
