@@ -178,6 +178,130 @@ size_t ars_workspace_bytes_ref(const ars_ctx* ctx);
 int ars_step_ref(ars_ctx* ctx, double* d_state, double* d_tmp, void* d_work, void* d_work_ref, int n_steps,
                  const double* d_dt_sched, void* stream);
 
+/* Adjoint of one step at a frozen time step (the gradient is that of the
+ * discrete step of eq. all_regime_scheme + Sec. 2.2 with dt held fixed):
+ *   d_lam_n = (dU^{n+1}/dU^n)^T d_lam_np1          (overwritten)
+ *   d_param_grad[0] += <d_lam_np1, dU^{n+1}/dmu>, d_param_grad[1] += ... dkappa
+ * d_state_n is U^n (the step's input), *d_dt the step's dt (device).
+ * Non-smooth operations differentiate the branch taken by the forward step
+ * (max/min: first argument on ties; upwind: u* >= 0 takes the left cell).
+ * d_param_grad may be NULL; with mu = kappa = 0 the dissipative terms are
+ * absent and no parameter derivative is produced.  d_work_adj: caller
+ * buffer of ars_workspace_bytes_adjoint bytes.  Deterministic (no atomics).
+ * d_lam_n must not alias d_lam_np1.  Asynchronous. */
+size_t ars_workspace_bytes_adjoint(const ars_ctx* ctx);
+int ars_step_adjoint(ars_ctx* ctx, const double* d_state_n, const double* d_lam_np1, double* d_lam_n,
+                     const double* d_dt, double* d_param_grad, void* d_work_adj, void* stream);
+
+/* Kinetic-energy objective J = sum (1/2) |m|^2 / rho dV of d_state into the
+ * device scalar *d_ke, and (if d_grad is not NULL) its gradient dJ/dU in
+ * state layout (d/drho = -|u|^2 dV/2, d/dm = u dV, d/dE = 0).  Uses the
+ * workspace's reduction area.  Asynchronous. */
+int ars_kinetic_energy(ars_ctx* ctx, const double* d_state, double* d_grad, double* d_ke, void* d_work,
+                       void* stream);
+
+/* Binomial checkpointing plan (host only) for reversing n steps with s
+ * snapshot slots, slot 0 holding U^0 and slots used as a stack.  Writes up
+ * to cap actions of 4 int32 {op, step, arg, 0}:
+ *   op 0 ADVANCE  the working state from step `step` to step `arg`
+ *   op 1 STORE    the working state (at step `step`) into slot `arg`
+ *   op 2 RESTORE  slot `arg` (holding step `step`) into the working state
+ *   op 3 ADJOINT  of step `step` (the working state is U^step)
+ * Returns the number of actions (call with cap = 0 to size the array) or
+ * ARS_EINVAL; *forward_steps = total steps advanced, which is the minimum
+ * ars_revolve_cost(n, s) over all such schedules. */
+int ars_revolve_plan(int n, int s, int32_t* actions, int cap, int64_t* forward_steps);
+int64_t ars_revolve_cost(int n, int s);
+
+/* ---- Batched problems -------------------------------------------------
+ * Many independent 2D problems (each its own ars_config: size, mu, kappa,
+ * boundaries, theta switch) advanced by one persistent launch; each
+ * instance keeps its own CFL time step (Sec. 2 step with the time-step
+ * rule of the single-problem calls) and its results equal those of
+ * ars_step on that instance alone, bit for bit.  One workgroup owns one
+ * instance for all steps (largest instances first), so no workgroup ever
+ * waits for another.
+ *
+ * States: one caller-owned device array of ars_batch_state_len() doubles;
+ * instance k occupies ars_batch_state_offset(k) onward, in the state layout
+ * of the single-problem calls.  d_tmps: a second array of the same length
+ * (ping-pong).  d_table: caller-owned device buffer of
+ * ars_batch_table_bytes() bytes holding the instance table (per-instance
+ * parameters, pointers, t, next dt and fault latch).
+ *
+ * ars_batch_create   validates every config (dim must be 2, else
+ *                    ARS_EUNSUPPORTED); host only.
+ * ars_batch_set_tiling  rows = row segments of 60 columns per workgroup
+ *                    (4 or 8); zc = per-instance vertical chunk counts
+ *                    (each must divide that instance's nz; NULL = the
+ *                    built-in cost model).  Results do not depend on the
+ *                    tiling.  Invalidates the captured graph; call
+ *                    ars_batch_bind again afterwards.
+ * ars_batch_bind     writes the table for these buffers (t = 0) and
+ *                    synchronises `stream`.
+ * ars_batch_step     advances every instance n_steps steps, dt of each step
+ *                    = cfl / (max rate of its current state).  Asynchronous.
+ * ars_batch_capture  captures the same launch (n_steps) into a hipGraph on
+ *                    `stream` (which must not be NULL); ars_batch_replay
+ *                    launches it.  A replay continues from the table's
+ *                    current t and states.
+ * ars_batch_read     copies per-instance t, next dt and the fault cell
+ *                    (-1: none) to host arrays of n entries (each may be
+ *                    NULL); synchronises; ARS_ENONPHYS if any instance
+ *                    latched a fault. */
+typedef struct ars_batch ars_batch;
+int ars_batch_create(int n_inst, const ars_config* cfgs, ars_batch** out);
+void ars_batch_destroy(ars_batch* b);
+size_t ars_batch_state_len(const ars_batch* b);
+size_t ars_batch_state_offset(const ars_batch* b, int k);
+size_t ars_batch_table_bytes(const ars_batch* b);
+int ars_batch_set_tiling(ars_batch* b, int rows, const int* zc);
+int ars_batch_get_tiling(const ars_batch* b, int* rows, int* zc);
+int ars_batch_bind(ars_batch* b, double* d_states, double* d_tmps, void* d_table, void* stream);
+int ars_batch_step(ars_batch* b, void* d_table, int n_steps, void* stream);
+int ars_batch_capture(ars_batch* b, void* d_table, int n_steps, void* stream);
+int ars_batch_replay(ars_batch* b, void* stream);
+int ars_batch_read(const ars_batch* b, const void* d_table, double* h_t, double* h_dt, int64_t* h_fault_cell,
+                   void* stream);
+
+/* ---- Launch shapes and autotuning --------------------------------------
+ * ars_set_tiling / ars_get_tiling: the fused step's launch shape, zchunk =
+ * smallest vertical share of planes a workgroup takes (>= 1) and wg_per_cu
+ * = workgroups per compute unit (0: as many as are resident at once, up to
+ * 32).  Results never depend on either, only time does.
+ *
+ * ars_autotune times the fused step (trial_steps steps after one untimed
+ * step, per candidate) for candidate (zchunk, wg_per_cu) pairs on a copy of
+ * d_state, keeps the fastest in ctx and returns it in *out (may be NULL).
+ * d_state is not modified; the workspace's rate slots and fault latch are
+ * reset (as by ars_workspace_init).  It allocates and frees a temporary
+ * device copy of two states: a set-up call, never to be captured.
+ *
+ * ars_batch_autotune times the batched launch over rows in {4, 8} and
+ * vertical chunking policies (zc_policy 0: the cost model, 1: no chunks,
+ * 2: twice, 3: half the model's chunks), applies the fastest with
+ * ars_batch_set_tiling and rebinds the table (t = 0).  d_states is
+ * restored to its contents at the call; it allocates a temporary copy.
+ *
+ * cache_path (may be NULL): text file of tuned shapes, one line per key
+ * "<key> <a> <b> <ms_per_step>"; a key found there is applied without
+ * timing (from_cache = 1), otherwise the result is appended.  Keys name
+ * the device (architecture, compute units) and the problem (dimension,
+ * grid, boundary kinds, theta and dissipation switches; for a batch a hash
+ * of all instances' shapes and switches). */
+typedef struct ars_tune_result {
+  int32_t zchunk, wg_per_cu;  /* fused step */
+  int32_t rows, zc_policy;    /* batch */
+  int32_t from_cache, n_candidates;
+  double ms_per_step;         /* of the chosen shape */
+} ars_tune_result;
+int ars_set_tiling(ars_ctx* ctx, int zchunk, int wg_per_cu);
+int ars_get_tiling(const ars_ctx* ctx, int* zchunk, int* wg_per_cu);
+int ars_autotune(ars_ctx* ctx, const double* d_state, void* d_work, int trial_steps, const char* cache_path,
+                 void* stream, ars_tune_result* out);
+int ars_batch_autotune(ars_batch* b, double* d_states, double* d_tmps, void* d_table, int trial_steps,
+                       const char* cache_path, void* stream, ars_tune_result* out);
+
 /* Diagnostics of d_state into *h_out (synchronises `stream`).  Returns
  * ARS_ENONPHYS (and clears the latch) if a fault was latched. */
 int ars_diagnostics(ars_ctx* ctx, const double* d_state, void* d_work, ars_diag* h_out, void* stream);

@@ -42,6 +42,14 @@ class ArsConfig(C.Structure):
     ]
 
 
+class ArsTuneResult(C.Structure):
+    _fields_ = [("zchunk", C.c_int32), ("wg_per_cu", C.c_int32), ("rows", C.c_int32), ("zc_policy", C.c_int32),
+                ("from_cache", C.c_int32), ("n_candidates", C.c_int32), ("ms_per_step", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 class ArsDiag(C.Structure):
     _fields_ = [
         ("mass", C.c_double), ("mom", C.c_double * 3), ("e_total", C.c_double), ("e_kin", C.c_double),
@@ -69,9 +77,30 @@ SIGNATURES = [
     ("ars_step_sched", C.c_int, [_VP, _VP, _VP, _VP, C.c_int, _VP, _VP, _VP]),
     ("ars_workspace_bytes_ref", C.c_size_t, [_VP]),
     ("ars_step_ref", C.c_int, [_VP, _VP, _VP, _VP, _VP, C.c_int, _VP, _VP]),
+    ("ars_workspace_bytes_adjoint", C.c_size_t, [_VP]),
+    ("ars_step_adjoint", C.c_int, [_VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
+    ("ars_kinetic_energy", C.c_int, [_VP, _VP, _VP, _VP, _VP, _VP]),
+    ("ars_revolve_plan", C.c_int, [C.c_int, C.c_int, C.POINTER(C.c_int32), C.c_int, C.POINTER(C.c_int64)]),
+    ("ars_revolve_cost", C.c_int64, [C.c_int, C.c_int]),
     ("ars_diagnostics", C.c_int, [_VP, _VP, _VP, C.POINTER(ArsDiag), _VP]),
     ("ars_fault", C.c_int, [_VP, _VP, C.POINTER(C.c_int64), _VP]),
     ("ars_strerror", C.c_char_p, [C.c_int]),
+    ("ars_batch_create", C.c_int, [C.c_int, _CP, C.POINTER(_VP)]),
+    ("ars_batch_destroy", None, [_VP]),
+    ("ars_batch_state_len", C.c_size_t, [_VP]),
+    ("ars_batch_state_offset", C.c_size_t, [_VP, C.c_int]),
+    ("ars_batch_table_bytes", C.c_size_t, [_VP]),
+    ("ars_batch_set_tiling", C.c_int, [_VP, C.c_int, C.POINTER(C.c_int)]),
+    ("ars_batch_get_tiling", C.c_int, [_VP, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+    ("ars_batch_bind", C.c_int, [_VP, _VP, _VP, _VP, _VP]),
+    ("ars_batch_step", C.c_int, [_VP, _VP, C.c_int, _VP]),
+    ("ars_batch_capture", C.c_int, [_VP, _VP, C.c_int, _VP]),
+    ("ars_batch_replay", C.c_int, [_VP, _VP]),
+    ("ars_batch_read", C.c_int, [_VP, _VP, _DP, _DP, C.POINTER(C.c_int64), _VP]),
+    ("ars_set_tiling", C.c_int, [_VP, C.c_int, C.c_int]),
+    ("ars_get_tiling", C.c_int, [_VP, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+    ("ars_autotune", C.c_int, [_VP, _VP, _VP, C.c_int, C.c_char_p, _VP, C.POINTER(ArsTuneResult)]),
+    ("ars_batch_autotune", C.c_int, [_VP, _VP, _VP, _VP, C.c_int, C.c_char_p, _VP, C.POINTER(ArsTuneResult)]),
 ]
 
 _lib = None
@@ -120,6 +149,24 @@ def make_config(cfg: dict) -> ArsConfig:
     return c
 
 
+def revolve_plan(n: int, s: int):
+    """Binomial checkpointing actions [(op, step, arg)] and the forward steps
+    they advance (see ars_revolve_plan in include/ars.h)."""
+    L = lib()
+    cnt = L.ars_revolve_plan(int(n), int(s), None, 0, None)
+    if cnt < 0:
+        raise ArsError(cnt, "ars_revolve_plan")
+    buf = (C.c_int32 * (4 * cnt))()
+    fwd = C.c_int64(0)
+    L.ars_revolve_plan(int(n), int(s), buf, cnt, C.byref(fwd))
+    acts = [(buf[4 * i], buf[4 * i + 1], buf[4 * i + 2]) for i in range(cnt)]
+    return acts, fwd.value
+
+
+def revolve_cost(n: int, s: int) -> int:
+    return lib().ars_revolve_cost(int(n), int(s))
+
+
 def validate(cfg: dict) -> int:
     c = make_config(cfg)
     return lib().ars_validate(C.byref(c))
@@ -166,6 +213,14 @@ class Context:
 
     def set_zchunk(self, z: int):
         _check(lib().ars_set_zchunk(self.h, int(z)), "ars_set_zchunk")
+
+    def set_tiling(self, zchunk: int, wg_per_cu: int = 0):
+        _check(lib().ars_set_tiling(self.h, int(zchunk), int(wg_per_cu)), "ars_set_tiling")
+
+    def tiling(self):
+        z, w = C.c_int(0), C.c_int(0)
+        _check(lib().ars_get_tiling(self.h, C.byref(z), C.byref(w)), "ars_get_tiling")
+        return z.value, w.value
 
     def zchunk(self) -> int:
         return lib().ars_get_zchunk(self.h)
@@ -239,6 +294,36 @@ class Solver:
                                   dt_sched.numel(), _ptr(dt_sched), self.stream), "ars_step_ref")
         return self
 
+    def adjoint_workspace(self):
+        if getattr(self, "_wadj", None) is None:
+            nb = lib().ars_workspace_bytes_adjoint(self.ctx.h)
+            self._wadj = self.torch.empty(nb, dtype=self.torch.uint8, device=self.device)
+        return self._wadj
+
+    def step_adjoint(self, U_n, lam_np1, dt, lam_n=None, param_grad=None):
+        """lam_n = (dU^{n+1}/dU^n)^T lam_np1 at frozen dt (a 1-element device
+        tensor); param_grad (2-element device tensor) accumulates the mu and
+        kappa derivatives.  Returns lam_n."""
+        t = self.torch
+        if lam_n is None:
+            lam_n = t.empty_like(lam_np1)
+        dt = dt.to(self.device, t.float64).reshape(-1)
+        w = self.adjoint_workspace()
+        _check(lib().ars_step_adjoint(self.ctx.h, _ptr(U_n), _ptr(lam_np1), _ptr(lam_n), _ptr(dt),
+                                      _ptr(param_grad) if param_grad is not None else None, _ptr(w), self.stream),
+               "ars_step_adjoint")
+        return lam_n
+
+    def kinetic_energy(self, U=None, grad=None, out=None):
+        """Device scalar KE of U (default: the solver state); fills grad (state
+        layout) with dKE/dU when given."""
+        t = self.torch
+        U = self.U if U is None else U
+        out = t.zeros(1, dtype=t.float64, device=self.device) if out is None else out
+        _check(lib().ars_kinetic_energy(self.ctx.h, _ptr(U), _ptr(grad) if grad is not None else None, _ptr(out),
+                                        _ptr(self.work), self.stream), "ars_kinetic_energy")
+        return out
+
     def diagnostics(self, raise_on_fault=True) -> dict:
         d = ArsDiag()
         rc = lib().ars_diagnostics(self.ctx.h, _ptr(self.U), _ptr(self.work), C.byref(d), self.stream)
@@ -248,6 +333,15 @@ class Solver:
                     e_grav=d.e_grav, max_u=d.max_u, mean_u=d.mean_u, max_mach=d.max_mach, nu_bot=d.nu_bot,
                     nu_top=d.nu_top, fault=d.fault, fault_cell=d.fault_cell)
 
+    def autotune(self, trial_steps: int = 10, cache_path=None) -> dict:
+        """Time candidate launch shapes of the fused step on a copy of the
+        current state and keep the fastest (``ars_autotune``)."""
+        r = ArsTuneResult()
+        _check(lib().ars_autotune(self.ctx.h, _ptr(self.U), _ptr(self.work), int(trial_steps),
+                                  cache_path.encode() if cache_path else None, self.stream, C.byref(r)),
+               "ars_autotune")
+        return r.as_dict()
+
     def fault(self):
         fc = C.c_int64(-1)
         rc = lib().ars_fault(self.ctx.h, _ptr(self.work), C.byref(fc), self.stream)
@@ -255,3 +349,94 @@ class Solver:
 
     def numpy(self):
         return self.U.detach().cpu().numpy()
+
+
+class Batch:
+    """Many independent 2D problems advanced by one persistent launch
+    (``ars_batch_*``).  ``cfgs``: list of config dicts.  ``states`` is one
+    flat device array; ``view(k)`` is instance k in state layout."""
+
+    def __init__(self, cfgs, device="cuda"):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("ars.Batch needs a GPU (no CPU fallback)")
+        self.torch = torch
+        self.cfgs = [dict(c) for c in cfgs]
+        self.n = len(self.cfgs)
+        arr = (ArsConfig * self.n)(*[make_config(c) for c in self.cfgs])
+        h = _VP()
+        _check(lib().ars_batch_create(self.n, arr, C.byref(h)), "ars_batch_create")
+        self.h = h
+        self.device = torch.device(device)
+        L = lib()
+        self.len = L.ars_batch_state_len(h)
+        self.off = [L.ars_batch_state_offset(h, k) for k in range(self.n)]
+        self.states = torch.zeros(self.len, dtype=torch.float64, device=self.device)
+        self.tmps = torch.zeros_like(self.states)
+        self.table = torch.zeros(L.ars_batch_table_bytes(h), dtype=torch.uint8, device=self.device)
+        self.bind()
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            lib().ars_batch_destroy(h)
+            self.h = None
+
+    @property
+    def stream(self):
+        return C.c_void_p(self.torch.cuda.current_stream(self.device).cuda_stream)
+
+    def view(self, k):
+        shape = state_shape(self.cfgs[k])
+        n = int(np.prod(shape))
+        return self.states[self.off[k]:self.off[k] + n].view(shape)
+
+    def bind(self):
+        _check(lib().ars_batch_bind(self.h, _ptr(self.states), _ptr(self.tmps), _ptr(self.table), self.stream),
+               "ars_batch_bind")
+        return self
+
+    def set_tiling(self, rows, zc=None):
+        z = (C.c_int * self.n)(*[int(v) for v in zc]) if zc is not None else None
+        _check(lib().ars_batch_set_tiling(self.h, int(rows), z), "ars_batch_set_tiling")
+        return self
+
+    def tiling(self):
+        r = C.c_int(0)
+        z = (C.c_int * self.n)()
+        _check(lib().ars_batch_get_tiling(self.h, C.byref(r), z), "ars_batch_get_tiling")
+        return r.value, list(z)
+
+    def autotune(self, trial_steps: int = 5, cache_path=None) -> dict:
+        """Time candidate tilings of the batched launch on the current
+        states (restored afterwards), apply the fastest and rebind (t = 0)."""
+        r = ArsTuneResult()
+        _check(lib().ars_batch_autotune(self.h, _ptr(self.states), _ptr(self.tmps), _ptr(self.table),
+                                        int(trial_steps), cache_path.encode() if cache_path else None, self.stream,
+                                        C.byref(r)), "ars_batch_autotune")
+        return r.as_dict()
+
+    def step(self, n):
+        _check(lib().ars_batch_step(self.h, _ptr(self.table), int(n), self.stream), "ars_batch_step")
+        return self
+
+    def capture(self, n, stream):
+        """Capture an n-step launch on ``stream`` (a non-default torch stream)."""
+        _check(lib().ars_batch_capture(self.h, _ptr(self.table), int(n), C.c_void_p(stream.cuda_stream)),
+               "ars_batch_capture")
+        return self
+
+    def replay(self, stream):
+        _check(lib().ars_batch_replay(self.h, C.c_void_p(stream.cuda_stream)), "ars_batch_replay")
+        return self
+
+    def read(self):
+        """(t, next dt, fault cell per instance (-1: none), status)."""
+        t = np.zeros(self.n)
+        dt = np.zeros(self.n)
+        fc = (C.c_int64 * self.n)()
+        rc = lib().ars_batch_read(self.h, _ptr(self.table), t.ctypes.data_as(_DP), dt.ctypes.data_as(_DP), fc,
+                                  self.stream)
+        if rc not in (OK, ENONPHYS):
+            raise ArsError(rc, "ars_batch_read")
+        return t, dt, np.array(list(fc), dtype=np.int64), rc

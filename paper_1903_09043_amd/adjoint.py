@@ -1,0 +1,132 @@
+"""Gradients of a convection run through the hand-written adjoint step.
+
+``rb_kinetic_energy(dT0, mu, kappa, problem)`` is a ``torch.autograd.Function``:
+its forward runs ``problem.nsteps`` explicit steps of the all-regime scheme
+from the Rayleigh-Benard base state heated by the temperature perturbation
+``dT0`` and returns the final kinetic energy; its backward returns
+dJ/d(dT0), dJ/dmu and dJ/dkappa.  The time step of every step is the one the
+forward run chose (the schedule is recorded and frozen: dt = CFL / max rate
+is not differentiated).  Intermediate states are not kept: the backward
+follows a binomial checkpointing plan (``ars_revolve_plan``) over
+``problem.slots`` state snapshots, recomputing forward steps between them.
+
+Everything numerical runs in libars.so (forward steps, adjoint steps,
+objective and its gradient); this module only sequences the calls.  Rayleigh
+and Prandtl numbers enter through ``workloads.ra_pr_to_mu_kappa`` written in
+torch operations, so autograd chains (Ra, Pr) -> (mu, kappa) -> J.
+"""
+import torch
+
+from . import ArsError, Solver, revolve_plan, workloads
+
+OP_ADVANCE, OP_STORE, OP_RESTORE, OP_ADJOINT = 0, 1, 2, 3
+
+
+class RBProblem:
+    """Base state and run length of the objective.
+
+    cfg, prob, params, seed: a set-up from ``workloads`` (params[3], the
+    seeded noise amplitude, is ignored: the perturbation is the argument
+    ``dT0``).  ``u0`` (optional, state-layout velocity field tensor of shape
+    (dim, ...)) adds a fixed initial flow.  ``dt_sched`` (optional device
+    tensor) replaces the CFL time steps by a given schedule."""
+
+    def __init__(self, cfg, prob, params, nsteps, slots, seed=0, u0=None, dt_sched=None, device="cuda"):
+        self.cfg = dict(cfg)
+        self.nsteps = int(nsteps)
+        self.slots = max(1, min(int(slots), self.nsteps))
+        self.device = torch.device(device)
+        base = Solver(self.cfg, device=device).init(prob, list(params[:3]) + [0.0], seed)
+        U = base.U.clone()
+        D = self.cfg["dim"]
+        self.gm1 = self.cfg.get("gamma", 5.0 / 3.0) - 1.0
+        self.rho = U[0].clone()
+        # base temperature p / rho of the hydrostatic state (no flow)
+        self.T = U[D + 1] * self.gm1 / self.rho
+        if u0 is not None:
+            u0 = torch.as_tensor(u0, dtype=torch.float64, device=self.device)
+            for k in range(D):
+                U[1 + k] = self.rho * u0[k]
+        self.U_base = U
+        self.dt_sched = dt_sched
+        self._solvers = {}
+
+    def solver(self, mu, kappa):
+        key = (float(mu), float(kappa))
+        if key not in self._solvers:
+            self._solvers.clear()
+            self._solvers[key] = Solver(dict(self.cfg, mu=key[0], kappa=key[1]), device=self.device)
+        return self._solvers[key]
+
+    def initial_state(self, dT0):
+        """U^0: base density and flow, p = rho (T + dT0)."""
+        D = self.cfg["dim"]
+        U = self.U_base.clone()
+        kin = torch.zeros_like(self.rho)
+        for k in range(D):
+            kin = kin + U[1 + k] * U[1 + k]
+        U[D + 1] = (self.rho * (self.T + dT0)) / self.gm1 + 0.5 * kin / self.rho
+        return U
+
+
+class _RBKineticEnergy(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, dT0, mu, kappa, problem):
+        S = problem.solver(mu.item(), kappa.item())
+        U0 = problem.initial_state(dT0.detach().to(problem.device, torch.float64))
+        S.U.copy_(U0)
+        n = problem.nsteps
+        if problem.dt_sched is not None:
+            log = problem.dt_sched.to(problem.device, torch.float64).contiguous()
+            S.step_sched(log)
+        else:
+            S.compute_dt()
+            log = torch.zeros(n, dtype=torch.float64, device=problem.device)
+            S.step(n, dt_log=log)
+        grad = torch.empty_like(S.U)
+        J = S.kinetic_energy(grad=grad).clone()
+        rc, cell = S.fault()
+        if rc != 0:
+            raise ArsError(rc, f"forward run (fault at cell {cell})")
+        ctx.problem = problem
+        ctx.S = S
+        ctx.save_for_backward(U0, log, grad)
+        return J.reshape(())
+
+    @staticmethod
+    def backward(ctx, gJ):
+        problem, S = ctx.problem, ctx.S
+        U0, log, gradN = ctx.saved_tensors
+        n, s = problem.nsteps, problem.slots
+        plan, _ = revolve_plan(n, s)
+        snaps = [U0] + [torch.empty_like(U0) for _ in range(s - 1)]
+        lam = gradN * gJ.to(gradN.dtype)
+        lam_next = torch.empty_like(lam)
+        pg = torch.zeros(2, dtype=torch.float64, device=problem.device)
+        for op, step, arg in plan:
+            if op == OP_RESTORE:
+                S.U.copy_(snaps[arg])
+            elif op == OP_ADVANCE:
+                S.step_sched(log[step:arg])
+            elif op == OP_STORE:
+                snaps[arg].copy_(S.U)
+            elif op == OP_ADJOINT:
+                S.step_adjoint(S.U, lam, log[step:step + 1], lam_n=lam_next, param_grad=pg)
+                lam, lam_next = lam_next, lam
+        D = problem.cfg["dim"]
+        g_dT = lam[D + 1] * problem.rho / problem.gm1
+        return g_dT, pg[0].reshape(()), pg[1].reshape(()), None
+
+
+def rb_kinetic_energy(dT0, mu, kappa, problem):
+    """J = kinetic energy after problem.nsteps steps from the base state with
+    temperature perturbation dT0 (differentiable in dT0, mu, kappa)."""
+    mu = torch.as_tensor(mu, dtype=torch.float64)
+    kappa = torch.as_tensor(kappa, dtype=torch.float64)
+    return _RBKineticEnergy.apply(dT0, mu, kappa, problem)
+
+
+def rb_kinetic_energy_ra_pr(dT0, Ra, Pr, problem, **layer):
+    """Same with the transport coefficients from (Ra, Pr) of the layer."""
+    mu, kappa = workloads.ra_pr_to_mu_kappa(Ra, Pr, **layer)
+    return rb_kinetic_energy(dT0, mu, kappa, problem)

@@ -1,0 +1,740 @@
+// ars_adjoint.hip -- reverse (adjoint) product of one explicit step at a
+// frozen time step:  lam^n = (dU^{n+1}/dU^n)^T lam^{n+1},  plus
+// <lam^{n+1}, dU^{n+1}/dmu> and <lam^{n+1}, dU^{n+1}/dkappa>.
+//
+// The forward intermediates of the step (primitives with wall ghosts,
+// acoustic faces, acoustic cell values) are recomputed by the reference
+// phase kernels on the padded grid; the reverse sweep then runs the phases
+// backwards, each as a gather (a face or a cell collects every contribution
+// it receives, in a fixed order), so the result is deterministic:
+//   update^T -> flux^T (transport + viscous + heat) -> acoustic cell^T
+//   -> face solver^T -> primitive gather -> (wall ghost + primitive)^T
+//   -> fold of periodic / outflow images onto interior cells.
+// Non-smooth operations differentiate the branch the forward step took
+// (max/min: first argument on ties; |x|: sign of x >= 0; upwind: u* >= 0
+// takes the left cell), as the oracle's tangent-linear model does.
+#include "ars_dev.h"
+#include "ars_internal.h"
+#include "ars_ref.h"
+
+namespace ars {
+
+enum {
+  A_GB = R_NFIELD,         // 3 axes x 5: adjoint of the total face fluxes
+  A_FB = A_GB + 15,        // 3 axes x (u*, Pi*, P, S) adjoints
+  A_BTC = A_FB + 12,       // 3 axes x 5: adjoint of b~ sent to the upwind cell
+  A_VL = A_BTC + 15,       // 3 axes x (u_0, u_1, u_2, T) viscous adjoint to the left cell
+  A_VR = A_VL + 12,        // same, right cell
+  A_VT = A_VR + 12,        // 3 axes x (2 tangential axes x 2) tangential-gradient adjoints
+  A_PM = A_VT + 12,        // 3 axes x (mu, kappa) partial derivatives
+  A_CB = A_PM + 6,         // L, Am_0, Am_1, Am_2, AE, S-bar adjoints per cell
+  A_CONSB = A_CB + 6,      // 5: adjoint of the cell's conserved values through b~
+  A_FPL = A_CONSB + 5,     // 3 axes x (rho, u_n, p, rho c, 1/(rho c), 1/c) to the left cell
+  A_FPR = A_FPL + 18,      // same, right cell
+  A_PB = A_FPR + 18,       // rho, u_0, u_1, u_2, p, rho c, 1/(rho c), 1/c, T
+  A_UB = A_PB + 9,         // 5: adjoint of the (image) cell's conserved values
+  A_NFIELD = A_UB + 5
+};
+
+size_t adjoint_workspace_bytes(const Params& P) {
+  RefGrid G = make_grid(P);
+  return (size_t)A_NFIELD * (size_t)G.npad * sizeof(double) + 4096;
+}
+
+struct AdjIO {
+  const double* lam1;  // lam^{n+1}, interior SoA
+  double* lam0;        // lam^n, interior SoA
+  const double* dt;
+  double* pgrad;       // [d/dmu, d/dkappa] accumulated
+};
+
+__device__ __forceinline__ int qa_of(int a, int qx, int qy, int qz) { return a == 0 ? qx : (a == 1 ? qy : qz); }
+__device__ __forceinline__ int Pa_of(const RefGrid& G, int a) { return a == 0 ? G.Px : (a == 1 ? G.Py : G.Pz); }
+// active axis index t (0..DIM-1) -> padded axis; velocity component of an axis
+template <int DIM>
+__device__ __forceinline__ int axis_of(int t) { return t == DIM - 1 ? 2 : t; }
+template <int DIM>
+__device__ __forceinline__ int comp_of(int a) { return a == 2 ? DIM - 1 : a; }
+
+template <int DIM>
+__device__ __forceinline__ bool interior_cell(const RefGrid& G, int qx, int qy, int qz) {
+  return qx >= 2 && qx < G.Px - 2 && qz >= 2 && qz < G.Pz - 2 && (DIM == 2 || (qy >= 2 && qy < G.Py - 2));
+}
+// cell in the range where the acoustic cell values exist: [1, P-1) on every active axis
+template <int DIM>
+__device__ __forceinline__ bool cell_range(const RefGrid& G, int qx, int qy, int qz) {
+  return qx >= 1 && qx < G.Px - 1 && qz >= 1 && qz < G.Pz - 1 && (DIM == 2 || (qy >= 1 && qy < G.Py - 1));
+}
+// face (a, L = (qx,qy,qz)) in the range of the flux phase
+template <int DIM>
+__device__ __forceinline__ bool flux_range(const RefGrid& G, int a, int qx, int qy, int qz) {
+  const int q[3] = {qx, qy, qz};
+  const int Pd[3] = {G.Px, G.Py, G.Pz};
+  for (int b = 0; b < 3; ++b) {
+    if (DIM == 2 && b == 1) continue;
+    if (b == a) {
+      if (q[b] < 1 || q[b] >= Pd[b] - 2) return false;
+    } else {
+      if (q[b] < 2 || q[b] >= Pd[b] - 2) return false;
+    }
+  }
+  return true;
+}
+
+// ---------------------------------------------------------------- K0: zero
+__global__ void k_adj_zero(double* W, long long from, long long count) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+       i += (long long)gridDim.x * blockDim.x)
+    W[from + i] = 0.0;
+}
+
+// ------------------------------------------------------- K1: update^T ------
+// nb_v(c) = b_v(c) [+ rho Phi for E] - sum_a lam_a (G_v(a,c) - G_v(a,c-e_a))
+// [+ lam_z S-bar(c) for m_z];  E' = nb_E - nb_rho Phi.
+template <int DIM>
+__global__ void k_adj_update(Params P, RefGrid G, AdjIO io, double* __restrict__ W) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= G.npad) return;
+  constexpr int NV = DIM + 2;
+  const long long n = G.npad;
+  int qx, qy, qz;
+  decode(G, i, qx, qy, qz);
+  const double dt = *io.dt;
+  const double lam[3] = {dt / P.dx[0], DIM == 3 ? dt / P.dx[1] : 0.0, dt / P.dx[2]};
+  auto nbar = [&](int x, int y, int z, int v) -> double {
+    if (!interior_cell<DIM>(G, x, y, z)) return 0.0;
+    const long long c = (x - 2) + (long long)P.nx * ((DIM == 3 ? y - 2 : 0) + (long long)P.ny * (z - 2));
+    const double lr = io.lam1[c], lE = io.lam1[c + (NV - 1) * P.ncell];
+    if (v == 0) return lr - phi_at(P, z - 2) * lE;
+    if (v == NV - 1) return lE;
+    return io.lam1[c + v * P.ncell];
+  };
+  if (interior_cell<DIM>(G, qx, qy, qz)) {
+    const long long c = (qx - 2) + (long long)P.nx * ((DIM == 3 ? qy - 2 : 0) + (long long)P.ny * (qz - 2));
+    for (int v = 0; v < NV; ++v) io.lam0[c + v * P.ncell] = io.lam1[c + v * P.ncell];
+  }
+  for (int t = 0; t < DIM; ++t) {
+    const int a = axis_of<DIM>(t);
+    if (!flux_range<DIM>(G, a, qx, qy, qz)) continue;
+    const int rx = qx + (a == 0), ry = qy + (a == 1), rz = qz + (a == 2);
+    for (int v = 0; v < NV; ++v)
+      W[(A_GB + 5 * a + v) * n + i] = lam[a] * (nbar(rx, ry, rz, v) - nbar(qx, qy, qz, v));
+  }
+}
+
+// ------------------------------------------------------- K2: flux^T --------
+template <int DIM, bool DISS>
+__global__ void k_adj_flux(Params P, RefGrid G, int a, double* __restrict__ W) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= G.npad) return;
+  constexpr int NV = DIM + 2;
+  int qx, qy, qz;
+  decode(G, i, qx, qy, qz);
+  if (!flux_range<DIM>(G, a, qx, qy, qz)) return;
+  const long long n = G.npad;
+  const long long j = i + astride(G, a);
+  const int f = R_FACE + 4 * a;
+  const double us = W[(f + 0) * n + i];
+  const double pi = W[(f + 1) * n + i];
+  const bool wall = W[(R_WALL + a) * n + i] != 0.0;
+  const int dn = comp_of<DIM>(a);
+  double Gb[NV];
+  for (int v = 0; v < NV; ++v) Gb[v] = W[(A_GB + 5 * a + v) * n + i];
+  double usb = 0.0;
+  double pib = Gb[1 + dn];
+  double btc[NV];
+  for (int v = 0; v < NV; ++v) btc[v] = 0.0;
+  if (!wall) {
+    const long long up = us >= 0.0 ? i : j;
+    for (int v = 0; v < NV - 1; ++v) {
+      btc[v] = Gb[v] * us;
+      usb += Gb[v] * W[(R_BT + v) * n + up];
+    }
+    const double bE = W[(R_BT + NV - 1) * n + up];
+    btc[NV - 1] = Gb[NV - 1] * us;
+    pib += Gb[NV - 1] * us;
+    usb += Gb[NV - 1] * (bE + pi);
+  }
+  W[(A_FB + 4 * a + 0) * n + i] = usb;
+  W[(A_FB + 4 * a + 1) * n + i] = pib;
+  for (int v = 0; v < NV; ++v) W[(A_BTC + 5 * a + v) * n + i] = btc[v];
+  if (DISS) {
+    // forward viscous quantities at the face
+    double uL[3], uR[3];
+    for (int k = 0; k < DIM; ++k) {
+      uL[k] = W[ufield(DIM, k) * n + i];
+      uR[k] = W[ufield(DIM, k) * n + j];
+    }
+    const double TL = W[R_T * n + i], TR = W[R_T * n + j];
+    const double idn = P.idx[a];
+    double g[3][3];
+    for (int k = 0; k < DIM; ++k) g[dn][k] = (uR[k] - uL[k]) * idn;
+    int tang[2] = {-1, -1};
+    int nt = 0;
+    for (int t = 0; t < DIM; ++t) {
+      if (t == dn) continue;
+      tang[nt++] = t;
+      const int b = axis_of<DIM>(t);
+      const long long sb_ = astride(G, b);
+      const double qb = P.qidx[b];
+      for (int k = 0; k < DIM; ++k) {
+        const int uf = ufield(DIM, k);
+        g[t][k] = ((W[uf * n + i + sb_] - W[uf * n + i - sb_]) + (W[uf * n + j + sb_] - W[uf * n + j - sb_])) * qb;
+      }
+    }
+    double div = g[0][0];
+    for (int t = 1; t < DIM; ++t) div = div + g[t][t];
+    double tau[3], uf[3];
+    for (int k = 0; k < DIM; ++k) {
+      double tk = P.mu * (g[dn][k] + g[k][dn]);
+      if (k == dn) tk = tk + P.eta * div;
+      tau[k] = tk;
+      uf[k] = 0.5 * (uL[k] + uR[k]);
+    }
+    // reverse: G_m_k -= tau_k ; G_E = (G_E - W) + Q
+    double taub[3];
+    for (int k = 0; k < DIM; ++k) taub[k] = -Gb[1 + k];
+    const double Wb = -Gb[NV - 1];
+    const double Qb = Gb[NV - 1];
+    double uLb[3] = {0, 0, 0}, uRb[3] = {0, 0, 0};
+    double TLb = 0.0, TRb = 0.0;
+    // Q = -(kappa * ((TR - TL) * idn))
+    const double x = (TR - TL) * idn;
+    const double kappab = -x * Qb;
+    const double dTb = (-P.kappa * Qb) * idn;
+    TRb += dTb;
+    TLb -= dTb;
+    // W = sum_k tau_k uf_k
+    for (int k = 0; k < DIM; ++k) {
+      taub[k] += Wb * uf[k];
+      const double ufb = Wb * tau[k];
+      uLb[k] += 0.5 * ufb;
+      uRb[k] += 0.5 * ufb;
+    }
+    double gb[3][3];
+    for (int s = 0; s < 3; ++s)
+      for (int k = 0; k < 3; ++k) gb[s][k] = 0.0;
+    double mub = 0.0, etab = 0.0, divb = 0.0;
+    for (int k = 0; k < DIM; ++k) {
+      const double ssum = g[dn][k] + g[k][dn];
+      mub += ssum * taub[k];
+      const double sb2 = P.mu * taub[k];
+      gb[dn][k] += sb2;
+      gb[k][dn] += sb2;
+      if (k == dn) {
+        etab += div * taub[k];
+        divb += P.eta * taub[k];
+      }
+    }
+    mub += etab * (-2.0 / 3.0);
+    for (int t = 0; t < DIM; ++t) gb[t][t] += divb;
+    for (int k = 0; k < DIM; ++k) {
+      uRb[k] += gb[dn][k] * idn;
+      uLb[k] -= gb[dn][k] * idn;
+    }
+    for (int k = 0; k < 3; ++k) {
+      W[(A_VL + 4 * a + k) * n + i] = uLb[k];
+      W[(A_VR + 4 * a + k) * n + i] = uRb[k];
+    }
+    W[(A_VL + 4 * a + 3) * n + i] = TLb;
+    W[(A_VR + 4 * a + 3) * n + i] = TRb;
+    for (int s = 0; s < 2; ++s) {
+      const int t = tang[s];
+      W[(A_VT + 4 * a + 2 * s + 0) * n + i] = t >= 0 ? gb[t][dn] : 0.0;
+      W[(A_VT + 4 * a + 2 * s + 1) * n + i] = t >= 0 ? gb[t][t] : 0.0;
+    }
+    W[(A_PM + 2 * a + 0) * n + i] = mub;
+    W[(A_PM + 2 * a + 1) * n + i] = kappab;
+  }
+}
+
+// ------------------------------------------------- K3: acoustic cell^T -----
+template <int DIM>
+__global__ void k_adj_cell(Params P, RefGrid G, AdjIO io, double* __restrict__ W) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= G.npad) return;
+  constexpr int NV = DIM + 2;
+  int qx, qy, qz;
+  decode(G, i, qx, qy, qz);
+  if (!cell_range<DIM>(G, qx, qy, qz)) return;
+  const long long n = G.npad;
+  const double dt = *io.dt;
+  const double lamz = dt / P.dx[2];
+  double btb[NV];
+  for (int v = 0; v < NV; ++v) btb[v] = 0.0;
+  for (int t = 0; t < DIM; ++t) {
+    const int a = axis_of<DIM>(t);
+    // c as the left cell of face (a, c)
+    if (flux_range<DIM>(G, a, qx, qy, qz) && W[(R_WALL + a) * n + i] == 0.0 &&
+        W[(R_FACE + 4 * a) * n + i] >= 0.0)
+      for (int v = 0; v < NV; ++v) btb[v] += W[(A_BTC + 5 * a + v) * n + i];
+    // c as the right cell of face (a, c - e_a)
+    const long long m = i - astride(G, a);
+    const int mx = qx - (a == 0), my = qy - (a == 1), mz = qz - (a == 2);
+    if (flux_range<DIM>(G, a, mx, my, mz) && W[(R_WALL + a) * n + m] == 0.0 && !(W[(R_FACE + 4 * a) * n + m] >= 0.0))
+      for (int v = 0; v < NV; ++v) btb[v] += W[(A_BTC + 5 * a + v) * n + m];
+  }
+  const double iL = 1.0 / W[R_L * n + i];
+  double consb[NV], Ab[NV];
+  double Lb = 0.0;
+  for (int v = 0; v < NV; ++v) {
+    consb[v] = btb[v] * iL;
+    Ab[v] = -btb[v] * iL;
+    Lb += btb[v] * W[(R_BT + v) * n + i];
+  }
+  Lb = -Lb * iL;
+  // calE = E + rho Phi
+  consb[0] += phi_at(P, qz - 2) * consb[NV - 1];
+  double sbb = -lamz * Ab[DIM];  // A for the vertical momentum: lam_z ((Pi+ - Pi-) - S-bar)
+  if (interior_cell<DIM>(G, qx, qy, qz)) {
+    const long long c = (qx - 2) + (long long)P.nx * ((DIM == 3 ? qy - 2 : 0) + (long long)P.ny * (qz - 2));
+    sbb += lamz * io.lam1[c + DIM * P.ncell];  // + lam_z S-bar in the update of m_z
+  }
+  W[(A_CB + 0) * n + i] = Lb;
+  for (int k = 0; k < 3; ++k) W[(A_CB + 1 + k) * n + i] = k < DIM ? Ab[1 + k] : 0.0;
+  W[(A_CB + 4) * n + i] = Ab[NV - 1];
+  W[(A_CB + 5) * n + i] = sbb;
+  for (int v = 0; v < 5; ++v) W[(A_CONSB + v) * n + i] = v < NV ? consb[v] : 0.0;
+}
+
+// ------------------------------------------------------ K4: face solver^T --
+template <int DIM, bool LM>
+__global__ void k_adj_face(Params P, RefGrid G, int a, AdjIO io, double* __restrict__ W) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= G.npad) return;
+  int qx, qy, qz;
+  decode(G, i, qx, qy, qz);
+  if (qa_of(a, qx, qy, qz) + 1 >= Pa_of(G, a)) return;
+  const long long n = G.npad;
+  const long long j = i + astride(G, a);
+  const double dt = *io.dt;
+  const double lama = dt / P.dx[a];
+  const int dn = comp_of<DIM>(a);
+  const int f = R_FACE + 4 * a;
+  double usb = W[(A_FB + 4 * a + 0) * n + i];
+  double pib = W[(A_FB + 4 * a + 1) * n + i];
+  double Pb = 0.0, Sb = 0.0;
+  if (cell_range<DIM>(G, qx, qy, qz)) {
+    usb += lama * W[(A_CB + 0) * n + i];
+    pib += lama * W[(A_CB + 1 + dn) * n + i];
+    Pb += lama * W[(A_CB + 4) * n + i];
+    if (a == 2) Sb += 0.5 * W[(A_CB + 5) * n + i];
+  }
+  const int rx = qx + (a == 0), ry = qy + (a == 1), rz = qz + (a == 2);
+  if (cell_range<DIM>(G, rx, ry, rz)) {
+    usb -= lama * W[(A_CB + 0) * n + j];
+    pib -= lama * W[(A_CB + 1 + dn) * n + j];
+    Pb -= lama * W[(A_CB + 4) * n + j];
+    if (a == 2) Sb += 0.5 * W[(A_CB + 5) * n + j];
+  }
+  // forward face values
+  const double us = W[(f + 0) * n + i];
+  const double pi = W[(f + 1) * n + i];
+  const bool wall = W[(R_WALL + a) * n + i] != 0.0;
+  const int uf = ufield(DIM, dn);
+  const double rhoL = W[R_RHO * n + i], rhoR = W[R_RHO * n + j];
+  const double uL = W[uf * n + i], uR = W[uf * n + j];
+  const double pL = W[R_P * n + i], pR = W[R_P * n + j];
+  const double rcL = W[R_RC * n + i], rcR = W[R_RC * n + j];
+  const double ircL = W[R_IRC * n + i], ircR = W[R_IRC * n + j];
+  const double icL = W[R_IC * n + i], icR = W[R_IC * n + j];
+  const double aa = P.K * dmax2(rcL, rcR);
+  double theta = 1.0, ma = 0.0, cmin = 0.0;
+  if (LM) {
+    cmin = dmin2(icL, icR);
+    ma = fabs(us) * cmin;
+    theta = dmin2(ma, 1.0);
+  }
+  const double h = (0.5 * aa) * theta;
+  const double du = uR - uL;
+  double rLb = 0, rRb = 0, uLb = 0, uRb = 0, pLb = 0, pRb = 0, rcLb = 0, rcRb = 0, iLb = 0, iRb = 0, cLb = 0,
+         cRb = 0;
+  // P = Pi* u*
+  pib += Pb * us;
+  usb += Pb * pi;
+  // Pi* = 0.5 (pL + pR) - h (uR - uL)
+  pLb += 0.5 * pib;
+  pRb += 0.5 * pib;
+  const double hb = -pib * du;
+  const double dub = -pib * h;
+  uRb += dub;
+  uLb -= dub;
+  const double ab = 0.5 * theta * hb;
+  const double thetab = (0.5 * aa) * hb;
+  if (LM && !wall) {
+    const double mab = (ma <= 1.0) ? thetab : 0.0;
+    const double absb = mab * cmin;
+    const double cminb = mab * fabs(us);
+    usb += (us >= 0.0) ? absb : -absb;
+    if (icL <= icR)
+      cLb += cminb;
+    else
+      cRb += cminb;
+  }
+  if (!wall) {
+    // u* = 0.5 (uL + uR) - ((pR - pL) - S) * (hK * min(irc))
+    const double m = P.hK * dmin2(ircL, ircR);
+    const double d1 = (pR - pL) - W[(f + 3) * n + i];
+    uLb += 0.5 * usb;
+    uRb += 0.5 * usb;
+    const double d1b = -usb * m;
+    const double mb = -usb * d1;
+    pRb += d1b;
+    pLb -= d1b;
+    Sb -= d1b;
+    if (ircL <= ircR)
+      iLb += P.hK * mb;
+    else
+      iRb += P.hK * mb;
+  }
+  if (a == 2) {
+    // S = (-0.5 (rhoL + rhoR)) * dphi
+    const double dphi = phi_at(P, qz + 1 - 2) - phi_at(P, qz - 2);
+    const double rb = -0.5 * (Sb * dphi);
+    rLb += rb;
+    rRb += rb;
+  }
+  // a = K max(rcL, rcR)
+  if (rcL >= rcR)
+    rcLb += P.K * ab;
+  else
+    rcRb += P.K * ab;
+  const int fl = A_FPL + 6 * a, fr = A_FPR + 6 * a;
+  W[(fl + 0) * n + i] = rLb;
+  W[(fl + 1) * n + i] = uLb;
+  W[(fl + 2) * n + i] = pLb;
+  W[(fl + 3) * n + i] = rcLb;
+  W[(fl + 4) * n + i] = iLb;
+  W[(fl + 5) * n + i] = cLb;
+  W[(fr + 0) * n + i] = rRb;
+  W[(fr + 1) * n + i] = uRb;
+  W[(fr + 2) * n + i] = pRb;
+  W[(fr + 3) * n + i] = rcRb;
+  W[(fr + 4) * n + i] = iRb;
+  W[(fr + 5) * n + i] = cRb;
+}
+
+// ---------------------------------------------- K5: primitive gather ------
+template <int DIM, bool DISS>
+__global__ void k_adj_pgather(Params P, RefGrid G, double* __restrict__ W) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= G.npad) return;
+  int qx, qy, qz;
+  decode(G, i, qx, qy, qz);
+  const long long n = G.npad;
+  double rho = 0, u[3] = {0, 0, 0}, p = 0, rc = 0, irc = 0, ic = 0, T = 0;
+  for (int t = 0; t < DIM; ++t) {
+    const int a = axis_of<DIM>(t);
+    const int qa = qa_of(a, qx, qy, qz);
+    const int Pa = Pa_of(G, a);
+    const long long sa = astride(G, a);
+    if (qa + 1 < Pa) {  // c is the left cell of face (a, c)
+      const int fl = A_FPL + 6 * a;
+      rho += W[(fl + 0) * n + i];
+      u[t] += W[(fl + 1) * n + i];
+      p += W[(fl + 2) * n + i];
+      rc += W[(fl + 3) * n + i];
+      irc += W[(fl + 4) * n + i];
+      ic += W[(fl + 5) * n + i];
+    }
+    if (qa >= 1) {  // c is the right cell of face (a, c - e_a)
+      const int fr = A_FPR + 6 * a;
+      const long long m = i - sa;
+      rho += W[(fr + 0) * n + m];
+      u[t] += W[(fr + 1) * n + m];
+      p += W[(fr + 2) * n + m];
+      rc += W[(fr + 3) * n + m];
+      irc += W[(fr + 4) * n + m];
+      ic += W[(fr + 5) * n + m];
+    }
+    if (DISS) {
+      if (flux_range<DIM>(G, a, qx, qy, qz)) {
+        for (int k = 0; k < DIM; ++k) u[k] += W[(A_VL + 4 * a + k) * n + i];
+        T += W[(A_VL + 4 * a + 3) * n + i];
+      }
+      const int mx = qx - (a == 0), my = qy - (a == 1), mz = qz - (a == 2);
+      if (flux_range<DIM>(G, a, mx, my, mz)) {
+        const long long m = i - sa;
+        for (int k = 0; k < DIM; ++k) u[k] += W[(A_VR + 4 * a + k) * n + m];
+        T += W[(A_VR + 4 * a + 3) * n + m];
+      }
+      // tangential gradients of faces along a: g[tb][k] with tb != t the
+      // other active axes; the face stores, per tangential slot, the adjoint
+      // of g[tb][t] (k = t) and g[tb][tb] (k = tb)
+      int s = 0;
+      for (int tb = 0; tb < DIM; ++tb) {
+        if (tb == t) continue;
+        const int b = axis_of<DIM>(tb);
+        const long long sb_ = astride(G, b);
+        const double qb = P.qidx[b];
+        // faces whose L, L+e_b, L-e_b, R+e_b, R-e_b touch c:
+        //  L = c - e_b (c = L + e_b, +), L = c + e_b (c = L - e_b, -),
+        //  L = c - e_b - e_a (c = R + e_b, +), L = c + e_b - e_a (c = R - e_b, -)
+        const int off[4][2] = {{-1, 0}, {+1, 0}, {-1, -1}, {+1, -1}};
+        const double sgn[4] = {1.0, -1.0, 1.0, -1.0};
+        for (int w = 0; w < 4; ++w) {
+          const int ob = off[w][0], oa = off[w][1];
+          int fx = qx, fy = qy, fz = qz;
+          if (b == 0) fx += ob; else if (b == 1) fy += ob; else fz += ob;
+          if (a == 0) fx += oa; else if (a == 1) fy += oa; else fz += oa;
+          if (fx < 0 || fx >= G.Px || fy < 0 || fy >= G.Py || fz < 0 || fz >= G.Pz) continue;
+          if (!flux_range<DIM>(G, a, fx, fy, fz)) continue;
+          const long long fi = G.pad(fx, fy, fz);
+          const double g_dir = W[(A_VT + 4 * a + 2 * s + 0) * n + fi];  // adjoint of g[tb][t]
+          const double g_tan = W[(A_VT + 4 * a + 2 * s + 1) * n + fi];  // adjoint of g[tb][tb]
+          u[t] += sgn[w] * qb * g_dir;
+          u[tb] += sgn[w] * qb * g_tan;
+        }
+        (void)sb_;
+        ++s;
+      }
+    }
+  }
+  W[(A_PB + 0) * n + i] = rho;
+  W[(A_PB + 1) * n + i] = u[0];
+  W[(A_PB + 2) * n + i] = u[1];
+  W[(A_PB + 3) * n + i] = u[2];
+  W[(A_PB + 4) * n + i] = p;
+  W[(A_PB + 5) * n + i] = rc;
+  W[(A_PB + 6) * n + i] = irc;
+  W[(A_PB + 7) * n + i] = ic;
+  W[(A_PB + 8) * n + i] = T;
+}
+
+// ------------------------------------- K6: (wall ghost + primitives)^T -----
+template <int DIM>
+__device__ void ghost_reverse(const Params& P, const double* W, long long n, long long gi, long long ci, int side,
+                              double& rho_b, double* u_b, double& T_b) {
+  // forward ghost values (stored at the ghost position) and interior values
+  const double gr = W[R_R * n + gi], gc = W[R_C * n + gi], gic = W[R_IC * n + gi], grho = W[R_RHO * n + gi];
+  const double gp = W[R_P * n + gi], Tg = W[R_T * n + gi];
+  const double Ti = W[R_T * n + ci], rhoi = W[R_RHO * n + ci];
+  const double dphi = (side == 0) ? phi_at(P, -1) - phi_at(P, 0) : phi_at(P, P.nz) - phi_at(P, P.nz - 1);
+  const double hd = 0.5 * dphi;
+  const double den = Tg + hd;
+  const double b_rho = W[(A_PB + 0) * n + gi], b_p = W[(A_PB + 4) * n + gi], b_rc = W[(A_PB + 5) * n + gi];
+  const double b_irc = W[(A_PB + 6) * n + gi], b_ic = W[(A_PB + 7) * n + gi], b_T = W[(A_PB + 8) * n + gi];
+  double rb = b_irc * gic;
+  const double icb = b_ic + b_irc * gr;
+  double cb = -icb * gic * gic;
+  double rhob = b_rho + b_rc * gc;
+  cb += b_rc * grho;
+  const double Xb = cb * 0.5 / gc;
+  double pb = b_p + Xb * P.gamma * gr;
+  rb += Xb * P.gamma * gp;
+  rhob += -rb * gr * gr;
+  rhob += pb * Tg;
+  double Tgb = b_T + pb * grho;
+  const double numb = rhob / den;
+  const double denb = -rhob * grho / den;
+  Tgb += denb;
+  rho_b += numb * (Ti - hd);
+  double Tib = numb * rhoi;
+  Tib += (P.thermal[side] == TH_FIXED) ? -Tgb : Tgb;
+  T_b += Tib;
+  for (int k = 0; k < DIM; ++k) {
+    const double ub = W[(A_PB + 1 + k) * n + gi];
+    const bool flip = P.noslip ? true : (k == DIM - 1);
+    u_b[k] += flip ? -ub : ub;
+  }
+}
+
+template <int DIM>
+__global__ void k_adj_prim(Params P, RefGrid G, double* __restrict__ W) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= G.npad) return;
+  constexpr int NV = DIM + 2;
+  int qx, qy, qz;
+  decode(G, i, qx, qy, qz);
+  const long long n = G.npad;
+  const bool wlo = P.bcz[0] == BC_WALL, whi = P.bcz[1] == BC_WALL;
+  const bool ghost = (qz < 2 && wlo) || (qz >= G.Pz - 2 && whi);
+  if (ghost) {
+    for (int v = 0; v < 5; ++v) W[(A_UB + v) * n + i] = 0.0;
+    return;
+  }
+  double rho_b = W[(A_PB + 0) * n + i];
+  double u_b[3];
+  for (int k = 0; k < DIM; ++k) u_b[k] = W[(A_PB + 1 + k) * n + i];
+  double p_b = W[(A_PB + 4) * n + i];
+  const double rc_b = W[(A_PB + 5) * n + i];
+  const double irc_b = W[(A_PB + 6) * n + i];
+  const double ic_b = W[(A_PB + 7) * n + i];
+  double T_b = W[(A_PB + 8) * n + i];
+  // wall ghosts built from this cell (both ghost layers)
+  const long long sz = astride(G, 2);
+  if (wlo && qz == 2) {
+    ghost_reverse<DIM>(P, W, n, i - sz, i, 0, rho_b, u_b, T_b);
+    ghost_reverse<DIM>(P, W, n, i - 2 * sz, i, 0, rho_b, u_b, T_b);
+  }
+  if (whi && qz == G.Pz - 3) {
+    ghost_reverse<DIM>(P, W, n, i + sz, i, 1, rho_b, u_b, T_b);
+    ghost_reverse<DIM>(P, W, n, i + 2 * sz, i, 1, rho_b, u_b, T_b);
+  }
+  // primitives of this cell from its conserved values
+  const double r = W[R_R * n + i], c = W[R_C * n + i], ic = W[R_IC * n + i], p = W[R_P * n + i];
+  const double rho = W[R_RHO * n + i];
+  double rb = irc_b * ic;
+  const double icb = ic_b + irc_b * r;
+  double cb = -icb * ic * ic;
+  rho_b += rc_b * c;
+  cb += rc_b * rho;
+  p_b += T_b * r;
+  rb += T_b * p;
+  const double Xb = cb * 0.5 / c;
+  p_b += Xb * P.gamma * r;
+  rb += Xb * P.gamma * p;
+  const double Eb = P.gm1 * p_b;
+  const double kinb = -P.gm1 * p_b;
+  double mb[3];
+  for (int k = 0; k < DIM; ++k) {
+    const double uk = W[ufield(DIM, k) * n + i];
+    const double mk = W[(R_CONS + 1 + k) * n + i];
+    mb[k] = 0.5 * kinb * uk;
+    const double ubt = u_b[k] + 0.5 * kinb * mk;
+    mb[k] += ubt * r;
+    rb += ubt * mk;
+  }
+  rho_b += -rb * r * r;
+  double Ub[NV];
+  Ub[0] = rho_b;
+  for (int k = 0; k < DIM; ++k) Ub[1 + k] = mb[k];
+  Ub[NV - 1] = Eb;
+  for (int v = 0; v < NV; ++v) Ub[v] += W[(A_CONSB + v) * n + i];
+  for (int v = 0; v < 5; ++v) W[(A_UB + v) * n + i] = v < NV ? Ub[v] : 0.0;
+}
+
+// ------------------------------------------------ K7: fold onto interior ----
+__device__ __forceinline__ int images(int ia, int n, const int* bc, bool wallaxis, int* out) {
+  int k = 0;
+  out[k++] = ia + 2;
+  if (wallaxis) return k;
+  const int ghosts[4] = {0, 1, n + 2, n + 3};
+  for (int g = 0; g < 4; ++g) {
+    const int q = ghosts[g];
+    if (resolve_lat(q - 2, n, bc) == ia) out[k++] = q;
+  }
+  return k;
+}
+
+template <int DIM>
+__global__ void k_adj_fold(Params P, RefGrid G, AdjIO io, const double* __restrict__ W) {
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= P.ncell) return;
+  constexpr int NV = DIM + 2;
+  const long long n = G.npad;
+  const int x = (int)(c % P.nx);
+  const long long r = c / P.nx;
+  const int y = (int)(r % P.ny);
+  const int z = (int)(r / P.ny);
+  int ix[5], iy[5], iz[5];
+  const int nxi = images(x, P.nx, P.bcx, false, ix);
+  int nyi = 1;
+  iy[0] = 0;
+  if (DIM == 3) nyi = images(y, P.ny, P.bcy, false, iy);
+  const bool zw = P.bcz[0] == BC_WALL;
+  const int nzi = images(z, P.nz, P.bcz, zw, iz);
+  double acc[NV];
+  for (int v = 0; v < NV; ++v) acc[v] = io.lam0[c + v * P.ncell];
+  for (int a = 0; a < nzi; ++a)
+    for (int b = 0; b < nyi; ++b)
+      for (int d = 0; d < nxi; ++d) {
+        const long long q = G.pad(ix[d], iy[b], iz[a]);
+        for (int v = 0; v < NV; ++v) acc[v] += W[(A_UB + v) * n + q];
+      }
+  for (int v = 0; v < NV; ++v) io.lam0[c + v * P.ncell] = acc[v];
+}
+
+// ----------------------------------------------- K8: parameter reduction ----
+__global__ void __launch_bounds__(256) k_adj_params(RefGrid G, const double* __restrict__ W, double* partial) {
+  __shared__ double sh[2][256];
+  double s0 = 0.0, s1 = 0.0;
+  const long long n = G.npad;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    for (int a = 0; a < 3; ++a) {
+      s0 += W[(A_PM + 2 * a + 0) * n + i];
+      s1 += W[(A_PM + 2 * a + 1) * n + i];
+    }
+  sh[0][threadIdx.x] = s0;
+  sh[1][threadIdx.x] = s1;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      sh[0][threadIdx.x] += sh[0][threadIdx.x + w];
+      sh[1][threadIdx.x] += sh[1][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    partial[2 * blockIdx.x] = sh[0][0];
+    partial[2 * blockIdx.x + 1] = sh[1][0];
+  }
+}
+
+__global__ void k_adj_params_final(int nb, const double* partial, double* pgrad) {
+  if (threadIdx.x == 0) {
+    double a = 0.0, b = 0.0;
+    for (int k = 0; k < nb; ++k) {
+      a += partial[2 * k];
+      b += partial[2 * k + 1];
+    }
+    pgrad[0] += a;
+    pgrad[1] += b;
+  }
+}
+
+template <int DIM>
+static hipError_t adjoint_t(const Params& P, const double* Un, const double* lam1, double* lam0, const double* d_dt,
+                            double* pgrad, void* wadj, hipStream_t s) {
+  RefGrid G = make_grid(P);
+  double* W = (double*)wadj;
+  const int bs = 256;
+  const unsigned nb = (unsigned)((G.npad + bs - 1) / bs);
+  hipError_t e = launch_ref_forward(P, Un, wadj, d_dt, s);
+  if (e != hipSuccess) return e;
+  {
+    const long long cnt = (long long)(A_NFIELD - R_NFIELD) * G.npad;
+    long long blocks = (cnt + bs - 1) / bs;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_adj_zero, dim3((unsigned)blocks), dim3(bs), 0, s, W, (long long)R_NFIELD * G.npad, cnt);
+  }
+  AdjIO io{lam1, lam0, d_dt, pgrad};
+  hipLaunchKernelGGL(k_adj_update<DIM>, dim3(nb), dim3(bs), 0, s, P, G, io, W);
+  for (int a = 0; a < 3; ++a) {
+    if (DIM == 2 && a == 1) continue;
+    if (P.diss)
+      hipLaunchKernelGGL((k_adj_flux<DIM, true>), dim3(nb), dim3(bs), 0, s, P, G, a, W);
+    else
+      hipLaunchKernelGGL((k_adj_flux<DIM, false>), dim3(nb), dim3(bs), 0, s, P, G, a, W);
+  }
+  hipLaunchKernelGGL(k_adj_cell<DIM>, dim3(nb), dim3(bs), 0, s, P, G, io, W);
+  for (int a = 0; a < 3; ++a) {
+    if (DIM == 2 && a == 1) continue;
+    if (P.low_mach)
+      hipLaunchKernelGGL((k_adj_face<DIM, true>), dim3(nb), dim3(bs), 0, s, P, G, a, io, W);
+    else
+      hipLaunchKernelGGL((k_adj_face<DIM, false>), dim3(nb), dim3(bs), 0, s, P, G, a, io, W);
+  }
+  if (P.diss)
+    hipLaunchKernelGGL((k_adj_pgather<DIM, true>), dim3(nb), dim3(bs), 0, s, P, G, W);
+  else
+    hipLaunchKernelGGL((k_adj_pgather<DIM, false>), dim3(nb), dim3(bs), 0, s, P, G, W);
+  hipLaunchKernelGGL(k_adj_prim<DIM>, dim3(nb), dim3(bs), 0, s, P, G, W);
+  const unsigned nc = (unsigned)((P.ncell + bs - 1) / bs);
+  hipLaunchKernelGGL(k_adj_fold<DIM>, dim3(nc), dim3(bs), 0, s, P, G, io, W);
+  if (P.diss && pgrad) {
+    double* partial = W + (size_t)A_NFIELD * G.npad;  // 4096 bytes after the fields: 256 blocks x 2
+    const int npb = 256;
+    hipLaunchKernelGGL(k_adj_params, dim3(npb), dim3(256), 0, s, G, W, partial);
+    hipLaunchKernelGGL(k_adj_params_final, dim3(1), dim3(64), 0, s, npb, partial, pgrad);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_step_adjoint(const Params& P, const double* Un, const double* lam_np1, double* lam_n,
+                               const double* d_dt, double* d_param_grad, void* wadj, hipStream_t s) {
+  return P.dim == 3 ? adjoint_t<3>(P, Un, lam_np1, lam_n, d_dt, d_param_grad, wadj, s)
+                    : adjoint_t<2>(P, Un, lam_np1, lam_n, d_dt, d_param_grad, wadj, s);
+}
+
+}  // namespace ars

@@ -15,13 +15,6 @@
 #include "ars_dev.h"
 #include "ars_internal.h"
 
-struct ars_ctx {
-  ars_config cfg;
-  ars::Params P;
-  ars::TileShape ts;
-  size_t len;
-};
-
 namespace {
 
 constexpr size_t CTL_BYTES = 256;
@@ -99,6 +92,8 @@ ars::Params derive(const ars_config* c) {
 ars::Control* ctl_of(void* w) { return (ars::Control*)w; }
 
 }  // namespace
+
+ars::Params ars::params_of(const ars_config* c) { return derive(c); }
 
 extern "C" {
 
@@ -194,6 +189,20 @@ int ars_set_zchunk(ars_ctx* c, int zchunk) {
 }
 
 int ars_get_zchunk(const ars_ctx* c) { return c ? c->ts.zchunk : -1; }
+
+int ars_set_tiling(ars_ctx* c, int zchunk, int wg_per_cu) {
+  if (!c || zchunk < 1 || wg_per_cu < 0 || wg_per_cu > 32) return ARS_EINVAL;
+  c->ts.zchunk = zchunk;
+  c->ts.wg_per_cu = wg_per_cu;
+  return ARS_OK;
+}
+
+int ars_get_tiling(const ars_ctx* c, int* zchunk, int* wg_per_cu) {
+  if (!c) return ARS_EINVAL;
+  if (zchunk) *zchunk = c->ts.zchunk;
+  if (wg_per_cu) *wg_per_cu = c->ts.wg_per_cu;
+  return ARS_OK;
+}
 
 int ars_workspace_init(ars_ctx* c, void* d_work, void* stream) {
   if (!c || !d_work) return ARS_EINVAL;
@@ -410,6 +419,24 @@ int ars_step_ref(ars_ctx* ctx, double* d_state, double* d_tmp, void* d_work, voi
       return ARS_EDEVICE;
   }
   return ARS_OK;
+}
+
+size_t ars_workspace_bytes_adjoint(const ars_ctx* c) { return c ? ars::adjoint_workspace_bytes(c->P) : 0; }
+
+int ars_step_adjoint(ars_ctx* ctx, const double* d_state_n, const double* d_lam_np1, double* d_lam_n,
+                     const double* d_dt, double* d_param_grad, void* d_work_adj, void* stream) {
+  if (!ctx || !d_state_n || !d_lam_np1 || !d_lam_n || !d_dt || !d_work_adj || d_lam_n == d_lam_np1)
+    return ARS_EINVAL;
+  return check(ars::launch_step_adjoint(ctx->P, d_state_n, d_lam_np1, d_lam_n, d_dt, d_param_grad, d_work_adj,
+                                        (hipStream_t)stream));
+}
+
+int ars_kinetic_energy(ars_ctx* ctx, const double* d_state, double* d_grad, double* d_ke, void* d_work,
+                       void* stream) {
+  if (!ctx || !d_state || !d_ke || !d_work) return ARS_EINVAL;
+  char* w = (char*)d_work;
+  double* partials = (double*)(w + CTL_BYTES);
+  return check(ars::launch_ke(ctx->P, d_state, d_grad, partials, d_ke, (hipStream_t)stream));
 }
 
 int ars_fault(ars_ctx* ctx, void* d_work, int64_t* fault_cell, void* stream) {

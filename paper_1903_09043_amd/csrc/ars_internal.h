@@ -2,6 +2,9 @@
 // units (not part of the public ABI).
 #pragma once
 #include <hip/hip_runtime.h>
+#include <vector>
+
+#include "../../include/ars.h"
 #include "ars_dev.h"
 
 namespace ars {
@@ -31,6 +34,21 @@ hipError_t launch_step_fused(const Params& P, const double* Uin, double* Uout, S
 size_t ref_workspace_bytes(const Params& P);
 hipError_t launch_step_ref(const Params& P, const double* Uin, double* Uout, void* wref, const double* d_dt,
                            Control* ctl, hipStream_t s);
+// forward phases only (primitives, faces, acoustic cell values) into wref
+hipError_t launch_ref_forward(const Params& P, const double* Uin, void* wref, const double* d_dt, hipStream_t s);
+
+// Adjoint step (ars_adjoint.hip).
+size_t adjoint_workspace_bytes(const Params& P);
+hipError_t launch_step_adjoint(const Params& P, const double* Un, const double* lam_np1, double* lam_n,
+                               const double* d_dt, double* d_param_grad, void* wadj, hipStream_t s);
+
+// Derived kernel parameters of a validated configuration (ars_api.hip).
+Params params_of(const ars_config* c);
+
+// Batched problems (ars_batch.hip): x segments of one instance and the
+// cost-model vertical chunk count for `rows` segments per workgroup.
+int batch_segments(const Params& P);
+int batch_default_zc(const Params& P, int rows);
 
 // Reductions (ars_reduce.hip).
 hipError_t launch_rate_reduce(const Params& P, const double* U, unsigned long long* slot, hipStream_t s);
@@ -38,5 +56,27 @@ hipError_t launch_ctl_prep(Control* ctl, int mode, hipStream_t s);
 hipError_t launch_dt_finish(const Params& P, Control* ctl, int slot, double* d_dt, hipStream_t s);
 size_t diag_partial_bytes(const Params& P);
 hipError_t launch_diag(const Params& P, const double* U, double* partials, double* out, hipStream_t s);
+hipError_t launch_ke(const Params& P, const double* U, double* grad, double* partials, double* out, hipStream_t s);
 
 }  // namespace ars
+
+struct ars_ctx {
+  ars_config cfg;
+  ars::Params P;
+  ars::TileShape ts;
+  size_t len;
+};
+
+struct ars_batch {
+  int n;
+  int rows;                   // row segments per workgroup (4 or 8)
+  std::vector<ars_config> cfg;
+  std::vector<ars::Params> P;
+  std::vector<int> zc;        // vertical chunks per instance
+  std::vector<size_t> off;    // state offsets (doubles)
+  std::vector<int> order;     // largest first
+  size_t total;
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+  bool captured;
+};

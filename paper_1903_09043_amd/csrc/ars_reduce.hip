@@ -158,6 +158,64 @@ __global__ void __launch_bounds__(256) k_diag_final(int nblocks, const double* p
   }
 }
 
+// ------------------------------------------------- kinetic-energy objective
+// KE = sum_cells (1/2) sum_k m_k u_k dV; optional gradient dKE/dU:
+// d/drho = -|u|^2 dV / 2, d/dm_k = u_k dV, d/dE = 0.
+template <int DIM>
+__global__ void __launch_bounds__(256) k_ke(Params P, double dV, const double* __restrict__ U,
+                                           double* __restrict__ grad, double* partials) {
+  constexpr int NV = DIM + 2;
+  __shared__ double sh[256];
+  double acc = 0.0;
+  for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < P.ncell;
+       c += (long long)gridDim.x * blockDim.x) {
+    const double rho = U[c];
+    const double r = 1.0 / rho;
+    double kin = 0.0, uu = 0.0;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+      const double m = U[c + (1 + k) * P.ncell];
+      const double u = m * r;
+      kin = (k == 0) ? m * u : kin + m * u;
+      uu = (k == 0) ? u * u : uu + u * u;
+      if (grad) grad[c + (1 + k) * P.ncell] = u * dV;
+    }
+    acc += 0.5 * kin;
+    if (grad) {
+      grad[c] = -0.5 * uu * dV;
+      grad[c + (NV - 1) * P.ncell] = 0.0;
+    }
+  }
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partials[blockIdx.x] = sh[0];
+}
+
+__global__ void k_ke_final(int nb, double dV, const double* partials, double* out) {
+  if (threadIdx.x == 0) {
+    double a = 0.0;
+    for (int b = 0; b < nb; ++b) a += partials[b];
+    *out = a * dV;
+  }
+}
+
+hipError_t launch_ke(const Params& P, const double* U, double* grad, double* partials, double* out, hipStream_t s) {
+  double dV = P.dx[0] * P.dx[2];
+  if (P.dim == 3) dV = P.dx[0] * P.dx[1] * P.dx[2];
+  long long nb = (P.ncell + 255) / 256;
+  if (nb > DIAG_NB) nb = DIAG_NB;
+  if (P.dim == 3)
+    hipLaunchKernelGGL(k_ke<3>, dim3((unsigned)nb), dim3(256), 0, s, P, dV, U, grad, partials);
+  else
+    hipLaunchKernelGGL(k_ke<2>, dim3((unsigned)nb), dim3(256), 0, s, P, dV, U, grad, partials);
+  hipLaunchKernelGGL(k_ke_final, dim3(1), dim3(64), 0, s, (int)nb, dV, partials, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_diag(const Params& P, const double* U, double* partials, double* out, hipStream_t s) {
   long long nb = (P.ncell + 255) / 256;
   if (nb > DIAG_NB) nb = DIAG_NB;

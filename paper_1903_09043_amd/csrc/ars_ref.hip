@@ -6,54 +6,13 @@
 // fused kernels bit for bit (and to expose the intermediates to tests).
 #include "ars_dev.h"
 #include "ars_internal.h"
+#include "ars_ref.h"
 
 namespace ars {
-
-struct RefGrid {
-  int D;
-  int Px, Py, Pz;      // padded extents (Py = 1 in 2D)
-  long long npad;
-  __host__ __device__ long long pad(int qx, int qy, int qz) const {
-    return qx + (long long)Px * (qy + (long long)Py * qz);
-  }
-};
-
-// Field offsets (in units of npad doubles) inside the reference workspace.
-enum {
-  R_RHO = 0, R_R, R_UX, R_UY, R_UZ, R_P, R_C, R_RC, R_T, R_IC, R_IRC,  // primitives (11)
-  R_CONS = 11,                                                         // 5 conserved
-  R_FACE = 16,                                                         // 3 axes x (us, pi, P, S)
-  R_WALL = 28,                                                         // 3 axes wall flags (as doubles)
-  R_L = 31, R_SB = 32, R_BT = 33,                                      // L, S-bar, 5 b~
-  R_G = 38,                                                            // 3 axes x 5 fluxes
-  R_NFIELD = 53
-};
-
-static RefGrid make_grid(const Params& P) {
-  RefGrid G;
-  G.D = P.dim;
-  G.Px = P.nx + 4;
-  G.Py = (P.dim == 3) ? P.ny + 4 : 1;
-  G.Pz = P.nz + 4;
-  G.npad = (long long)G.Px * G.Py * G.Pz;
-  return G;
-}
 
 size_t ref_workspace_bytes(const Params& P) {
   RefGrid G = make_grid(P);
   return (size_t)R_NFIELD * (size_t)G.npad * sizeof(double);
-}
-
-__device__ __forceinline__ void decode(const RefGrid& G, long long i, int& qx, int& qy, int& qz) {
-  qx = (int)(i % G.Px);
-  long long r = i / G.Px;
-  qy = (int)(r % G.Py);
-  qz = (int)(r / G.Py);
-}
-
-// axis helpers: a = 0 (x), 1 (y, 3D only), 2 (vertical)
-__device__ __forceinline__ long long astride(const RefGrid& G, int a) {
-  return a == 0 ? 1 : (a == 1 ? (long long)G.Px : (long long)G.Px * G.Py);
 }
 
 template <int DIM>
@@ -105,8 +64,6 @@ __global__ void k_ref_prim(Params P, RefGrid G, const double* __restrict__ U, do
   }
 }
 
-// velocity component k (0..DIM-1) -> field
-__device__ __forceinline__ int ufield(int DIM, int k) { return k == DIM - 1 ? R_UZ : (k == 0 ? R_UX : R_UY); }
 
 template <int DIM, bool LM>
 __global__ void k_ref_face(Params P, RefGrid G, int a, double* __restrict__ W) {
@@ -339,6 +296,28 @@ static hipError_t ref_t(const Params& P, const double* Uin, double* Uout, void* 
   const unsigned nc = (unsigned)((P.ncell + bs - 1) / bs);
   hipLaunchKernelGGL(k_ref_update<DIM>, dim3(nc), dim3(bs), 0, s, P, G, d_dt, W, Uout, ctl);
   return hipGetLastError();
+}
+
+template <int DIM>
+static hipError_t ref_forward_t(const Params& P, const double* Uin, void* wref, const double* d_dt, hipStream_t s) {
+  RefGrid G = make_grid(P);
+  double* W = (double*)wref;
+  const int bs = 256;
+  const unsigned nb = (unsigned)((G.npad + bs - 1) / bs);
+  hipLaunchKernelGGL(k_ref_prim<DIM>, dim3(nb), dim3(bs), 0, s, P, G, Uin, W);
+  for (int a = 0; a < 3; ++a) {
+    if (DIM == 2 && a == 1) continue;
+    if (P.low_mach)
+      hipLaunchKernelGGL((k_ref_face<DIM, true>), dim3(nb), dim3(bs), 0, s, P, G, a, W);
+    else
+      hipLaunchKernelGGL((k_ref_face<DIM, false>), dim3(nb), dim3(bs), 0, s, P, G, a, W);
+  }
+  hipLaunchKernelGGL(k_ref_cell<DIM>, dim3(nb), dim3(bs), 0, s, P, G, d_dt, W);
+  return hipGetLastError();
+}
+
+hipError_t launch_ref_forward(const Params& P, const double* Uin, void* wref, const double* d_dt, hipStream_t s) {
+  return P.dim == 3 ? ref_forward_t<3>(P, Uin, wref, d_dt, s) : ref_forward_t<2>(P, Uin, wref, d_dt, s);
 }
 
 hipError_t launch_step_ref(const Params& P, const double* Uin, double* Uout, void* wref, const double* d_dt,

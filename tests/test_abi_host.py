@@ -27,7 +27,7 @@ def test_library_exports_every_declared_symbol():
     for s in syms:
         assert hasattr(L, s), s
     bound = {name for name, _, _ in A.SIGNATURES}
-    assert set(syms) <= bound | {"ars_step_adjoint", "ars_batch_create"} or set(syms) <= bound, set(syms) - bound
+    assert set(syms) <= bound, set(syms) - bound
 
 
 def test_strerror():
@@ -100,3 +100,38 @@ def test_workloads_transport_coefficients():
     ras = [W.ra_pr_to_mu_kappa(1.0, 1.0)[0] / c["mu"] for c, *_ in insts]
     ras = np.array(ras) ** 2
     assert ras.min() >= 5e2 * (1 - 1e-9) and ras.max() <= 5e3 * (1 + 1e-9)
+
+
+def test_batch_host_side():
+    """ars_batch_create / tiling / layout need no GPU: sizes, offsets,
+    rejection of 3D and invalid instances, tiling checks."""
+    import ctypes as C
+    L = A.lib()
+    cfgs = [W.rb([64, 32], [2.0, 1.0])[0], W.rb([20, 12], [2.0, 1.0])[0], W.gresho(n=48)[0]]
+
+    def create(cs):
+        arr = (A.ArsConfig * len(cs))(*[A.make_config(c) for c in cs])
+        h = C.c_void_p()
+        return L.ars_batch_create(len(cs), arr, C.byref(h)), h
+
+    rc, h = create(cfgs)
+    assert rc == 0
+    try:
+        cells = [64 * 32, 20 * 12, 48 * 48]
+        assert L.ars_batch_state_len(h) == 4 * sum(cells)
+        assert [L.ars_batch_state_offset(h, k) for k in range(3)] == [0, 4 * cells[0], 4 * (cells[0] + cells[1])]
+        assert L.ars_batch_table_bytes(h) > 0
+        r = C.c_int()
+        z = (C.c_int * 3)()
+        assert L.ars_batch_get_tiling(h, C.byref(r), z) == 0 and r.value == 4
+        assert all(cfg["n"][1] % v == 0 for cfg, v in zip(cfgs, z))
+        assert L.ars_batch_set_tiling(h, 6, None) == A.EINVAL
+        assert L.ars_batch_set_tiling(h, 8, (C.c_int * 3)(2, 5, 1)) == A.EINVAL  # 5 does not divide 12
+        assert L.ars_batch_set_tiling(h, 8, (C.c_int * 3)(2, 4, 16)) == 0
+        assert L.ars_batch_get_tiling(h, C.byref(r), z) == 0 and r.value == 8 and list(z) == [2, 4, 16]
+        assert L.ars_batch_replay(h, None) == A.EINVAL  # nothing captured
+    finally:
+        L.ars_batch_destroy(h)
+    assert create(cfgs + [W.rb([8, 8, 8], [1.0, 1.0, 1.0])[0]])[0] == A.EUNSUPPORTED
+    assert create([dict(cfgs[0], cfl=0.0)])[0] == A.EINVAL
+    assert L.ars_batch_create(0, None, C.byref(C.c_void_p())) == A.EINVAL

@@ -1,0 +1,105 @@
+"""Gradient of a convection run through torch.autograd (run on an MI355X).
+
+J = kinetic energy after N steps of the 3D Rayleigh-Benard layer from the
+base state heated by dT0; gradient w.r.t. dT0, mu, kappa (and Ra through the
+(Ra, Pr) -> (mu, kappa) map) by the adjoint step with binomial
+checkpointing.  Checks: checkpointed = all-states-stored gradient bit for
+bit; central differences at the frozen time-step schedule.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1903_09043_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def T():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def make_problem(T, slots, nsteps=12, n=(16, 12, 10), Ra=2e4, dt_sched=None):
+    from paper_1903_09043_amd.adjoint import RBProblem
+    cfg, prob, prm, seed = W.rb(list(n), [1.0, 1.0, 1.0], Ra=Ra, seed=0, amp=0.0)
+    rng = np.random.default_rng(5)
+    u0 = 0.1 * rng.standard_normal((3,) + tuple(reversed(n)))
+    return RBProblem(cfg, prob, prm, nsteps, slots, u0=u0, dt_sched=dt_sched), cfg
+
+
+def test_checkpointed_gradient_equals_store_all(T):
+    from paper_1903_09043_amd.adjoint import rb_kinetic_energy
+    grads = []
+    for slots in (3, 12):
+        pb, cfg = make_problem(T, slots)
+        dT = (1e-2 * T.tensor(np.random.default_rng(1).standard_normal(pb.rho.shape))).cuda().requires_grad_()
+        mu = T.tensor(cfg["mu"], dtype=T.float64, requires_grad=True)
+        ka = T.tensor(cfg["kappa"], dtype=T.float64, requires_grad=True)
+        J = rb_kinetic_energy(dT, mu, ka, pb)
+        J.backward()
+        grads.append((J.item(), dT.grad.cpu().numpy(), mu.grad.item(), ka.grad.item()))
+        say("slots", slots, "J", J.item(), "dJ/dmu", mu.grad.item(), "dJ/dkappa", ka.grad.item())
+    (J0, g0, m0, k0), (J1, g1, m1, k1) = grads
+    assert J0 == J1 and np.array_equal(g0, g1) and m0 == m1 and k0 == k1
+
+
+def test_gradient_vs_central_differences(T):
+    from paper_1903_09043_amd.adjoint import rb_kinetic_energy, rb_kinetic_energy_ra_pr
+    pb, cfg = make_problem(T, 4)
+    rng = np.random.default_rng(2)
+    dT0 = (1e-2 * T.tensor(rng.standard_normal(pb.rho.shape))).cuda()
+    dT = dT0.clone().requires_grad_()
+    mu = T.tensor(cfg["mu"], dtype=T.float64, requires_grad=True)
+    ka = T.tensor(cfg["kappa"], dtype=T.float64, requires_grad=True)
+    J = rb_kinetic_energy(dT, mu, ka, pb)
+    J.backward()
+    g = dT.grad.cpu().numpy()
+    # freeze the schedule the forward run chose
+    S = pb.solver(cfg["mu"], cfg["kappa"])
+    S.U.copy_(pb.initial_state(dT0))
+    S.compute_dt()
+    log = T.zeros(pb.nsteps, dtype=T.float64, device="cuda")
+    S.step(pb.nsteps, dt_log=log)
+    pf, _ = make_problem(T, 4, dt_sched=log)
+
+    def Jf(x, m=cfg["mu"], k=cfg["kappa"]):
+        with T.no_grad():
+            return rb_kinetic_energy(x, m, k, pf).item()
+
+    assert Jf(dT0) == J.item()
+    for k in range(5):
+        d = T.tensor(rng.standard_normal(pb.rho.shape)).cuda()  # unit-RMS direction
+        h = 1e-7
+        fd = (Jf(dT0 + h * d) - Jf(dT0 - h * d)) / (2 * h)
+        ad = float(np.sum(g * d.cpu().numpy()))
+        say("dT direction", k, "fd", fd, "adjoint", ad)
+        assert abs(fd - ad) <= 1e-5 * max(abs(fd), abs(ad))
+    for name, grad, base in (("mu", mu.grad.item(), cfg["mu"]), ("kappa", ka.grad.item(), cfg["kappa"])):
+        hp = 1e-3 * base
+        if name == "mu":
+            fd = (Jf(dT0, m=base + hp) - Jf(dT0, m=base - hp)) / (2 * hp)
+        else:
+            fd = (Jf(dT0, k=base + hp) - Jf(dT0, k=base - hp)) / (2 * hp)
+        say(name, "fd", fd, "adjoint", grad)
+        assert abs(fd - grad) <= 1e-5 * abs(fd)
+    # Ra through the (Ra, Pr) -> (mu, kappa) map
+    Ra = T.tensor(2e4, dtype=T.float64, requires_grad=True)
+    J2 = rb_kinetic_energy_ra_pr(dT0, Ra, 1.0, pf)
+    J2.backward()
+    hr = 1.0
+    with T.no_grad():
+        fp = rb_kinetic_energy_ra_pr(dT0, T.tensor(2e4 + hr, dtype=T.float64), 1.0, pf).item()
+        fm = rb_kinetic_energy_ra_pr(dT0, T.tensor(2e4 - hr, dtype=T.float64), 1.0, pf).item()
+    fd = (fp - fm) / (2 * hr)
+    say("Ra", "fd", fd, "adjoint", Ra.grad.item())
+    assert abs(fd - Ra.grad.item()) <= 1e-5 * abs(fd)
