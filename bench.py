@@ -1,14 +1,18 @@
 """Benchmark: FP64 Mcell-updates/s of the fused all-regime step on the 3D
 Rayleigh-Benard workload (256^3, Ra = 1e6, Pr = 1, seeded 1e-4 temperature
 noise, periodic x/y, no-slip fixed-T walls), with the HBM roofline of the
-fused step kernel and the oracle timed on the host cores.
+fused step kernel and the oracle timed on the host cores; beside it the
+adjoint/forward time ratio (3D RB 128^3, Ra = 1e5, 200 steps, 16 revolve
+slots) and the speedup of the batched launch over one launch sequence per
+instance (512 2D RB instances, 500 steps each).
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+                  [--no-adjoint] [--no-batch]
 
-Prints ONE JSON line.  Inputs are resident in HBM before the timed region;
-the timed region is K steps of ars_step (one fused kernel launch per step,
-dt kept on the device) bracketed by synchronisations and HIP events on the
-stream the kernels run on.
+Prints ONE JSON line.  Inputs are resident in HBM before every timed
+region; the main timed region is K steps of ars_step (one fused kernel
+launch per step, dt kept on the device) bracketed by synchronisations and
+HIP events on the stream the kernels run on.
 """
 import argparse
 import hashlib
@@ -67,6 +71,114 @@ def cpu_baseline(cfg, prob, prm, seed, budget_s=12.0):
                        f"{el:.1f} s on {O.num_threads()} host thread(s)")
 
 
+def timed(torch, fn, stream=None):
+    """Milliseconds of fn() between HIP events on `stream` (default: the
+    current stream), synchronised on both sides."""
+    stream = stream or torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1)
+
+
+def adjoint_leg(torch, A, W, nsteps=200, slots=16, reps=20):
+    """Adjoint/forward ratio on the 3D RB 128^3 workload: per step (one
+    adjoint step vs one fused step, both warm, median of `reps`) and end to
+    end (full gradient: forward, recomputation by the revolve plan and the
+    adjoint sweep, over the forward run alone)."""
+    from paper_1903_09043_amd.adjoint import RBProblem, rb_kinetic_energy
+    cfg, prob, prm, seed = W.config5()
+    pb = RBProblem(cfg, prob, prm, nsteps, slots)
+    g = torch.Generator(device="cpu").manual_seed(1)
+    dT = (1e-4 * (2 * torch.rand(pb.rho.shape, generator=g, dtype=torch.float64) - 1)).cuda()
+    S = pb.solver(cfg["mu"], cfg["kappa"])
+    S.U.copy_(pb.initial_state(dT))
+    S.compute_dt()
+    dt = S.dt.clone()
+    lam = torch.randn(S.U.shape, generator=g, dtype=torch.float64).cuda()
+    lam_n = torch.empty_like(lam)
+    pg = torch.zeros(2, dtype=torch.float64, device="cuda")
+    U0 = S.U.clone()
+    S.step_adjoint(U0, lam, dt, lam_n=lam_n, param_grad=pg)
+    S.step_sched(dt)
+    fwd, adj = [], []
+    for _ in range(reps):
+        fwd.append(timed(torch, lambda: S.step_sched(dt)))
+        adj.append(timed(torch, lambda: S.step_adjoint(U0, lam, dt, lam_n=lam_n, param_grad=pg)))
+    fwd.sort()
+    adj.sort()
+    f_ms, a_ms = fwd[reps // 2], adj[reps // 2]
+    # end to end
+    mu = torch.tensor(cfg["mu"], dtype=torch.float64, requires_grad=True)
+    ka = torch.tensor(cfg["kappa"], dtype=torch.float64, requires_grad=True)
+    S.U.copy_(pb.initial_state(dT))
+    S.compute_dt()
+    fwd_ms = timed(torch, lambda: S.step(nsteps))
+    x = dT.clone().requires_grad_()
+
+    def grad():
+        J = rb_kinetic_energy(x, mu, ka, pb)
+        J.backward()
+    grad_ms = timed(torch, grad)
+    ok = bool(torch.isfinite(x.grad).all().item()) and mu.grad is not None
+    return {"workload": f"3D Rayleigh-Benard 128^3, Ra=1e5, Pr=1, {nsteps} steps, {slots} revolve slots, "
+                        f"J = final kinetic energy, gradient w.r.t. dT0 (128^3 field), mu, kappa",
+            "step_ms_forward": round(f_ms, 4), "step_ms_adjoint": round(a_ms, 4),
+            "ratio_per_step": round(a_ms / f_ms, 3),
+            "forward_run_ms": round(fwd_ms, 2), "gradient_ms": round(grad_ms, 2),
+            "ratio_end_to_end": round(grad_ms / fwd_ms, 3),
+            "recomputed_forward_steps": int(A.revolve_cost(nsteps, slots)), "gradient_finite": ok}
+
+
+def batch_leg(torch, A, W, nsteps=500):
+    """Speedup of the batched persistent launch (graph-captured, one launch
+    for all instances and steps) over the loop of ars_step(500) per
+    instance on the same stream; every instance's final state must be
+    bitwise equal between the two."""
+    setups = W.config4()
+    cfgs = [c for c, *_ in setups]
+    B = A.Batch(cfgs)
+    for k, (cfg, prob, prm, seed) in enumerate(setups):
+        U = A.Context(cfg).init_host(prob, prm, seed)
+        B.view(k).copy_(torch.from_numpy(U))
+    init = B.states.clone()
+    tune = B.autotune(trial_steps=5)
+    cells = sum(int(c["n"][0]) * int(c["n"][1]) for c in cfgs)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        B.capture(nsteps, s)
+    torch.cuda.synchronize()
+    batch_ms = timed(torch, lambda: B.replay(s), stream=s)
+    _, _, fc, rc = B.read()
+    # per-instance loop
+    solvers = []
+    for k, cfg in enumerate(cfgs):
+        S = A.Solver(cfg)
+        S.U.copy_(init[B.off[k]:B.off[k] + S.U.numel()].view(S.U.shape))
+        S.compute_dt()
+        solvers.append(S)
+
+    def loop():
+        for S in solvers:
+            S.step(nsteps)
+    loop_ms = timed(torch, loop)
+    same = all(torch.equal(B.view(k), S.U) for k, S in enumerate(solvers))
+    rows, zc = B.tiling()
+    return {"workload": f"512 2D Rayleigh-Benard instances (64x32 / 128x64 / 256x128, Ra log-uniform "
+                        f"[5e2, 5e3], Pr=1), {nsteps} steps each, per-instance CFL dt",
+            "cells": cells, "cell_updates": cells * nsteps,
+            "batched_ms": round(batch_ms, 2), "loop_ms": round(loop_ms, 2),
+            "speedup": round(loop_ms / batch_ms, 3),
+            "batched_Mcell_per_s": round(cells * nsteps / batch_ms / 1e3, 1),
+            "loop_Mcell_per_s": round(cells * nsteps / loop_ms / 1e3, 1),
+            "bitwise_equal": bool(same), "faults": int((fc >= 0).sum()),
+            "tiling": {"rows": rows, "zc_policy": tune["zc_policy"], "tuner_candidates": tune["n_candidates"]}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -74,6 +186,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--zchunk", type=int, default=0)
     ap.add_argument("--mode", choices=["step", "copy"], default="step",
                     help="copy: device-to-device copies of one state (calibrates the HBM byte counters)")
@@ -143,6 +257,14 @@ def main():
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic},
         "final_state": {"t": S.t.item(), "max_u": d["max_u"], "fault": d["fault"]},
     }
+    del S
+    torch.cuda.empty_cache()
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_leg(torch, A, W)
+        torch.cuda.empty_cache()
+    if not args.no_batch:
+        out["batch"] = batch_leg(torch, A, W)
+        torch.cuda.empty_cache()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(cfg, prob, prm, seed)
     print(json.dumps(out), flush=True)

@@ -77,29 +77,39 @@ def test_gradient_vs_central_differences(T):
             return rb_kinetic_energy(x, m, k, pf).item()
 
     assert Jf(dT0) == J.item()
+
+    # A central difference that straddles a switch of a non-smooth branch
+    # (upwind side of a face, |u*| in theta) measures the mean of the two
+    # one-sided slopes instead of the derivative of the branch taken; such a
+    # switch is rare but not impossible over a few thousand faces, so each
+    # check accepts agreement at either of two step sizes.
+    def agree(f, ad, hs, what):
+        errs = []
+        for h in hs:
+            fd = f(h)
+            errs.append(abs(fd - ad) / max(abs(fd), abs(ad)))
+            say(what, "h", h, "fd", fd, "adjoint", ad, "rel", errs[-1])
+            if errs[-1] <= 1e-5:
+                return
+        assert min(errs) <= 1e-5, (what, errs)
+
     for k in range(5):
         d = T.tensor(rng.standard_normal(pb.rho.shape)).cuda()  # unit-RMS direction
-        h = 1e-7
-        fd = (Jf(dT0 + h * d) - Jf(dT0 - h * d)) / (2 * h)
         ad = float(np.sum(g * d.cpu().numpy()))
-        say("dT direction", k, "fd", fd, "adjoint", ad)
-        assert abs(fd - ad) <= 1e-5 * max(abs(fd), abs(ad))
-    for name, grad, base in (("mu", mu.grad.item(), cfg["mu"]), ("kappa", ka.grad.item(), cfg["kappa"])):
-        hp = 1e-3 * base
-        if name == "mu":
-            fd = (Jf(dT0, m=base + hp) - Jf(dT0, m=base - hp)) / (2 * hp)
-        else:
-            fd = (Jf(dT0, k=base + hp) - Jf(dT0, k=base - hp)) / (2 * hp)
-        say(name, "fd", fd, "adjoint", grad)
-        assert abs(fd - grad) <= 1e-5 * abs(fd)
+        agree(lambda h: (Jf(dT0 + h * d) - Jf(dT0 - h * d)) / (2 * h), ad, (1e-7, 1e-8), f"dT direction {k}")
+    base_mu, base_ka = cfg["mu"], cfg["kappa"]
+    agree(lambda h: (Jf(dT0, m=base_mu * (1 + h)) - Jf(dT0, m=base_mu * (1 - h))) / (2 * h * base_mu),
+          mu.grad.item(), (1e-4, 1e-5), "mu")
+    agree(lambda h: (Jf(dT0, k=base_ka * (1 + h)) - Jf(dT0, k=base_ka * (1 - h))) / (2 * h * base_ka),
+          ka.grad.item(), (1e-4, 1e-5), "kappa")
     # Ra through the (Ra, Pr) -> (mu, kappa) map
     Ra = T.tensor(2e4, dtype=T.float64, requires_grad=True)
     J2 = rb_kinetic_energy_ra_pr(dT0, Ra, 1.0, pf)
     J2.backward()
-    hr = 1.0
-    with T.no_grad():
-        fp = rb_kinetic_energy_ra_pr(dT0, T.tensor(2e4 + hr, dtype=T.float64), 1.0, pf).item()
-        fm = rb_kinetic_energy_ra_pr(dT0, T.tensor(2e4 - hr, dtype=T.float64), 1.0, pf).item()
-    fd = (fp - fm) / (2 * hr)
-    say("Ra", "fd", fd, "adjoint", Ra.grad.item())
-    assert abs(fd - Ra.grad.item()) <= 1e-5 * abs(fd)
+
+    def fd_ra(hr):
+        with T.no_grad():
+            fp = rb_kinetic_energy_ra_pr(dT0, T.tensor(2e4 + hr, dtype=T.float64), 1.0, pf).item()
+            fm = rb_kinetic_energy_ra_pr(dT0, T.tensor(2e4 - hr, dtype=T.float64), 1.0, pf).item()
+        return (fp - fm) / (2 * hr)
+    agree(fd_ra, Ra.grad.item(), (1.0, 0.1), "Ra")
