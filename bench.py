@@ -29,7 +29,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 
 def kernel_hash():
     h = hashlib.sha256()
-    for f in ("ars_fused.hip", "ars_dev.h"):
+    for f in ("ars_fused.hip", "ars_fused.h", "ars_dev.h"):
         h.update(open(os.path.join(ROOT, "paper_1903_09043_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -188,6 +188,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--only", choices=["adjoint", "batch"], default=None,
+                    help="run one side leg alone (profiling); prints its JSON object")
     ap.add_argument("--zchunk", type=int, default=0)
     ap.add_argument("--mode", choices=["step", "copy"], default="step",
                     help="copy: device-to-device copies of one state (calibrates the HBM byte counters)")
@@ -200,6 +202,12 @@ def main():
     import paper_1903_09043_amd as A
     from paper_1903_09043_amd import workloads as W
 
+    if args.only == "adjoint":
+        print(json.dumps({"adjoint": adjoint_leg(torch, A, W)}), flush=True)
+        return
+    if args.only == "batch":
+        print(json.dumps({"batch": batch_leg(torch, A, W)}), flush=True)
+        return
     cfg, prob, prm, seed = W.config2(n=args.n)
     ncell = args.n ** 3
     if args.mode == "copy":
