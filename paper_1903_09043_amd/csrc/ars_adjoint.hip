@@ -81,13 +81,6 @@ __device__ __forceinline__ bool flux_range(const RefGrid& G, int a, int qx, int 
   return true;
 }
 
-// ---------------------------------------------------------------- K0: zero
-__global__ void k_adj_zero(double* W, long long from, long long count) {
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < count;
-       i += (long long)gridDim.x * blockDim.x)
-    W[from + i] = 0.0;
-}
-
 // ------------------------------------------------------- K1: update^T ------
 // nb_v(c) = b_v(c) [+ rho Phi for E] - sum_a lam_a (G_v(a,c) - G_v(a,c-e_a))
 // [+ lam_z S-bar(c) for m_z];  E' = nb_E - nb_rho Phi.
@@ -130,8 +123,18 @@ __global__ void k_adj_flux(Params P, RefGrid G, int a, double* __restrict__ W) {
   constexpr int NV = DIM + 2;
   int qx, qy, qz;
   decode(G, i, qx, qy, qz);
-  if (!flux_range<DIM>(G, a, qx, qy, qz)) return;
   const long long n = G.npad;
+  if (!flux_range<DIM>(G, a, qx, qy, qz)) {
+    // faces outside the flux range carry no flux: their adjoints are zero
+    // (read by the face solver's reverse and the parameter reduction)
+    W[(A_FB + 4 * a + 0) * n + i] = 0.0;
+    W[(A_FB + 4 * a + 1) * n + i] = 0.0;
+    if (DISS) {
+      W[(A_PM + 2 * a + 0) * n + i] = 0.0;
+      W[(A_PM + 2 * a + 1) * n + i] = 0.0;
+    }
+    return;
+  }
   const long long j = i + astride(G, a);
   const int f = R_FACE + 4 * a;
   const double us = W[(f + 0) * n + i];
@@ -256,8 +259,11 @@ __global__ void k_adj_cell(Params P, RefGrid G, AdjIO io, double* __restrict__ W
   constexpr int NV = DIM + 2;
   int qx, qy, qz;
   decode(G, i, qx, qy, qz);
-  if (!cell_range<DIM>(G, qx, qy, qz)) return;
   const long long n = G.npad;
+  if (!cell_range<DIM>(G, qx, qy, qz)) {
+    for (int v = 0; v < 5; ++v) W[(A_CONSB + v) * n + i] = 0.0;  // no acoustic cell values here
+    return;
+  }
   const double dt = *io.dt;
   const double lamz = dt / P.dx[2];
   double btb[NV];
@@ -646,12 +652,14 @@ __global__ void k_adj_fold(Params P, RefGrid G, AdjIO io, const double* __restri
 }
 
 // ----------------------------------------------- K8: parameter reduction ----
+template <int DIM>
 __global__ void __launch_bounds__(256) k_adj_params(RefGrid G, const double* __restrict__ W, double* partial) {
   __shared__ double sh[2][256];
   double s0 = 0.0, s1 = 0.0;
   const long long n = G.npad;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
     for (int a = 0; a < 3; ++a) {
+      if (DIM == 2 && a == 1) continue;  // no faces along the inactive axis
       s0 += W[(A_PM + 2 * a + 0) * n + i];
       s1 += W[(A_PM + 2 * a + 1) * n + i];
     }
@@ -692,12 +700,6 @@ static hipError_t adjoint_t(const Params& P, const double* Un, const double* lam
   const unsigned nb = (unsigned)((G.npad + bs - 1) / bs);
   hipError_t e = launch_ref_forward(P, Un, wadj, d_dt, s);
   if (e != hipSuccess) return e;
-  {
-    const long long cnt = (long long)(A_NFIELD - R_NFIELD) * G.npad;
-    long long blocks = (cnt + bs - 1) / bs;
-    if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL(k_adj_zero, dim3((unsigned)blocks), dim3(bs), 0, s, W, (long long)R_NFIELD * G.npad, cnt);
-  }
   AdjIO io{lam1, lam0, d_dt, pgrad};
   hipLaunchKernelGGL(k_adj_update<DIM>, dim3(nb), dim3(bs), 0, s, P, G, io, W);
   for (int a = 0; a < 3; ++a) {
@@ -725,7 +727,7 @@ static hipError_t adjoint_t(const Params& P, const double* Un, const double* lam
   if (P.diss && pgrad) {
     double* partial = W + (size_t)A_NFIELD * G.npad;  // 4096 bytes after the fields: 256 blocks x 2
     const int npb = 256;
-    hipLaunchKernelGGL(k_adj_params, dim3(npb), dim3(256), 0, s, G, W, partial);
+    hipLaunchKernelGGL(k_adj_params<DIM>, dim3(npb), dim3(256), 0, s, G, W, partial);
     hipLaunchKernelGGL(k_adj_params_final, dim3(1), dim3(64), 0, s, npb, partial, pgrad);
   }
   return hipGetLastError();

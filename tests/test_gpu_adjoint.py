@@ -49,6 +49,9 @@ def perturbed(cfg, prob, prm, seed, amp_u=1e-2):
 def gpu_adjoint(A, cfg, U, lam, dt):
     import torch
     S = A.Solver(cfg)
+    # poison the workspace: every field the reverse sweep reads must have
+    # been written by it in this call (NaN bytes otherwise propagate)
+    S.adjoint_workspace().fill_(0xFF)
     Ud = torch.as_tensor(U).cuda()
     ld = torch.as_tensor(lam).cuda()
     pg = torch.zeros(2, dtype=torch.float64, device="cuda")

@@ -113,3 +113,62 @@ def test_gradient_vs_central_differences(T):
             fm = rb_kinetic_energy_ra_pr(dT0, T.tensor(2e4 - hr, dtype=T.float64), 1.0, pf).item()
         return (fp - fm) / (2 * hr)
     agree(fd_ra, Ra.grad.item(), (1.0, 0.1), "Ra")
+
+
+def test_config5_gradient_vs_finite_differences(T):
+    """The adjoint workload at full size: 3D RB 128^3, Ra = 1e5, Pr = 1, 200
+    steps from the base state heated by a seeded 1e-4 perturbation, 16
+    revolve slots.  dJ/d(dT0) against central differences along 10 seeded
+    unit-RMS directions, and dJ/dRa through the (Ra, Pr) map, all at the
+    frozen time-step schedule of the forward run."""
+    from paper_1903_09043_amd.adjoint import RBProblem, rb_kinetic_energy, rb_kinetic_energy_ra_pr
+    cfg, prob, prm, seed = W.config5()
+    pb = RBProblem(cfg, prob, prm, 200, 16)
+    g0 = T.Generator(device="cpu").manual_seed(0)
+    dT0 = (1e-4 * (2 * T.rand(pb.rho.shape, generator=g0, dtype=T.float64) - 1)).cuda()
+    x = dT0.clone().requires_grad_()
+    mu = T.tensor(cfg["mu"], dtype=T.float64, requires_grad=True)
+    ka = T.tensor(cfg["kappa"], dtype=T.float64, requires_grad=True)
+    J = rb_kinetic_energy(x, mu, ka, pb)
+    J.backward()
+    say("config5 J", J.item(), "dJ/dmu", mu.grad.item(), "dJ/dkappa", ka.grad.item())
+    g = x.grad
+    S = pb.solver(cfg["mu"], cfg["kappa"])
+    S.U.copy_(pb.initial_state(dT0))
+    S.compute_dt()
+    log = T.zeros(200, dtype=T.float64, device="cuda")
+    S.step(200, dt_log=log)
+    pf = RBProblem(cfg, prob, prm, 200, 16, dt_sched=log)
+
+    def Jf(v):
+        with T.no_grad():
+            return rb_kinetic_energy(v, cfg["mu"], cfg["kappa"], pf).item()
+
+    assert Jf(dT0) == J.item()
+    for k in range(1, 11):
+        gk = T.Generator(device="cpu").manual_seed(k)
+        d = T.randn(pb.rho.shape, generator=gk, dtype=T.float64).cuda()
+        d = d / d.pow(2).mean().sqrt()
+        ad = float((g * d).sum().item())
+        errs = []
+        for h in (1e-9, 1e-10):
+            fd = (Jf(dT0 + h * d) - Jf(dT0 - h * d)) / (2 * h)
+            errs.append(abs(fd - ad) / max(abs(fd), abs(ad)))
+            say("direction", k, "h", h, "fd", fd, "adjoint", ad, "rel", errs[-1])
+            if errs[-1] <= 1e-5:
+                break
+        assert min(errs) <= 1e-5, (k, errs)
+    Ra = T.tensor(1e5, dtype=T.float64, requires_grad=True)
+    J2 = rb_kinetic_energy_ra_pr(dT0, Ra, 1.0, pf)
+    J2.backward()
+    errs = []
+    for hr in (10.0, 1.0):
+        with T.no_grad():
+            fp = rb_kinetic_energy_ra_pr(dT0, T.tensor(1e5 + hr, dtype=T.float64), 1.0, pf).item()
+            fm = rb_kinetic_energy_ra_pr(dT0, T.tensor(1e5 - hr, dtype=T.float64), 1.0, pf).item()
+        fd = (fp - fm) / (2 * hr)
+        errs.append(abs(fd - Ra.grad.item()) / abs(fd))
+        say("Ra h", hr, "fd", fd, "adjoint", Ra.grad.item(), "rel", errs[-1])
+        if errs[-1] <= 1e-5:
+            break
+    assert min(errs) <= 1e-5, errs

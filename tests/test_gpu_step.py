@@ -247,3 +247,74 @@ def test_full_size_256cubed_one_step(A):
     err = close(U3, Uo)
     say("256^3 max rel err", err, "bitwise", bitwise(U3, Uo))
     assert err <= 1e-12
+
+
+def test_full_size_256cubed_10_steps_from_init(A):
+    """3D RB 256^3 from the initial state: 10 GPU steps (CFL time steps
+    chosen on the device) against 10 oracle steps on the whole grid."""
+    import torch
+    cfg, prob, prm, seed = W.config2()
+    S = A.Solver(cfg).init(prob, prm, seed)
+    log = torch.zeros(10, dtype=torch.float64, device="cuda")
+    S.step(10, dt_log=log)
+    torch.cuda.synchronize()
+    U = S.numpy()
+    say("256^3 x 10 oracle (threads=%d)" % O.num_threads())
+    r = O.run(cfg, O.init(cfg, prob, prm, seed), 10)
+    assert r["status"] == 0
+    assert np.array_equal(log.cpu().numpy(), r["dt_log"][:10])
+    err = close(U, r["U"])
+    say("256^3 x 10 max rel err", err, "bitwise", bitwise(U, r["U"]))
+    assert err <= 1e-12
+
+
+@pytest.mark.parametrize("lm", [1, 0])
+def test_gresho_1024_full_size(A, lm):
+    """2D Gresho vortex 1024^2, Mach 1e-3, periodic: 10 GPU steps equal 10
+    oracle steps on the whole grid; then 5000 steps on the GPU (the run
+    length of the workload) keep the kinetic energy, more of it with the
+    low-Mach correction than without (Sec. 4.2)."""
+    import torch
+    cfg, prob, prm, seed = W.config3(low_mach=lm)
+    S = A.Solver(cfg).init(prob, prm, seed)
+    ke0 = S.diagnostics()["e_kin"]
+    S.step(10)
+    torch.cuda.synchronize()
+    U = S.numpy()
+    r = O.run(cfg, O.init(cfg, prob, prm, seed), 10)
+    err = close(U, r["U"])
+    say("gresho 1024 lm", lm, "10 steps max rel err", err, "bitwise", bitwise(U, r["U"]))
+    assert err <= 1e-12
+    S.step(4990)
+    d = S.diagnostics()
+    ratio = d["e_kin"] / ke0
+    say("gresho 1024 lm", lm, "t", S.t.item(), "KE(t)/KE(0)", ratio)
+    if lm:
+        assert ratio > 0.99
+        test_gresho_1024_full_size.ratio_on = ratio
+    else:
+        assert ratio < getattr(test_gresho_1024_full_size, "ratio_on", 1.0)
+
+
+def test_checkpoint_resume(A, tmp_path):
+    """A run of 1000 steps equals 500 steps, a save of the state as raw FP64
+    and of t, a load into a fresh solver and 500 more steps, bit for bit
+    (dt of the resumed run comes from the loaded state)."""
+    import torch
+    cfg, prob, prm, seed = W.config1()
+    S = A.Solver(cfg).init(prob, prm, seed)
+    S.step(1000)
+    torch.cuda.synchronize()
+    ref, t_ref = S.numpy(), S.t.item()
+    S1 = A.Solver(cfg).init(prob, prm, seed)
+    S1.step(500)
+    torch.cuda.synchronize()
+    f = tmp_path / "state.f64"
+    S1.numpy().tofile(f)
+    np.array([S1.t.item()]).tofile(tmp_path / "t.f64")
+    S2 = A.Solver(cfg)
+    S2.set_state(np.fromfile(f, dtype=np.float64).reshape(S2.U.shape))
+    S2.t.fill_(float(np.fromfile(tmp_path / "t.f64")[0]))
+    S2.step(500)
+    torch.cuda.synchronize()
+    assert bitwise(S2.numpy(), ref) and S2.t.item() == t_ref
