@@ -34,9 +34,9 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
-def load_traffic(n_cells):
-    """HBM bytes per launch of the fused step from the committed rocprofv3
-    counter summary, if it was taken on the current kernel source."""
+def load_counters():
+    """The committed rocprofv3 counter summary of the fused step, if it was
+    taken on the current kernel source (else None)."""
     p = os.path.join(ROOT, "profiles", "fused_step_rb3d_256_counters.json")
     if not os.path.exists(p):
         return None
@@ -46,7 +46,31 @@ def load_traffic(n_cells):
         return None
     if d.get("kernel_hash") != kernel_hash():
         return None
+    return d
+
+
+def load_traffic(n_cells):
+    """HBM bytes per launch of the fused step (FETCH_SIZE and WRITE_SIZE,
+    scaled by a copy of known size) for the 256^3 workload."""
+    d = load_counters()
+    if d is None or n_cells != 256 ** 3:
+        return None
     return d.get("bytes_per_launch")
+
+
+def valu_view(ms_per_launch, n):
+    """Instruction-issue view of the same kernel from the committed SQ
+    counters (FP64 VALU: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T
+    lane-ops/s): the balanced issue bound of the measured instruction count
+    over the measured launch time."""
+    d = load_counters()
+    if d is None or "valu" not in d or n != 256:
+        return None
+    v = d["valu"]
+    return {"valu_lane_instr_per_cell": v["valu_lane_instructions_per_cell"],
+            "fp64_lane_instr_per_cell": v["fp64_lane_instructions_per_cell"],
+            "valu_busy_frac": v["valu_busy_frac"], "issue_bound_ms": v["balanced_issue_bound_ms"],
+            "issue_bound_frac": round(v["balanced_issue_bound_ms"] / ms_per_launch, 3)}
 
 
 def cpu_baseline(cfg, prob, prm, seed, budget_s=12.0):
@@ -262,7 +286,8 @@ def main():
                                f"theta on, periodic x/y, no-slip fixed-T walls",
                    "cells": ncell, "zchunk": S.ctx.zchunk()},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic},
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "valu_view": valu_view(ms / args.steps, args.n)},
         "final_state": {"t": S.t.item(), "max_u": d["max_u"], "fault": d["fault"]},
     }
     del S

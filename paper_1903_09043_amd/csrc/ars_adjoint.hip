@@ -7,9 +7,13 @@
 // phase kernels on the padded grid; the reverse sweep then runs the phases
 // backwards, each as a gather (a face or a cell collects every contribution
 // it receives, in a fixed order), so the result is deterministic:
-//   update^T -> flux^T (transport + viscous + heat) -> acoustic cell^T
-//   -> face solver^T -> primitive gather -> (wall ghost + primitive)^T
+//   (update + flux)^T per face, all axes in one pass (transport + viscous +
+//   heat; the face flux adjoint is formed from lam^{n+1} on the fly)
+//   -> acoustic cell^T -> (face solver^T + primitive gather), each face's
+//   reverse evaluated by both of its cells -> (wall ghost + primitive)^T
 //   -> fold of periodic / outflow images onto interior cells.
+// Only small per-face and per-cell adjoints go through memory between the
+// passes; quantities a later pass can form from its inputs are recomputed.
 // Non-smooth operations differentiate the branch the forward step took
 // (max/min: first argument on ties; |x|: sign of x >= 0; upwind: u* >= 0
 // takes the left cell), as the oracle's tangent-linear model does.
@@ -20,18 +24,14 @@
 namespace ars {
 
 enum {
-  A_GB = R_NFIELD,         // 3 axes x 5: adjoint of the total face fluxes
-  A_FB = A_GB + 15,        // 3 axes x (u*, Pi*, P, S) adjoints
-  A_BTC = A_FB + 12,       // 3 axes x 5: adjoint of b~ sent to the upwind cell
-  A_VL = A_BTC + 15,       // 3 axes x (u_0, u_1, u_2, T) viscous adjoint to the left cell
+  A_FB = R_NFIELD,         // 3 axes x (u*, Pi*) adjoints from the flux reverse
+  A_VL = A_FB + 6,         // 3 axes x (u_0, u_1, u_2, T) viscous adjoint to the left cell
   A_VR = A_VL + 12,        // same, right cell
   A_VT = A_VR + 12,        // 3 axes x (2 tangential axes x 2) tangential-gradient adjoints
   A_PM = A_VT + 12,        // 3 axes x (mu, kappa) partial derivatives
   A_CB = A_PM + 6,         // L, Am_0, Am_1, Am_2, AE, S-bar adjoints per cell
   A_CONSB = A_CB + 6,      // 5: adjoint of the cell's conserved values through b~
-  A_FPL = A_CONSB + 5,     // 3 axes x (rho, u_n, p, rho c, 1/(rho c), 1/c) to the left cell
-  A_FPR = A_FPL + 18,      // same, right cell
-  A_PB = A_FPR + 18,       // rho, u_0, u_1, u_2, p, rho c, 1/(rho c), 1/c, T
+  A_PB = A_CONSB + 5,      // rho, u_0, u_1, u_2, p, rho c, 1/(rho c), 1/c, T
   A_UB = A_PB + 9,         // 5: adjoint of the (image) cell's conserved values
   A_NFIELD = A_UB + 5
 };
@@ -81,54 +81,45 @@ __device__ __forceinline__ bool flux_range(const RefGrid& G, int a, int qx, int 
   return true;
 }
 
-// ------------------------------------------------------- K1: update^T ------
+// ------------------------------------------------ update^T (helpers) -----
 // nb_v(c) = b_v(c) [+ rho Phi for E] - sum_a lam_a (G_v(a,c) - G_v(a,c-e_a))
-// [+ lam_z S-bar(c) for m_z];  E' = nb_E - nb_rho Phi.
+// [+ lam_z S-bar(c) for m_z];  E' = nb_E - nb_rho Phi.  The adjoint of nb
+// at an interior padded cell, zero elsewhere:
 template <int DIM>
-__global__ void k_adj_update(Params P, RefGrid G, AdjIO io, double* __restrict__ W) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= G.npad) return;
+__device__ __forceinline__ double nbar(const Params& P, const RefGrid& G, const AdjIO& io, int x, int y, int z,
+                                       int v) {
   constexpr int NV = DIM + 2;
-  const long long n = G.npad;
-  int qx, qy, qz;
-  decode(G, i, qx, qy, qz);
-  const double dt = *io.dt;
-  const double lam[3] = {dt / P.dx[0], DIM == 3 ? dt / P.dx[1] : 0.0, dt / P.dx[2]};
-  auto nbar = [&](int x, int y, int z, int v) -> double {
-    if (!interior_cell<DIM>(G, x, y, z)) return 0.0;
-    const long long c = (x - 2) + (long long)P.nx * ((DIM == 3 ? y - 2 : 0) + (long long)P.ny * (z - 2));
-    const double lr = io.lam1[c], lE = io.lam1[c + (NV - 1) * P.ncell];
-    if (v == 0) return lr - phi_at(P, z - 2) * lE;
-    if (v == NV - 1) return lE;
-    return io.lam1[c + v * P.ncell];
-  };
-  if (interior_cell<DIM>(G, qx, qy, qz)) {
-    const long long c = (qx - 2) + (long long)P.nx * ((DIM == 3 ? qy - 2 : 0) + (long long)P.ny * (qz - 2));
-    for (int v = 0; v < NV; ++v) io.lam0[c + v * P.ncell] = io.lam1[c + v * P.ncell];
-  }
-  for (int t = 0; t < DIM; ++t) {
-    const int a = axis_of<DIM>(t);
-    if (!flux_range<DIM>(G, a, qx, qy, qz)) continue;
-    const int rx = qx + (a == 0), ry = qy + (a == 1), rz = qz + (a == 2);
-    for (int v = 0; v < NV; ++v)
-      W[(A_GB + 5 * a + v) * n + i] = lam[a] * (nbar(rx, ry, rz, v) - nbar(qx, qy, qz, v));
-  }
+  if (!interior_cell<DIM>(G, x, y, z)) return 0.0;
+  const long long c = (x - 2) + (long long)P.nx * ((DIM == 3 ? y - 2 : 0) + (long long)P.ny * (z - 2));
+  const double lr = io.lam1[c], lE = io.lam1[c + (NV - 1) * P.ncell];
+  if (v == 0) return lr - phi_at(P, z - 2) * lE;
+  if (v == NV - 1) return lE;
+  return io.lam1[c + v * P.ncell];
+}
+
+// Adjoint of the total flux of face (a, L = (qx, qy, qz)) in the flux range.
+template <int DIM>
+__device__ __forceinline__ void face_gbar(const Params& P, const RefGrid& G, const AdjIO& io, int a, double lama,
+                                          int qx, int qy, int qz, double* Gb) {
+  constexpr int NV = DIM + 2;
+  const int rx = qx + (a == 0), ry = qy + (a == 1), rz = qz + (a == 2);
+#pragma unroll
+  for (int v = 0; v < NV; ++v)
+    Gb[v] = lama * (nbar<DIM>(P, G, io, rx, ry, rz, v) - nbar<DIM>(P, G, io, qx, qy, qz, v));
 }
 
 // ------------------------------------------------------- K2: flux^T --------
 template <int DIM, bool DISS>
-__global__ void k_adj_flux(Params P, RefGrid G, int a, double* __restrict__ W) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= G.npad) return;
+__device__ __forceinline__ void adj_flux_face(const Params& P, const RefGrid& G, const AdjIO& io, int a,
+                                              double lama, long long i, int qx, int qy, int qz,
+                                              double* __restrict__ W) {
   constexpr int NV = DIM + 2;
-  int qx, qy, qz;
-  decode(G, i, qx, qy, qz);
   const long long n = G.npad;
   if (!flux_range<DIM>(G, a, qx, qy, qz)) {
     // faces outside the flux range carry no flux: their adjoints are zero
     // (read by the face solver's reverse and the parameter reduction)
-    W[(A_FB + 4 * a + 0) * n + i] = 0.0;
-    W[(A_FB + 4 * a + 1) * n + i] = 0.0;
+    W[(A_FB + 2 * a + 0) * n + i] = 0.0;
+    W[(A_FB + 2 * a + 1) * n + i] = 0.0;
     if (DISS) {
       W[(A_PM + 2 * a + 0) * n + i] = 0.0;
       W[(A_PM + 2 * a + 1) * n + i] = 0.0;
@@ -142,25 +133,19 @@ __global__ void k_adj_flux(Params P, RefGrid G, int a, double* __restrict__ W) {
   const bool wall = W[(R_WALL + a) * n + i] != 0.0;
   const int dn = comp_of<DIM>(a);
   double Gb[NV];
-  for (int v = 0; v < NV; ++v) Gb[v] = W[(A_GB + 5 * a + v) * n + i];
+  face_gbar<DIM>(P, G, io, a, lama, qx, qy, qz, Gb);
   double usb = 0.0;
   double pib = Gb[1 + dn];
-  double btc[NV];
-  for (int v = 0; v < NV; ++v) btc[v] = 0.0;
   if (!wall) {
+    // (the b~ adjoint Gb * u* of the upwind cell is formed by the cell pass)
     const long long up = us >= 0.0 ? i : j;
-    for (int v = 0; v < NV - 1; ++v) {
-      btc[v] = Gb[v] * us;
-      usb += Gb[v] * W[(R_BT + v) * n + up];
-    }
+    for (int v = 0; v < NV - 1; ++v) usb += Gb[v] * W[(R_BT + v) * n + up];
     const double bE = W[(R_BT + NV - 1) * n + up];
-    btc[NV - 1] = Gb[NV - 1] * us;
     pib += Gb[NV - 1] * us;
     usb += Gb[NV - 1] * (bE + pi);
   }
-  W[(A_FB + 4 * a + 0) * n + i] = usb;
-  W[(A_FB + 4 * a + 1) * n + i] = pib;
-  for (int v = 0; v < NV; ++v) W[(A_BTC + 5 * a + v) * n + i] = btc[v];
+  W[(A_FB + 2 * a + 0) * n + i] = usb;
+  W[(A_FB + 2 * a + 1) * n + i] = pib;
   if (DISS) {
     // forward viscous quantities at the face
     double uL[3], uR[3];
@@ -251,6 +236,20 @@ __global__ void k_adj_flux(Params P, RefGrid G, int a, double* __restrict__ W) {
   }
 }
 
+template <int DIM, bool DISS>
+__global__ void k_adj_flux(Params P, RefGrid G, AdjIO io, double* __restrict__ W) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= G.npad) return;
+  int qx, qy, qz;
+  decode(G, i, qx, qy, qz);
+  const double dt = *io.dt;
+#pragma unroll
+  for (int t = 0; t < DIM; ++t) {
+    const int a = axis_of<DIM>(t);
+    adj_flux_face<DIM, DISS>(P, G, io, a, dt / P.dx[a], i, qx, qy, qz, W);
+  }
+}
+
 // ------------------------------------------------- K3: acoustic cell^T -----
 template <int DIM>
 __global__ void k_adj_cell(Params P, RefGrid G, AdjIO io, double* __restrict__ W) {
@@ -270,15 +269,26 @@ __global__ void k_adj_cell(Params P, RefGrid G, AdjIO io, double* __restrict__ W
   for (int v = 0; v < NV; ++v) btb[v] = 0.0;
   for (int t = 0; t < DIM; ++t) {
     const int a = axis_of<DIM>(t);
-    // c as the left cell of face (a, c)
-    if (flux_range<DIM>(G, a, qx, qy, qz) && W[(R_WALL + a) * n + i] == 0.0 &&
-        W[(R_FACE + 4 * a) * n + i] >= 0.0)
-      for (int v = 0; v < NV; ++v) btb[v] += W[(A_BTC + 5 * a + v) * n + i];
-    // c as the right cell of face (a, c - e_a)
+    const double lama = dt / P.dx[a];
+    double Gb[NV];
+    // c as the left (upwind) cell of face (a, c): b~ adjoint Gb u*
+    if (flux_range<DIM>(G, a, qx, qy, qz) && W[(R_WALL + a) * n + i] == 0.0) {
+      const double us = W[(R_FACE + 4 * a) * n + i];
+      if (us >= 0.0) {
+        face_gbar<DIM>(P, G, io, a, lama, qx, qy, qz, Gb);
+        for (int v = 0; v < NV; ++v) btb[v] += Gb[v] * us;
+      }
+    }
+    // c as the right (upwind) cell of face (a, c - e_a)
     const long long m = i - astride(G, a);
     const int mx = qx - (a == 0), my = qy - (a == 1), mz = qz - (a == 2);
-    if (flux_range<DIM>(G, a, mx, my, mz) && W[(R_WALL + a) * n + m] == 0.0 && !(W[(R_FACE + 4 * a) * n + m] >= 0.0))
-      for (int v = 0; v < NV; ++v) btb[v] += W[(A_BTC + 5 * a + v) * n + m];
+    if (flux_range<DIM>(G, a, mx, my, mz) && W[(R_WALL + a) * n + m] == 0.0) {
+      const double us = W[(R_FACE + 4 * a) * n + m];
+      if (!(us >= 0.0)) {
+        face_gbar<DIM>(P, G, io, a, lama, mx, my, mz, Gb);
+        for (int v = 0; v < NV; ++v) btb[v] += Gb[v] * us;
+      }
+    }
   }
   const double iL = 1.0 / W[R_L * n + i];
   double consb[NV], Ab[NV];
@@ -304,21 +314,20 @@ __global__ void k_adj_cell(Params P, RefGrid G, AdjIO io, double* __restrict__ W
 }
 
 // ------------------------------------------------------ K4: face solver^T --
+// Reverse of the face solver of face (a, L = i = (qx, qy, qz)) (requires
+// L + e_a inside the padded grid): adjoints of (rho, u_n, p, rho c,
+// 1/(rho c), 1/c) of the left cell into bl[6] and of the right cell into
+// br[6].  Evaluated by both cells of the face in the primitive gather.
 template <int DIM, bool LM>
-__global__ void k_adj_face(Params P, RefGrid G, int a, AdjIO io, double* __restrict__ W) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= G.npad) return;
-  int qx, qy, qz;
-  decode(G, i, qx, qy, qz);
-  if (qa_of(a, qx, qy, qz) + 1 >= Pa_of(G, a)) return;
+__device__ __forceinline__ void face_reverse(const Params& P, const RefGrid& G, double lama, int a, long long i,
+                                             int qx, int qy, int qz, const double* __restrict__ W, double* bl,
+                                             double* br) {
   const long long n = G.npad;
   const long long j = i + astride(G, a);
-  const double dt = *io.dt;
-  const double lama = dt / P.dx[a];
   const int dn = comp_of<DIM>(a);
   const int f = R_FACE + 4 * a;
-  double usb = W[(A_FB + 4 * a + 0) * n + i];
-  double pib = W[(A_FB + 4 * a + 1) * n + i];
+  double usb = W[(A_FB + 2 * a + 0) * n + i];
+  double pib = W[(A_FB + 2 * a + 1) * n + i];
   double Pb = 0.0, Sb = 0.0;
   if (cell_range<DIM>(G, qx, qy, qz)) {
     usb += lama * W[(A_CB + 0) * n + i];
@@ -405,53 +414,55 @@ __global__ void k_adj_face(Params P, RefGrid G, int a, AdjIO io, double* __restr
     rcLb += P.K * ab;
   else
     rcRb += P.K * ab;
-  const int fl = A_FPL + 6 * a, fr = A_FPR + 6 * a;
-  W[(fl + 0) * n + i] = rLb;
-  W[(fl + 1) * n + i] = uLb;
-  W[(fl + 2) * n + i] = pLb;
-  W[(fl + 3) * n + i] = rcLb;
-  W[(fl + 4) * n + i] = iLb;
-  W[(fl + 5) * n + i] = cLb;
-  W[(fr + 0) * n + i] = rRb;
-  W[(fr + 1) * n + i] = uRb;
-  W[(fr + 2) * n + i] = pRb;
-  W[(fr + 3) * n + i] = rcRb;
-  W[(fr + 4) * n + i] = iRb;
-  W[(fr + 5) * n + i] = cRb;
+  bl[0] = rLb;
+  bl[1] = uLb;
+  bl[2] = pLb;
+  bl[3] = rcLb;
+  bl[4] = iLb;
+  bl[5] = cLb;
+  br[0] = rRb;
+  br[1] = uRb;
+  br[2] = pRb;
+  br[3] = rcRb;
+  br[4] = iRb;
+  br[5] = cRb;
 }
 
 // ---------------------------------------------- K5: primitive gather ------
-template <int DIM, bool DISS>
-__global__ void k_adj_pgather(Params P, RefGrid G, double* __restrict__ W) {
+template <int DIM, bool DISS, bool LM>
+__global__ void k_adj_pgather(Params P, RefGrid G, AdjIO io, double* __restrict__ W) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= G.npad) return;
   int qx, qy, qz;
   decode(G, i, qx, qy, qz);
   const long long n = G.npad;
+  const double dt = *io.dt;
   double rho = 0, u[3] = {0, 0, 0}, p = 0, rc = 0, irc = 0, ic = 0, T = 0;
   for (int t = 0; t < DIM; ++t) {
     const int a = axis_of<DIM>(t);
     const int qa = qa_of(a, qx, qy, qz);
     const int Pa = Pa_of(G, a);
     const long long sa = astride(G, a);
+    const double lama = dt / P.dx[a];
+    double bl[6], br[6];
     if (qa + 1 < Pa) {  // c is the left cell of face (a, c)
-      const int fl = A_FPL + 6 * a;
-      rho += W[(fl + 0) * n + i];
-      u[t] += W[(fl + 1) * n + i];
-      p += W[(fl + 2) * n + i];
-      rc += W[(fl + 3) * n + i];
-      irc += W[(fl + 4) * n + i];
-      ic += W[(fl + 5) * n + i];
+      face_reverse<DIM, LM>(P, G, lama, a, i, qx, qy, qz, W, bl, br);
+      rho += bl[0];
+      u[t] += bl[1];
+      p += bl[2];
+      rc += bl[3];
+      irc += bl[4];
+      ic += bl[5];
     }
     if (qa >= 1) {  // c is the right cell of face (a, c - e_a)
-      const int fr = A_FPR + 6 * a;
       const long long m = i - sa;
-      rho += W[(fr + 0) * n + m];
-      u[t] += W[(fr + 1) * n + m];
-      p += W[(fr + 2) * n + m];
-      rc += W[(fr + 3) * n + m];
-      irc += W[(fr + 4) * n + m];
-      ic += W[(fr + 5) * n + m];
+      face_reverse<DIM, LM>(P, G, lama, a, m, qx - (a == 0), qy - (a == 1), qz - (a == 2), W, bl, br);
+      rho += br[0];
+      u[t] += br[1];
+      p += br[2];
+      rc += br[3];
+      irc += br[4];
+      ic += br[5];
     }
     if (DISS) {
       if (flux_range<DIM>(G, a, qx, qy, qz)) {
@@ -701,26 +712,19 @@ static hipError_t adjoint_t(const Params& P, const double* Un, const double* lam
   hipError_t e = launch_ref_forward(P, Un, wadj, d_dt, s);
   if (e != hipSuccess) return e;
   AdjIO io{lam1, lam0, d_dt, pgrad};
-  hipLaunchKernelGGL(k_adj_update<DIM>, dim3(nb), dim3(bs), 0, s, P, G, io, W);
-  for (int a = 0; a < 3; ++a) {
-    if (DIM == 2 && a == 1) continue;
-    if (P.diss)
-      hipLaunchKernelGGL((k_adj_flux<DIM, true>), dim3(nb), dim3(bs), 0, s, P, G, a, W);
-    else
-      hipLaunchKernelGGL((k_adj_flux<DIM, false>), dim3(nb), dim3(bs), 0, s, P, G, a, W);
-  }
-  hipLaunchKernelGGL(k_adj_cell<DIM>, dim3(nb), dim3(bs), 0, s, P, G, io, W);
-  for (int a = 0; a < 3; ++a) {
-    if (DIM == 2 && a == 1) continue;
-    if (P.low_mach)
-      hipLaunchKernelGGL((k_adj_face<DIM, true>), dim3(nb), dim3(bs), 0, s, P, G, a, io, W);
-    else
-      hipLaunchKernelGGL((k_adj_face<DIM, false>), dim3(nb), dim3(bs), 0, s, P, G, a, io, W);
-  }
   if (P.diss)
-    hipLaunchKernelGGL((k_adj_pgather<DIM, true>), dim3(nb), dim3(bs), 0, s, P, G, W);
+    hipLaunchKernelGGL((k_adj_flux<DIM, true>), dim3(nb), dim3(bs), 0, s, P, G, io, W);
   else
-    hipLaunchKernelGGL((k_adj_pgather<DIM, false>), dim3(nb), dim3(bs), 0, s, P, G, W);
+    hipLaunchKernelGGL((k_adj_flux<DIM, false>), dim3(nb), dim3(bs), 0, s, P, G, io, W);
+  hipLaunchKernelGGL(k_adj_cell<DIM>, dim3(nb), dim3(bs), 0, s, P, G, io, W);
+  if (P.diss && P.low_mach)
+    hipLaunchKernelGGL((k_adj_pgather<DIM, true, true>), dim3(nb), dim3(bs), 0, s, P, G, io, W);
+  else if (P.diss)
+    hipLaunchKernelGGL((k_adj_pgather<DIM, true, false>), dim3(nb), dim3(bs), 0, s, P, G, io, W);
+  else if (P.low_mach)
+    hipLaunchKernelGGL((k_adj_pgather<DIM, false, true>), dim3(nb), dim3(bs), 0, s, P, G, io, W);
+  else
+    hipLaunchKernelGGL((k_adj_pgather<DIM, false, false>), dim3(nb), dim3(bs), 0, s, P, G, io, W);
   hipLaunchKernelGGL(k_adj_prim<DIM>, dim3(nb), dim3(bs), 0, s, P, G, W);
   const unsigned nc = (unsigned)((P.ncell + bs - 1) / bs);
   hipLaunchKernelGGL(k_adj_fold<DIM>, dim3(nc), dim3(bs), 0, s, P, G, io, W);
