@@ -652,7 +652,8 @@ __global__ void k_adj_fold(Params P, RefGrid G, AdjIO io, const double* __restri
   const bool zw = P.bcz[0] == BC_WALL;
   const int nzi = images(z, P.nz, P.bcz, zw, iz);
   double acc[NV];
-  for (int v = 0; v < NV; ++v) acc[v] = io.lam0[c + v * P.ncell];
+  // identity part of the update (b' = b + ...): lam^n starts from lam^{n+1}
+  for (int v = 0; v < NV; ++v) acc[v] = io.lam1[c + v * P.ncell];
   for (int a = 0; a < nzi; ++a)
     for (int b = 0; b < nyi; ++b)
       for (int d = 0; d < nxi; ++d) {
