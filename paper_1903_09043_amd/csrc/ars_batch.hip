@@ -24,8 +24,10 @@
 
 namespace ars {
 
+// Mutable per-instance record; the instance's Params live in a separate
+// read-only array of the table so the kernel reads them through a
+// non-aliased constant pointer (uniform loads) instead of a private copy.
 struct BatchInst {
-  Params P;
   double* U;
   double* tmp;
   double t;                       // in/out: accumulated time
@@ -57,15 +59,17 @@ __device__ double block_max(double v, double* red) {
 // rows of the workgroup take EY units per pass (rows past the last unit
 // march a copy that writes nothing).
 template <bool LM, bool DISS, int EX, int EY>
-__global__ void __launch_bounds__(EX* EY) k_batch(BatchInst* insts, const int* order, int nsteps) {
+__global__ void __launch_bounds__(EX* EY) k_batch(BatchInst* insts, const Params* __restrict__ params,
+                                                  const int* __restrict__ order, int nsteps) {
   constexpr int NPOS = EX * EY;
   using Ly = FusedLayout<2>;
   __shared__ double sm[Ly::TOTAL * NPOS];
   __shared__ double red[NPOS / 64];
   __shared__ unsigned long long badsh;
-  BatchInst* I = &insts[order[blockIdx.x]];
+  const int k = order[blockIdx.x];
+  BatchInst* I = &insts[k];
   if ((I->lm != 0) != LM || (I->diss != 0) != DISS) return;  // another variant's instance
-  const Params P = I->P;
+  const Params& P = params[k];
   const int tid = threadIdx.x;
   const int py = tid / EX;
   const int nxs = I->nxs;
@@ -123,7 +127,10 @@ namespace {
 constexpr int BEX = 64;  // positions per row segment (60 output columns)
 constexpr int BTX = BEX - 4;
 
-size_t table_bytes(int n) { return (size_t)n * sizeof(ars::BatchInst) + (size_t)n * sizeof(int) + 256; }
+// table: [BatchInst x n][Params x n][order: int x n]
+size_t params_offset(int n) { return ((size_t)n * sizeof(ars::BatchInst) + 255) / 256 * 256; }
+size_t order_offset(int n) { return params_offset(n) + ((size_t)n * sizeof(ars::Params) + 255) / 256 * 256; }
+size_t table_bytes(int n) { return order_offset(n) + (size_t)n * sizeof(int) + 256; }
 
 }  // namespace
 
@@ -151,26 +158,28 @@ int ars::batch_default_zc(const Params& P, int rows) {
 namespace {
 
 template <int EY>
-void launch_rows(ars_batch* b, ars::BatchInst* insts, const int* order, int nsteps, hipStream_t s) {
+void launch_rows(ars_batch* b, ars::BatchInst* insts, const ars::Params* params, const int* order, int nsteps,
+                 hipStream_t s) {
   const dim3 grid(b->n), block(BEX * EY);
   // each instance is advanced by the variant matching its (theta,
   // dissipation) flags; the other variants' workgroups return at once
   bool have[2][2] = {{false, false}, {false, false}};
   for (int k = 0; k < b->n; ++k) have[b->P[k].low_mach != 0][b->P[k].diss != 0] = true;
-  if (have[1][1]) hipLaunchKernelGGL((ars::k_batch<true, true, BEX, EY>), grid, block, 0, s, insts, order, nsteps);
-  if (have[1][0]) hipLaunchKernelGGL((ars::k_batch<true, false, BEX, EY>), grid, block, 0, s, insts, order, nsteps);
-  if (have[0][1]) hipLaunchKernelGGL((ars::k_batch<false, true, BEX, EY>), grid, block, 0, s, insts, order, nsteps);
-  if (have[0][0]) hipLaunchKernelGGL((ars::k_batch<false, false, BEX, EY>), grid, block, 0, s, insts, order, nsteps);
+  if (have[1][1]) hipLaunchKernelGGL((ars::k_batch<true, true, BEX, EY>), grid, block, 0, s, insts, params, order, nsteps);
+  if (have[1][0]) hipLaunchKernelGGL((ars::k_batch<true, false, BEX, EY>), grid, block, 0, s, insts, params, order, nsteps);
+  if (have[0][1]) hipLaunchKernelGGL((ars::k_batch<false, true, BEX, EY>), grid, block, 0, s, insts, params, order, nsteps);
+  if (have[0][0]) hipLaunchKernelGGL((ars::k_batch<false, false, BEX, EY>), grid, block, 0, s, insts, params, order, nsteps);
 }
 
 hipError_t launch_batch(ars_batch* b, void* table, int nsteps, hipStream_t s) {
   char* base = (char*)table;
   ars::BatchInst* insts = (ars::BatchInst*)base;
-  const int* order = (const int*)(base + (size_t)b->n * sizeof(ars::BatchInst));
+  const ars::Params* params = (const ars::Params*)(base + params_offset(b->n));
+  const int* order = (const int*)(base + order_offset(b->n));
   if (b->rows == 8)
-    launch_rows<8>(b, insts, order, nsteps, s);
+    launch_rows<8>(b, insts, params, order, nsteps, s);
   else
-    launch_rows<4>(b, insts, order, nsteps, s);
+    launch_rows<4>(b, insts, params, order, nsteps, s);
   return hipGetLastError();
 }
 
@@ -259,20 +268,21 @@ int ars_batch_bind(ars_batch* b, double* d_states, double* d_tmps, void* d_table
   if (!b || !d_states || !d_tmps || !d_table) return ARS_EINVAL;
   std::vector<char> h(table_bytes(b->n), 0);
   ars::BatchInst* insts = (ars::BatchInst*)h.data();
+  ars::Params* params = (ars::Params*)(h.data() + params_offset(b->n));
   for (int k = 0; k < b->n; ++k) {
     ars::BatchInst& I = insts[k];
-    I.P = b->P[k];
+    params[k] = b->P[k];
     I.U = d_states + b->off[k];
     I.tmp = d_tmps + b->off[k];
     I.t = 0.0;
     I.dt = 0.0;
     I.fault_cell = ~0ull;
-    I.nxs = ars::batch_segments(I.P);
+    I.nxs = ars::batch_segments(b->P[k]);
     I.zc = b->zc[k];
-    I.lm = I.P.low_mach;
-    I.diss = I.P.diss;
+    I.lm = b->P[k].low_mach;
+    I.diss = b->P[k].diss;
   }
-  std::memcpy(h.data() + (size_t)b->n * sizeof(ars::BatchInst), b->order.data(), (size_t)b->n * sizeof(int));
+  std::memcpy(h.data() + order_offset(b->n), b->order.data(), (size_t)b->n * sizeof(int));
   hipStream_t s = (hipStream_t)stream;
   if (hipMemcpyAsync(d_table, h.data(), h.size(), hipMemcpyHostToDevice, s) != hipSuccess) return ARS_EDEVICE;
   return hipStreamSynchronize(s) == hipSuccess ? ARS_OK : ARS_EDEVICE;
