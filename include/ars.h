@@ -200,6 +200,19 @@ int ars_step_adjoint(ars_ctx* ctx, const double* d_state_n, const double* d_lam_
 int ars_kinetic_energy(ars_ctx* ctx, const double* d_state, double* d_grad, double* d_ke, void* d_work,
                        void* stream);
 
+/* Nusselt-number objective at a fixed-temperature wall (side 0: bottom,
+ * 1: top of the gravity axis) of d_state into the device scalar *d_nu:
+ * the horizontal mean of the two-point wall conductive flux,
+ * 2 (T_wall - T_0)/dz at the bottom or 2 (T_{n-1} - T_wall)/dz at the top,
+ * times depth / (T_bottom - T_top) (the conductive profile gives 1; the
+ * quantity the diagnostics report as nu_bot / nu_top).  If d_grad is not
+ * NULL it receives dNu/dU in state layout (zero except on the
+ * wall-adjacent plane).  ARS_EINVAL unless the gravity axis has walls on
+ * both sides, that side is a fixed-T wall and the wall temperatures
+ * differ.  Uses the workspace's reduction area.  Asynchronous. */
+int ars_nusselt(ars_ctx* ctx, const double* d_state, int side, double* d_grad, double* d_nu, void* d_work,
+                void* stream);
+
 /* Binomial checkpointing plan (host only) for reversing n steps with s
  * snapshot slots, slot 0 holding U^0 and slots used as a stack.  Writes up
  * to cap actions of 4 int32 {op, step, arg, 0}:

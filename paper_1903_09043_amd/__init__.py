@@ -80,6 +80,7 @@ SIGNATURES = [
     ("ars_workspace_bytes_adjoint", C.c_size_t, [_VP]),
     ("ars_step_adjoint", C.c_int, [_VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
     ("ars_kinetic_energy", C.c_int, [_VP, _VP, _VP, _VP, _VP, _VP]),
+    ("ars_nusselt", C.c_int, [_VP, _VP, C.c_int, _VP, _VP, _VP, _VP]),
     ("ars_revolve_plan", C.c_int, [C.c_int, C.c_int, C.POINTER(C.c_int32), C.c_int, C.POINTER(C.c_int64)]),
     ("ars_revolve_cost", C.c_int64, [C.c_int, C.c_int]),
     ("ars_diagnostics", C.c_int, [_VP, _VP, _VP, C.POINTER(ArsDiag), _VP]),
@@ -322,6 +323,16 @@ class Solver:
         out = t.zeros(1, dtype=t.float64, device=self.device) if out is None else out
         _check(lib().ars_kinetic_energy(self.ctx.h, _ptr(U), _ptr(grad) if grad is not None else None, _ptr(out),
                                         _ptr(self.work), self.stream), "ars_kinetic_energy")
+        return out
+
+    def nusselt(self, side=0, U=None, grad=None, out=None):
+        """Device scalar Nusselt number at the bottom (side 0) or top (1)
+        fixed-T wall; fills grad (state layout) with dNu/dU when given."""
+        t = self.torch
+        U = self.U if U is None else U
+        out = t.zeros(1, dtype=t.float64, device=self.device) if out is None else out
+        _check(lib().ars_nusselt(self.ctx.h, _ptr(U), int(side), _ptr(grad) if grad is not None else None,
+                                 _ptr(out), _ptr(self.work), self.stream), "ars_nusselt")
         return out
 
     def diagnostics(self, raise_on_fault=True) -> dict:

@@ -3,7 +3,9 @@
 ``rb_kinetic_energy(dT0, mu, kappa, problem)`` is a ``torch.autograd.Function``:
 its forward runs ``problem.nsteps`` explicit steps of the all-regime scheme
 from the Rayleigh-Benard base state heated by the temperature perturbation
-``dT0`` and returns the final kinetic energy; its backward returns
+``dT0`` and returns the final kinetic energy (or, with
+``RBProblem(objective="nu_bot" / "nu_top")`` and ``rb_objective``, the final
+Nusselt number at the bottom / top wall); its backward returns
 dJ/d(dT0), dJ/dmu and dJ/dkappa.  The time step of every step is the one the
 forward run chose (the schedule is recorded and frozen: dt = CFL / max rate
 is not differentiated).  Intermediate states are not kept: the backward
@@ -31,7 +33,11 @@ class RBProblem:
     (dim, ...)) adds a fixed initial flow.  ``dt_sched`` (optional device
     tensor) replaces the CFL time steps by a given schedule."""
 
-    def __init__(self, cfg, prob, params, nsteps, slots, seed=0, u0=None, dt_sched=None, device="cuda"):
+    def __init__(self, cfg, prob, params, nsteps, slots, seed=0, u0=None, dt_sched=None, device="cuda",
+                 objective="kinetic_energy"):
+        if objective not in ("kinetic_energy", "nu_bot", "nu_top"):
+            raise ValueError(f"unknown objective {objective!r}")
+        self.objective = objective
         self.cfg = dict(cfg)
         self.nsteps = int(nsteps)
         self.slots = max(1, min(int(slots), self.nsteps))
@@ -69,7 +75,7 @@ class RBProblem:
         return U
 
 
-class _RBKineticEnergy(torch.autograd.Function):
+class _RBObjective(torch.autograd.Function):
     @staticmethod
     def forward(ctx, dT0, mu, kappa, problem):
         S = problem.solver(mu.item(), kappa.item())
@@ -84,7 +90,10 @@ class _RBKineticEnergy(torch.autograd.Function):
             log = torch.zeros(n, dtype=torch.float64, device=problem.device)
             S.step(n, dt_log=log)
         grad = torch.empty_like(S.U)
-        J = S.kinetic_energy(grad=grad).clone()
+        if problem.objective == "kinetic_energy":
+            J = S.kinetic_energy(grad=grad).clone()
+        else:
+            J = S.nusselt(0 if problem.objective == "nu_bot" else 1, grad=grad).clone()
         rc, cell = S.fault()
         if rc != 0:
             raise ArsError(rc, f"forward run (fault at cell {cell})")
@@ -118,15 +127,30 @@ class _RBKineticEnergy(torch.autograd.Function):
         return g_dT, pg[0].reshape(()), pg[1].reshape(()), None
 
 
+def rb_objective(dT0, mu, kappa, problem):
+    """J = problem.objective (final kinetic energy or Nusselt number) after
+    problem.nsteps steps from the base state with temperature perturbation
+    dT0 (differentiable in dT0, mu, kappa)."""
+    mu = torch.as_tensor(mu, dtype=torch.float64)
+    kappa = torch.as_tensor(kappa, dtype=torch.float64)
+    return _RBObjective.apply(dT0, mu, kappa, problem)
+
+
 def rb_kinetic_energy(dT0, mu, kappa, problem):
     """J = kinetic energy after problem.nsteps steps from the base state with
     temperature perturbation dT0 (differentiable in dT0, mu, kappa)."""
-    mu = torch.as_tensor(mu, dtype=torch.float64)
-    kappa = torch.as_tensor(kappa, dtype=torch.float64)
-    return _RBKineticEnergy.apply(dT0, mu, kappa, problem)
+    if problem.objective != "kinetic_energy":
+        raise ValueError("problem was built for another objective; use rb_objective")
+    return rb_objective(dT0, mu, kappa, problem)
 
 
 def rb_kinetic_energy_ra_pr(dT0, Ra, Pr, problem, **layer):
     """Same with the transport coefficients from (Ra, Pr) of the layer."""
     mu, kappa = workloads.ra_pr_to_mu_kappa(Ra, Pr, **layer)
     return rb_kinetic_energy(dT0, mu, kappa, problem)
+
+
+def rb_objective_ra_pr(dT0, Ra, Pr, problem, **layer):
+    """problem.objective with the transport coefficients from (Ra, Pr)."""
+    mu, kappa = workloads.ra_pr_to_mu_kappa(Ra, Pr, **layer)
+    return rb_objective(dT0, mu, kappa, problem)

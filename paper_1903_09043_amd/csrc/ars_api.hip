@@ -439,6 +439,21 @@ int ars_kinetic_energy(ars_ctx* ctx, const double* d_state, double* d_grad, doub
   return check(ars::launch_ke(ctx->P, d_state, d_grad, partials, d_ke, (hipStream_t)stream));
 }
 
+int ars_nusselt(ars_ctx* ctx, const double* d_state, int side, double* d_grad, double* d_nu, void* d_work,
+                void* stream) {
+  if (!ctx || !d_state || !d_nu || !d_work || (side != 0 && side != 1)) return ARS_EINVAL;
+  const ars_config& c = ctx->cfg;
+  const int z = c.dim - 1;
+  if (c.bc[z][0] != ARS_BC_WALL || c.bc[z][1] != ARS_BC_WALL || c.thermal[side] != ARS_T_FIXED) return ARS_EINVAL;
+  const double dT = c.T_wall[0] - c.T_wall[1];
+  if (!(dT != 0.0)) return ARS_EINVAL;
+  const double ncol = (double)ctx->P.nx * (double)ctx->P.ny;
+  const double C = (c.L[z] / dT) / ncol;
+  char* w = (char*)d_work;
+  double* partials = (double*)(w + CTL_BYTES);
+  return check(ars::launch_nusselt(ctx->P, side, C, d_state, d_grad, partials, d_nu, (hipStream_t)stream));
+}
+
 int ars_fault(ars_ctx* ctx, void* d_work, int64_t* fault_cell, void* stream) {
   if (!ctx || !d_work) return ARS_EINVAL;
   hipStream_t s = (hipStream_t)stream;

@@ -57,6 +57,8 @@ hipError_t launch_dt_finish(const Params& P, Control* ctl, int slot, double* d_d
 size_t diag_partial_bytes(const Params& P);
 hipError_t launch_diag(const Params& P, const double* U, double* partials, double* out, hipStream_t s);
 hipError_t launch_ke(const Params& P, const double* U, double* grad, double* partials, double* out, hipStream_t s);
+hipError_t launch_nusselt(const Params& P, int side, double C, const double* U, double* grad, double* partials,
+                          double* out, hipStream_t s);
 
 }  // namespace ars
 

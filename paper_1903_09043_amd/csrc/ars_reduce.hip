@@ -216,6 +216,84 @@ hipError_t launch_ke(const Params& P, const double* U, double* grad, double* par
   return hipGetLastError();
 }
 
+// ------------------------------------------------ Nusselt-number objective
+// Nu = C sum_cols 2 (T_w - T_0)/dz (bottom) or C sum_cols 2 (T_{n-1} - T_w)/dz
+// (top), C = depth / (dT ncol); optional gradient dNu/dU (zero except on the
+// wall-adjacent plane): with T = (gamma-1)(E - kin) / rho,
+// dT/dE = (gamma-1)/rho, dT/dm_k = -(gamma-1) u_k / rho,
+// dT/drho = (gamma-1)|u|^2/(2 rho) - T/rho.
+template <int DIM>
+__global__ void __launch_bounds__(256) k_nu(Params P, int side, double C, const double* __restrict__ U,
+                                           double* __restrict__ grad, double* partials) {
+  constexpr int NV = DIM + 2;
+  __shared__ double sh[256];
+  const long long plane = (long long)P.nx * P.ny;
+  const long long base = side == 0 ? 0 : plane * (P.nz - 1);
+  const double sgn = side == 0 ? -1.0 : 1.0;  // d(flux)/dT of the wall-adjacent cell
+  const double Tw = 0.5 * P.Tw2[side];
+  double acc = 0.0;
+  for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < plane;
+       c += (long long)gridDim.x * blockDim.x) {
+    const long long i = base + c;
+    double b[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) b[v] = U[i + v * P.ncell];
+    const Prim<DIM> q = cons_to_prim<DIM>(P, b);
+    const double f = side == 0 ? 2.0 * (Tw - q.T) / P.dx[2] : 2.0 * (q.T - Tw) / P.dx[2];
+    acc += f;
+    if (grad) {
+      const double dNdT = C * (sgn * 2.0 / P.dx[2]);
+      double uu = 0.0;
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) {
+        uu += q.u[k] * q.u[k];
+        grad[i + (1 + k) * P.ncell] = dNdT * (-(P.gm1 * q.u[k]) * q.r);
+      }
+      grad[i] = dNdT * ((0.5 * (P.gm1 * uu)) * q.r - q.T * q.r);
+      grad[i + (NV - 1) * P.ncell] = dNdT * (P.gm1 * q.r);
+    }
+  }
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partials[blockIdx.x] = sh[0];
+}
+
+__global__ void k_nu_final(int nb, double C, const double* partials, double* out) {
+  if (threadIdx.x == 0) {
+    double a = 0.0;
+    for (int b = 0; b < nb; ++b) a += partials[b];
+    *out = a * C;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_fill(double* p, long long n, double v) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+hipError_t launch_nusselt(const Params& P, int side, double C, const double* U, double* grad, double* partials,
+                          double* out, hipStream_t s) {
+  const long long plane = (long long)P.nx * P.ny;
+  long long nb = (plane + 255) / 256;
+  if (nb > DIAG_NB) nb = DIAG_NB;
+  if (grad) {
+    const long long n = (long long)(P.dim + 2) * P.ncell;
+    long long fb = (n + 255) / 256;
+    if (fb > 4096) fb = 4096;
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)fb), dim3(256), 0, s, grad, n, 0.0);
+  }
+  if (P.dim == 3)
+    hipLaunchKernelGGL(k_nu<3>, dim3((unsigned)nb), dim3(256), 0, s, P, side, C, U, grad, partials);
+  else
+    hipLaunchKernelGGL(k_nu<2>, dim3((unsigned)nb), dim3(256), 0, s, P, side, C, U, grad, partials);
+  hipLaunchKernelGGL(k_nu_final, dim3(1), dim3(64), 0, s, (int)nb, C, partials, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_diag(const Params& P, const double* U, double* partials, double* out, hipStream_t s) {
   long long nb = (P.ncell + 255) / 256;
   if (nb > DIAG_NB) nb = DIAG_NB;

@@ -172,3 +172,57 @@ def test_config5_gradient_vs_finite_differences(T):
         if errs[-1] <= 1e-5:
             break
     assert min(errs) <= 1e-5, errs
+
+
+def test_nusselt_objective(T):
+    """Nusselt number at both walls: value against the oracle's diagnostics,
+    gradient of the final Nu through the adjoint against central
+    differences (frozen schedule), and dNu/dU of the objective itself
+    against differences of the objective."""
+    import oracle as O
+    import paper_1903_09043_amd as A
+    from paper_1903_09043_amd.adjoint import RBProblem, rb_objective
+    cfg, prob, prm, seed = W.rb([12, 10, 8], [1.0, 1.0, 1.0], Ra=2e4, seed=3, amp=1e-2)
+    S = A.Solver(cfg).init(prob, prm, seed)
+    S.step(7)
+    g = T.empty_like(S.U)
+    nb = S.nusselt(0, grad=g).item()
+    nt = S.nusselt(1).item()
+    T.cuda.synchronize()
+    d = O.diag(cfg, S.numpy())
+    say("Nu bottom", nb, d["nu_bot"], "top", nt, d["nu_top"])
+    assert abs(nb - d["nu_bot"]) <= 1e-12 * abs(d["nu_bot"])
+    assert abs(nt - d["nu_top"]) <= 1e-12 * abs(d["nu_top"])
+    # dNu/dU of the objective against a central difference along a random direction
+    dU = T.tensor(np.random.default_rng(4).standard_normal(tuple(S.U.shape))).cuda() * S.U.abs() * 1e-3
+    h = 1e-3
+    fd = (S.nusselt(0, U=S.U + h * dU).item() - S.nusselt(0, U=S.U - h * dU).item()) / (2 * h)
+    ad = float((g * dU).sum().item())
+    say("dNu/dU fd", fd, "analytic", ad)
+    assert abs(fd - ad) <= 1e-7 * abs(fd)
+    for objective in ("nu_bot", "nu_top"):
+        pb = RBProblem(cfg, prob, prm, 10, 3, objective=objective)
+        rng = np.random.default_rng(6)
+        dT0 = (1e-2 * T.tensor(rng.standard_normal(pb.rho.shape))).cuda()
+        x = dT0.clone().requires_grad_()
+        J = rb_objective(x, cfg["mu"], cfg["kappa"], pb)
+        J.backward()
+        S2 = pb.solver(cfg["mu"], cfg["kappa"])
+        S2.U.copy_(pb.initial_state(dT0))
+        S2.compute_dt()
+        log = T.zeros(10, dtype=T.float64, device="cuda")
+        S2.step(10, dt_log=log)
+        pf = RBProblem(cfg, prob, prm, 10, 3, dt_sched=log, objective=objective)
+        for k in range(3):
+            dd = T.tensor(rng.standard_normal(pb.rho.shape)).cuda()
+            ad = float((x.grad * dd).sum().item())
+            errs = []
+            for hh in (1e-7, 1e-8):
+                with T.no_grad():
+                    fd = (rb_objective(dT0 + hh * dd, cfg["mu"], cfg["kappa"], pf).item()
+                          - rb_objective(dT0 - hh * dd, cfg["mu"], cfg["kappa"], pf).item()) / (2 * hh)
+                errs.append(abs(fd - ad) / max(abs(fd), abs(ad)))
+                say(objective, "direction", k, "h", hh, "fd", fd, "adjoint", ad, "rel", errs[-1])
+                if errs[-1] <= 1e-5:
+                    break
+            assert min(errs) <= 1e-5, (objective, k, errs)

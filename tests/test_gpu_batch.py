@@ -211,3 +211,44 @@ def test_autotune_and_cache(A, tmp_path):
     assert S2.autotune(trial_steps=2, cache_path=cache)["from_cache"] == 1
     lines = open(cache).read().splitlines()
     assert len(lines) == 2 and lines[0].startswith("batch:") and lines[1].startswith("step:")
+
+
+def test_batch_degenerate_instances(A):
+    """Instances one cell wide or tall, narrower than a row segment, or with
+    outflow sides, mixed with a regular one: bitwise equal to the
+    single-problem path after 30 steps, for both row counts."""
+    import torch
+    from tests import inputs as I
+
+    def cfg(n, L, bc, g=0.0, thermal=(0, 0), T_wall=(1.0, 1.0), lm=1):
+        return dict(dim=2, n=list(n), L=list(L), gamma=5.0 / 3.0, g=g, mu=2e-3, kappa=3e-3, K=1.1, cfl=0.4,
+                    low_mach=lm, dt_mode=0, bc=bc, wall_noslip=1, thermal=list(thermal), T_wall=list(T_wall))
+
+    cfgs = [cfg([1, 7], [0.2, 1.0], [[0, 0], [1, 1]], g=1.0, thermal=(1, 1), T_wall=(1.0, 0.5)),
+            cfg([5, 1], [1.0, 0.2], [[0, 0], [0, 0]]),
+            cfg([3, 2], [1.0, 1.0], [[2, 2], [2, 2]], lm=0),
+            cfg([61, 4], [2.0, 1.0], [[2, 2], [1, 1]], g=1.0, thermal=(1, 0), T_wall=(1.0, 0.5)),
+            W.rb([64, 32], [2.0, 1.0], Ra=1e4)[0]]
+    states = []
+    for k, c in enumerate(cfgs):
+        if c["g"] != 0.0:
+            U = O.init(c, W.PROB_RB, [c["T_wall"][0], c["T_wall"][1], -1.0, 1e-2], k)
+        else:
+            U = I.white_random(c, seed=k)
+        states.append(U)
+    for rows in (4, 8):
+        B = A.Batch(cfgs)
+        for k, U in enumerate(states):
+            B.view(k).copy_(torch.from_numpy(U))
+        B.set_tiling(rows).bind()
+        B.step(30)
+        torch.cuda.synchronize()
+        t, dt, fc, rc = B.read()
+        assert rc == 0
+        for k, (c, U) in enumerate(zip(cfgs, states)):
+            S = A.Solver(c)
+            S.set_state(U)
+            S.step(30)
+            torch.cuda.synchronize()
+            assert np.array_equal(B.view(k).cpu().numpy(), S.numpy()), (rows, k, c["n"])
+            assert t[k] == S.t.item() and dt[k] == S.dt.item()
