@@ -705,7 +705,9 @@ int orc_init(const orc_config* c, int problem, const double* prm, int nprm, uint
           ut = 0.0;
           p = p0 - 2.0 + 4.0 * std::log(2.0);
         }
-        double ux = -(ut * y) / r, uy = (ut * x) / r;
+        // u_theta vanishes at the centre (u_theta = 5 r), so the Cartesian
+        // components -u_theta y / r, u_theta x / r have the limit 0 there
+        double ux = r > 0.0 ? -(ut * y) / r : 0.0, uy = r > 0.0 ? (ut * x) / r : 0.0;
         const double rho = 1.0;
         U[cell] = rho;
         U[N + cell] = rho * ux;

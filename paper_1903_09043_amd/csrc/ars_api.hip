@@ -294,7 +294,8 @@ int ars_init_state_host(const ars_ctx* ctx, int problem, const double* prm, int 
             ut = 0.0;
             p = p0 - 2.0 + 4.0 * std::log(2.0);
           }
-          const double ux = -(ut * y) / r, uy = (ut * x) / r;
+          // u_theta = 5 r vanishes at the centre: velocity 0 there
+          const double ux = r > 0.0 ? -(ut * y) / r : 0.0, uy = r > 0.0 ? (ut * x) / r : 0.0;
           const long long cidx = i + (long long)P.nx * j;
           h[cidx] = 1.0;
           h[N + cidx] = 1.0 * ux;

@@ -61,7 +61,7 @@ def test_create_rejects_1d():
     assert e.value.status == A.EUNSUPPORTED
 
 
-@pytest.mark.parametrize("which", ["rb2d", "rb3d", "gresho", "sod", "iso", "uniform", "rb2d_seed"])
+@pytest.mark.parametrize("which", ["rb2d", "rb3d", "gresho", "gresho_odd", "sod", "iso", "uniform", "rb2d_seed"])
 def test_host_init_bitwise_equals_oracle(which):
     if which == "rb2d":
         cfg, prob, prm, seed = W.config1()
@@ -71,6 +71,8 @@ def test_host_init_bitwise_equals_oracle(which):
         cfg, prob, prm, seed = W.rb([12, 10, 9], [1.0, 1.0, 1.0], Ra=1e5, seed=5)
     elif which == "gresho":
         cfg, prob, prm, seed = W.gresho(n=96, Ma=1e-2)
+    elif which == "gresho_odd":  # a cell centre on the vortex centre
+        cfg, prob, prm, seed = W.gresho(n=33, Ma=1e-2)
     elif which == "sod":
         cfg = dict(dim=2, n=[100, 3], L=[1.0, 1.0], gamma=1.4, bc=[[2, 2], [0, 0]])
         prob, prm, seed = W.PROB_SOD, [], 0

@@ -493,3 +493,16 @@ def test_dense_adjoint_dot_product():
     lhs = np.sum(tl * lam)
     rhs = np.sum(dU * adj) + 0.3 * gmu - 0.2 * gk
     assert abs(lhs - rhs) <= 1e-12 * max(abs(lhs), 1.0)
+
+
+def test_gresho_centre_cell():
+    """Odd grid: one cell centre sits on the vortex centre, where the
+    velocity of the Gresho vortex (u_theta = 5 r, Sec. 4.2) is 0; the
+    state is finite and that cell is at rest with the centre pressure."""
+    cfg, prob, prm, seed = W.gresho(n=33, Ma=1e-2)
+    U = O.init(cfg, prob, prm, seed)
+    assert np.all(np.isfinite(U))
+    assert U[1, 16, 16] == 0.0 and U[2, 16, 16] == 0.0
+    g = cfg["gamma"]
+    p0 = 1.0 / (g * 1e-2 ** 2)
+    assert U[3, 16, 16] == p0 / (g - 1.0)
