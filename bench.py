@@ -292,6 +292,7 @@ def main():
                    "cells": ncell, "zchunk": S.ctx.zchunk()},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "measured_hbm_GBps": round(traffic / launch_s / 1e9, 1) if traffic else None,
                      "valu_view": valu_view(ms / args.steps, args.n)},
         "final_state": {"t": S.t.item(), "max_u": d["max_u"], "fault": d["fault"]},
     }
