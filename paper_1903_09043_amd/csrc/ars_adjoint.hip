@@ -10,8 +10,9 @@
 //   (update + flux)^T per face, all axes in one pass (transport + viscous +
 //   heat; the face flux adjoint is formed from lam^{n+1} on the fly)
 //   -> acoustic cell^T -> (face solver^T + primitive gather), each face's
-//   reverse evaluated by both of its cells -> (wall ghost + primitive)^T
-//   -> fold of periodic / outflow images onto interior cells.
+//   reverse evaluated by both of its cells -> fold onto interior cells of
+//   (wall ghost + primitive)^T evaluated at the cell and at each of its
+//   periodic / outflow images.
 // Only small per-face and per-cell adjoints go through memory between the
 // passes; quantities a later pass can form from its inputs are recomputed.
 // Non-smooth operations differentiate the branch the forward step took
@@ -28,17 +29,17 @@ enum {
   A_VL = A_FB + 6,         // 3 axes x (u_0, u_1, u_2, T) viscous adjoint to the left cell
   A_VR = A_VL + 12,        // same, right cell
   A_VT = A_VR + 12,        // 3 axes x (2 tangential axes x 2) tangential-gradient adjoints
-  A_PM = A_VT + 12,        // 3 axes x (mu, kappa) partial derivatives
-  A_CB = A_PM + 6,         // L, Am_0, Am_1, Am_2, AE, S-bar adjoints per cell
+  A_CB = A_VT + 12,        // L, Am_0, Am_1, Am_2, AE, S-bar adjoints per cell
   A_CONSB = A_CB + 6,      // 5: adjoint of the cell's conserved values through b~
   A_PB = A_CONSB + 5,      // rho, u_0, u_1, u_2, p, rho c, 1/(rho c), 1/c, T
-  A_UB = A_PB + 9,         // 5: adjoint of the (image) cell's conserved values
-  A_NFIELD = A_UB + 5
+  A_NFIELD = A_PB + 9
 };
 
 size_t adjoint_workspace_bytes(const Params& P) {
   RefGrid G = make_grid(P);
-  return (size_t)A_NFIELD * (size_t)G.npad * sizeof(double) + 4096;
+  // fields, then two partial sums (mu, kappa) per block of the flux reverse
+  const size_t nblk = (size_t)((G.npad + 255) / 256);
+  return (size_t)A_NFIELD * (size_t)G.npad * sizeof(double) + 2 * nblk * sizeof(double) + 256;
 }
 
 struct AdjIO {
@@ -112,7 +113,7 @@ __device__ __forceinline__ void face_gbar(const Params& P, const RefGrid& G, con
 template <int DIM, bool DISS>
 __device__ __forceinline__ void adj_flux_face(const Params& P, const RefGrid& G, const AdjIO& io, int a,
                                               double lama, long long i, int qx, int qy, int qz,
-                                              double* __restrict__ W) {
+                                              double* __restrict__ W, double& mu_acc, double& kappa_acc) {
   constexpr int NV = DIM + 2;
   const long long n = G.npad;
   if (!flux_range<DIM>(G, a, qx, qy, qz)) {
@@ -120,10 +121,6 @@ __device__ __forceinline__ void adj_flux_face(const Params& P, const RefGrid& G,
     // (read by the face solver's reverse and the parameter reduction)
     W[(A_FB + 2 * a + 0) * n + i] = 0.0;
     W[(A_FB + 2 * a + 1) * n + i] = 0.0;
-    if (DISS) {
-      W[(A_PM + 2 * a + 0) * n + i] = 0.0;
-      W[(A_PM + 2 * a + 1) * n + i] = 0.0;
-    }
     return;
   }
   const long long j = i + astride(G, a);
@@ -231,22 +228,44 @@ __device__ __forceinline__ void adj_flux_face(const Params& P, const RefGrid& G,
       W[(A_VT + 4 * a + 2 * s + 0) * n + i] = t >= 0 ? gb[t][dn] : 0.0;
       W[(A_VT + 4 * a + 2 * s + 1) * n + i] = t >= 0 ? gb[t][t] : 0.0;
     }
-    W[(A_PM + 2 * a + 0) * n + i] = mub;
-    W[(A_PM + 2 * a + 1) * n + i] = kappab;
+    mu_acc += mub;
+    kappa_acc += kappab;
   }
 }
 
+// One thread per padded cell, its three +faces; with dissipation the mu and
+// kappa partials of the block are summed in a fixed order into
+// partial[2 block + 0 / 1].
 template <int DIM, bool DISS>
-__global__ void k_adj_flux(Params P, RefGrid G, AdjIO io, double* __restrict__ W) {
+__global__ void __launch_bounds__(256) k_adj_flux(Params P, RefGrid G, AdjIO io, double* __restrict__ W,
+                                                  double* __restrict__ partial) {
+  __shared__ double sh[2][256];
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= G.npad) return;
-  int qx, qy, qz;
-  decode(G, i, qx, qy, qz);
-  const double dt = *io.dt;
+  double mu_acc = 0.0, kappa_acc = 0.0;
+  if (i < G.npad) {
+    int qx, qy, qz;
+    decode(G, i, qx, qy, qz);
+    const double dt = *io.dt;
 #pragma unroll
-  for (int t = 0; t < DIM; ++t) {
-    const int a = axis_of<DIM>(t);
-    adj_flux_face<DIM, DISS>(P, G, io, a, dt / P.dx[a], i, qx, qy, qz, W);
+    for (int t = 0; t < DIM; ++t) {
+      const int a = axis_of<DIM>(t);
+      adj_flux_face<DIM, DISS>(P, G, io, a, dt / P.dx[a], i, qx, qy, qz, W, mu_acc, kappa_acc);
+    }
+  }
+  if (!DISS) return;
+  sh[0][threadIdx.x] = mu_acc;
+  sh[1][threadIdx.x] = kappa_acc;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      sh[0][threadIdx.x] += sh[0][threadIdx.x + w];
+      sh[1][threadIdx.x] += sh[1][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    partial[2 * blockIdx.x] = sh[0][0];
+    partial[2 * blockIdx.x + 1] = sh[1][0];
   }
 }
 
@@ -556,18 +575,20 @@ __device__ void ghost_reverse(const Params& P, const double* W, long long n, lon
   }
 }
 
+// Conserved-value adjoint of padded position i (vertical index qz) from its
+// primitive adjoints, the reverse of the wall ghosts it builds and the
+// direct adjoint through b~.  Wall ghost positions carry none (their
+// adjoint goes to the interior cell they are built from).  Evaluated by the
+// fold for every image of an interior cell.
 template <int DIM>
-__global__ void k_adj_prim(Params P, RefGrid G, double* __restrict__ W) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= G.npad) return;
+__device__ __forceinline__ void prim_reverse(const Params& P, const RefGrid& G, const double* __restrict__ W,
+                                             long long i, int qz, double* Ub) {
   constexpr int NV = DIM + 2;
-  int qx, qy, qz;
-  decode(G, i, qx, qy, qz);
   const long long n = G.npad;
   const bool wlo = P.bcz[0] == BC_WALL, whi = P.bcz[1] == BC_WALL;
   const bool ghost = (qz < 2 && wlo) || (qz >= G.Pz - 2 && whi);
   if (ghost) {
-    for (int v = 0; v < 5; ++v) W[(A_UB + v) * n + i] = 0.0;
+    for (int v = 0; v < NV; ++v) Ub[v] = 0.0;
     return;
   }
   double rho_b = W[(A_PB + 0) * n + i];
@@ -613,12 +634,10 @@ __global__ void k_adj_prim(Params P, RefGrid G, double* __restrict__ W) {
     rb += ubt * mk;
   }
   rho_b += -rb * r * r;
-  double Ub[NV];
   Ub[0] = rho_b;
   for (int k = 0; k < DIM; ++k) Ub[1 + k] = mb[k];
   Ub[NV - 1] = Eb;
   for (int v = 0; v < NV; ++v) Ub[v] += W[(A_CONSB + v) * n + i];
-  for (int v = 0; v < 5; ++v) W[(A_UB + v) * n + i] = v < NV ? Ub[v] : 0.0;
 }
 
 // ------------------------------------------------ K7: fold onto interior ----
@@ -658,25 +677,25 @@ __global__ void k_adj_fold(Params P, RefGrid G, AdjIO io, const double* __restri
     for (int b = 0; b < nyi; ++b)
       for (int d = 0; d < nxi; ++d) {
         const long long q = G.pad(ix[d], iy[b], iz[a]);
-        for (int v = 0; v < NV; ++v) acc[v] += W[(A_UB + v) * n + q];
+        double Ub[NV];
+        prim_reverse<DIM>(P, G, W, q, iz[a], Ub);
+        for (int v = 0; v < NV; ++v) acc[v] += Ub[v];
       }
   for (int v = 0; v < NV; ++v) io.lam0[c + v * P.ncell] = acc[v];
 }
 
 // ----------------------------------------------- K8: parameter reduction ----
-template <int DIM>
-__global__ void __launch_bounds__(256) k_adj_params(RefGrid G, const double* __restrict__ W, double* partial) {
+// Sum of the per-block partials in a fixed order (thread-strided, then a
+// tree), added to pgrad.
+__global__ void __launch_bounds__(256) k_adj_params_final(int nb, const double* partial, double* pgrad) {
   __shared__ double sh[2][256];
-  double s0 = 0.0, s1 = 0.0;
-  const long long n = G.npad;
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
-    for (int a = 0; a < 3; ++a) {
-      if (DIM == 2 && a == 1) continue;  // no faces along the inactive axis
-      s0 += W[(A_PM + 2 * a + 0) * n + i];
-      s1 += W[(A_PM + 2 * a + 1) * n + i];
-    }
-  sh[0][threadIdx.x] = s0;
-  sh[1][threadIdx.x] = s1;
+  double a = 0.0, b = 0.0;
+  for (int k = threadIdx.x; k < nb; k += blockDim.x) {
+    a += partial[2 * k];
+    b += partial[2 * k + 1];
+  }
+  sh[0][threadIdx.x] = a;
+  sh[1][threadIdx.x] = b;
   __syncthreads();
   for (int w = 128; w >= 1; w >>= 1) {
     if ((int)threadIdx.x < w) {
@@ -686,20 +705,8 @@ __global__ void __launch_bounds__(256) k_adj_params(RefGrid G, const double* __r
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    partial[2 * blockIdx.x] = sh[0][0];
-    partial[2 * blockIdx.x + 1] = sh[1][0];
-  }
-}
-
-__global__ void k_adj_params_final(int nb, const double* partial, double* pgrad) {
-  if (threadIdx.x == 0) {
-    double a = 0.0, b = 0.0;
-    for (int k = 0; k < nb; ++k) {
-      a += partial[2 * k];
-      b += partial[2 * k + 1];
-    }
-    pgrad[0] += a;
-    pgrad[1] += b;
+    pgrad[0] += sh[0][0];
+    pgrad[1] += sh[1][0];
   }
 }
 
@@ -713,10 +720,11 @@ static hipError_t adjoint_t(const Params& P, const double* Un, const double* lam
   hipError_t e = launch_ref_forward(P, Un, wadj, d_dt, s);
   if (e != hipSuccess) return e;
   AdjIO io{lam1, lam0, d_dt, pgrad};
+  double* partial = W + (size_t)A_NFIELD * G.npad;  // 2 doubles per flux block
   if (P.diss)
-    hipLaunchKernelGGL((k_adj_flux<DIM, true>), dim3(nb), dim3(bs), 0, s, P, G, io, W);
+    hipLaunchKernelGGL((k_adj_flux<DIM, true>), dim3(nb), dim3(bs), 0, s, P, G, io, W, partial);
   else
-    hipLaunchKernelGGL((k_adj_flux<DIM, false>), dim3(nb), dim3(bs), 0, s, P, G, io, W);
+    hipLaunchKernelGGL((k_adj_flux<DIM, false>), dim3(nb), dim3(bs), 0, s, P, G, io, W, partial);
   hipLaunchKernelGGL(k_adj_cell<DIM>, dim3(nb), dim3(bs), 0, s, P, G, io, W);
   if (P.diss && P.low_mach)
     hipLaunchKernelGGL((k_adj_pgather<DIM, true, true>), dim3(nb), dim3(bs), 0, s, P, G, io, W);
@@ -726,15 +734,9 @@ static hipError_t adjoint_t(const Params& P, const double* Un, const double* lam
     hipLaunchKernelGGL((k_adj_pgather<DIM, false, true>), dim3(nb), dim3(bs), 0, s, P, G, io, W);
   else
     hipLaunchKernelGGL((k_adj_pgather<DIM, false, false>), dim3(nb), dim3(bs), 0, s, P, G, io, W);
-  hipLaunchKernelGGL(k_adj_prim<DIM>, dim3(nb), dim3(bs), 0, s, P, G, W);
   const unsigned nc = (unsigned)((P.ncell + bs - 1) / bs);
   hipLaunchKernelGGL(k_adj_fold<DIM>, dim3(nc), dim3(bs), 0, s, P, G, io, W);
-  if (P.diss && pgrad) {
-    double* partial = W + (size_t)A_NFIELD * G.npad;  // 4096 bytes after the fields: 256 blocks x 2
-    const int npb = 256;
-    hipLaunchKernelGGL(k_adj_params<DIM>, dim3(npb), dim3(256), 0, s, G, W, partial);
-    hipLaunchKernelGGL(k_adj_params_final, dim3(1), dim3(64), 0, s, npb, partial, pgrad);
-  }
+  if (P.diss && pgrad) hipLaunchKernelGGL(k_adj_params_final, dim3(1), dim3(256), 0, s, (int)nb, partial, pgrad);
   return hipGetLastError();
 }
 
