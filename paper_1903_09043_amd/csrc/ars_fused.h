@@ -2,6 +2,7 @@
 // the single-problem step kernel and the batched kernel.
 #pragma once
 #include "ars_dev.h"
+
 #include "ars_internal.h"
 
 namespace ars {
@@ -70,6 +71,12 @@ __device__ __forceinline__ void march_tile(const Params& P, const double* __rest
   constexpr int NV = DIM + 2;
   constexpr int NPOS = EX * EY;
   constexpr int TX = EX - 4;
+  // 2D: every wave is a row segment whose only halo lanes are its two ends,
+  // so the stages run on all lanes (results of halo lanes are discarded,
+  // their LDS slots never read by a needed position) and the code stays
+  // branch-free; 3D keeps the per-position guards that let whole halo
+  // waves skip stages.
+  constexpr bool UNI = (DIM == 2);
   constexpr int TY = (DIM == 3) ? EY - 4 : 1;
   constexpr int Z = DIM - 1;  // index of the vertical velocity component
   using Ly = FusedLayout<DIM>;
@@ -183,7 +190,7 @@ __device__ __forceinline__ void march_tile(const Params& P, const double* __rest
     __syncthreads();  // ---------------------------------------------- bar 1
 
     // ================= step 2a: acoustic cell values of plane p-1 ===========
-    const bool doL = (p - 1 >= z0 - 1) && (p - 1 <= z1) && needL;
+    const bool doL = (p - 1 >= z0 - 1) && (p - 1 <= z1) && (UNI || needL);
     if (doL) {
       double Lc = 1.0;
       // x faces: +x own (registers), -x from the left neighbour
@@ -250,7 +257,7 @@ __device__ __forceinline__ void march_tile(const Params& P, const double* __rest
 
     // tangential differences of plane p-1 (for vertical viscous faces)
     double dX1[4] = {0.0, 0.0, 0.0, 0.0};
-    if (DISS && lat_out) {
+    if (DISS && (UNI || lat_out)) {
       // 3D: dx ux, dx uz, dy uy, dy uz ; 2D: dx ux, dx uy
       dX1[0] = sm[(Ly::V + 0) * NPOS + pxp] - sm[(Ly::V + 0) * NPOS + pxm];
       dX1[1] = sm[(Ly::V + Z) * NPOS + pxp] - sm[(Ly::V + Z) * NPOS + pxm];
@@ -265,10 +272,10 @@ __device__ __forceinline__ void march_tile(const Params& P, const double* __rest
     // GX slot (an output cell or its -x/-y neighbour) has it computed
     double GXn[NV], GYn[NV];
     const bool doG = (p - 1 >= z0) && (p - 1 < z1);
-    if (doG && (needGx || needGy)) {
+    if (doG && (UNI || needGx || needGy)) {
 #pragma unroll
       for (int dir = 0; dir < DIM - 1; ++dir) {
-        if (!(dir == 0 ? needGx : needGy)) continue;
+        if (!UNI && !(dir == 0 ? needGx : needGy)) continue;
         const int nb = dir == 0 ? pxp : pyp;
         const double us = Fo1[3 * dir + 0];
         const double pi = Fo1[3 * dir + 1];
@@ -350,7 +357,7 @@ __device__ __forceinline__ void march_tile(const Params& P, const double* __rest
     double Gz[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) Gz[v] = 0.0;
-    const bool doGz = (p - 1 >= z0) && (p - 1 <= z1) && lat_out;
+    const bool doGz = (p - 1 >= z0) && (p - 1 <= z1) && (UNI || lat_out);
     if (doGz) {
       const bool wall = wall_face_below(P, zs + p - 2);
       double tr[NV];
@@ -434,11 +441,11 @@ __device__ __forceinline__ void march_tile(const Params& P, const double* __rest
     __syncthreads();  // ---------------------------------------------- bar 3
 
     // ================= step 4: publish lateral fluxes of plane p-1 ==========
-    if (doG && needGx) {
+    if (doG && (UNI || needGx)) {
 #pragma unroll
       for (int v = 0; v < NV; ++v) sm[(Ly::GX + v) * NPOS + tid] = GXn[v];
     }
-    if (DIM == 3 && doG && needGy) {
+    if (DIM == 3 && doG && (UNI || needGy)) {
 #pragma unroll
       for (int v = 0; v < NV; ++v) sm[(Ly::GX + NV + v) * NPOS + tid] = GYn[v];
     }
