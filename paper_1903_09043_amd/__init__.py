@@ -389,8 +389,8 @@ class Batch:
 
     def __del__(self):
         h = getattr(self, "h", None)
-        if h is not None and h.value:
-            lib().ars_batch_destroy(h)
+        if h is not None and h.value and _lib is not None:
+            _lib.ars_batch_destroy(h)
             self.h = None
 
     @property
