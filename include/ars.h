@@ -83,6 +83,13 @@ enum {
  *             flips (free slip).
  *  thermal[s], T_wall[s]  bottom / top wall: adiabatic (T_ghost = T) or
  *             fixed temperature (T_ghost = 2 T_wall - T).
+ *  energy_form 0: the scheme of eq. all_regime_scheme on the total energy
+ *             E + rho Phi with the relaxation of the potential (Sec. 2.1.4);
+ *             1: the non-conservative energy scheme of App. B (energy
+ *             without the potential, source (uS)_i = (u*_{i+1/2} S_{i+1/2} +
+ *             u*_{i-1/2} S_{i-1/2})/2 along the gravity axis, no relaxation
+ *             step).  With g = 0 the two coincide.  The adjoint step
+ *             supports energy_form 0 only.
  */
 typedef struct ars_config {
   int32_t dim;
@@ -95,6 +102,8 @@ typedef struct ars_config {
   int32_t wall_noslip;
   int32_t thermal[2];
   double T_wall[2];
+  int32_t energy_form;
+  int32_t pad_;
 } ars_config;
 
 /* Diagnostics of a state (Sec. 4 reports max velocity, mean absolute

@@ -27,7 +27,10 @@
 //                         Stokes hypothesis, Fourier law.
 //   O8 update          -- eq. (all_regime_scheme) summed over directions,
 //                         then the relaxation step Psi^{n+1} = Phi (Sec.
-//                         2.1.4) realised as E = calE - rho Phi.
+//                         2.1.4) realised as E = calE - rho Phi; or, with
+//                         energy_form = 1, the non-conservative energy
+//                         scheme of App. B (energy without the potential,
+//                         source (uS)_i, no relaxation step).
 //   O9 validity        -- L > 0, rho > 0, p > 0, finite.
 //
 // Multi-dimensional form: unsplit (every face from U^n with one dt, L sums
@@ -113,6 +116,8 @@ typedef struct orc_config {
   int32_t wall_noslip;
   int32_t thermal[2];
   double T_wall[2];
+  int32_t energy_form;  // 0: total energy with the relaxed potential; 1: App. B
+  int32_t pad_;
 } orc_config;
 }
 
@@ -353,6 +358,11 @@ int step_impl(const orc_config& c, const S* U, S* Uout, double dt, S mu, S kappa
   A.L.assign(NP, S(1.0));
   A.bt.assign((size_t)nv * NP, S(0.0));
   std::vector<S> Sbar(NP, S(0.0));
+  // App. B (non-conservative energy): no relaxation of the potential; the
+  // energy's acoustic update carries the source (uS)_i = (u*_{i+1/2}
+  // S_{i+1/2} + u*_{i-1/2} S_{i-1/2}) / 2 of the gravity axis.
+  const bool nc = c.energy_form == 1;
+  std::vector<S> uSbar(nc ? NP : 0, S(0.0));
 #pragma omp parallel for schedule(static)
   for (int q2 = (D > 2 ? 1 : 0); q2 < (D > 2 ? G.P[2] - 1 : 1); ++q2)
     for (int q1 = (D > 1 ? 1 : 0); q1 < (D > 1 ? G.P[1] - 1 : 1); ++q1)
@@ -373,7 +383,17 @@ int step_impl(const orc_config& c, const S* U, S* Uout, double dt, S mu, S kappa
         S AE = S(lam[0]) * (A.face[0][p].P - A.face[0][p - stride[0]].P);
         for (int d = 1; d < D; ++d) AE = AE + S(lam[d]) * (A.face[d][p].P - A.face[d][p - stride[d]].P);
         S rho = st.cons[0 * NP + p];
-        S calE = st.cons[(1 + D) * NP + p] + rho * S(st.phi[q[z]]);
+        S calE;
+        if (nc) {
+          const Face<S>& fu = A.face[z][p];
+          const Face<S>& fd = A.face[z][p - stride[z]];
+          S uS = S(0.5) * (fu.ustar * fu.S_ + fd.ustar * fd.S_);
+          uSbar[p] = uS;
+          AE = AE - S(lam[z]) * uS;
+          calE = st.cons[(1 + D) * NP + p];
+        } else {
+          calE = st.cons[(1 + D) * NP + p] + rho * S(st.phi[q[z]]);
+        }
         S iL = S(1.0) / Lc;
         A.L[p] = Lc;
         A.bt[0 * NP + p] = rho * iL;
@@ -465,10 +485,15 @@ int step_impl(const orc_config& c, const S* U, S* Uout, double dt, S mu, S kappa
           if (kk == z) v = v + S(lam[z]) * Sbar[p];
           nm[kk] = v;
         }
-        S calE = st.cons[(1 + D) * NP + p] + rho * phic;
+        S calE = nc ? st.cons[(1 + D) * NP + p] : st.cons[(1 + D) * NP + p] + rho * phic;
         for (int d = 0; d < D; ++d)
           calE = calE - S(lam[d]) * (A.Gf[d][(1 + D) * NP + p] - A.Gf[d][(1 + D) * NP + p - stride[d]]);
-        S nE = calE - nr * phic;
+        S nE;
+        if (nc) {
+          nE = calE + S(lam[z]) * uSbar[p];
+        } else {
+          nE = calE - nr * phic;
+        }
         Uout[0 * G.ncell + cell] = nr;
         for (int kk = 0; kk < D; ++kk) Uout[(1 + kk) * G.ncell + cell] = nm[kk];
         Uout[(1 + D) * G.ncell + cell] = nE;
@@ -548,6 +573,7 @@ int orc_validate(const orc_config* c) {
   if (!(c->gamma > 1.0) || !(c->mu >= 0.0) || !(c->kappa >= 0.0) || !(c->K >= 1.0) || !(c->cfl > 0.0))
     return ORC_EINVAL;
   if (c->dt_mode != 0 && c->dt_mode != 1) return ORC_EINVAL;
+  if (c->energy_form != 0 && c->energy_form != 1) return ORC_EINVAL;
   return ORC_OK;
 }
 

@@ -39,6 +39,8 @@ class ArsConfig(C.Structure):
         ("wall_noslip", C.c_int32),
         ("thermal", C.c_int32 * 2),
         ("T_wall", C.c_double * 2),
+        ("energy_form", C.c_int32),
+        ("pad_", C.c_int32),
     ]
 
 
@@ -147,6 +149,7 @@ def make_config(cfg: dict) -> ArsConfig:
     c.thermal[0], c.thermal[1] = int(th[0]), int(th[1])
     tw = cfg.get("T_wall", [1.0, 1.0])
     c.T_wall[0], c.T_wall[1] = float(tw[0]), float(tw[1])
+    c.energy_form = int(cfg.get("energy_form", 0))
     return c
 
 

@@ -86,6 +86,7 @@ ars::Params derive(const ars_config* c) {
   P.dt_mode = c->dt_mode;
   P.low_mach = c->low_mach;
   P.diss = (c->mu > 0.0 || c->kappa > 0.0) ? 1 : 0;
+  P.nc = c->energy_form == 1 ? 1 : 0;
   return P;
 }
 
@@ -129,6 +130,7 @@ int ars_validate(const ars_config* c) {
       !std::isfinite(c->cfl) || !std::isfinite(c->gamma))
     return ARS_EINVAL;
   if (c->dt_mode != 0 && c->dt_mode != 1) return ARS_EINVAL;
+  if (c->energy_form != 0 && c->energy_form != 1) return ARS_EINVAL;
   if (c->low_mach != 0 && c->low_mach != 1) return ARS_EINVAL;
   for (int s = 0; s < 2; ++s)
     if (c->thermal[s] != ARS_T_ADIABATIC && c->thermal[s] != ARS_T_FIXED) return ARS_EINVAL;
@@ -428,6 +430,7 @@ int ars_step_adjoint(ars_ctx* ctx, const double* d_state_n, const double* d_lam_
                      const double* d_dt, double* d_param_grad, void* d_work_adj, void* stream) {
   if (!ctx || !d_state_n || !d_lam_np1 || !d_lam_n || !d_dt || !d_work_adj || d_lam_n == d_lam_np1)
     return ARS_EINVAL;
+  if (ctx->P.nc) return ARS_EUNSUPPORTED;  // the reverse of the App. B energy form is not built
   return check(ars::launch_step_adjoint(ctx->P, d_state_n, d_lam_np1, d_lam_n, d_dt, d_param_grad, d_work_adj,
                                         (hipStream_t)stream));
 }

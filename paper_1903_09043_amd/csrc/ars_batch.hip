@@ -35,7 +35,7 @@ struct BatchInst {
   unsigned long long fault_cell;  // out: smallest faulting cell (~0: none)
   int nxs;                        // x segments of TX columns
   int zc;                         // vertical chunks (divides nz)
-  int lm, diss;
+  int lm, diss, nc, pad_;
 };
 
 template <int NPOS>
@@ -58,7 +58,7 @@ __device__ double block_max(double v, double* red) {
 // nxs * zc units (x segment, vertical chunk) of equal plane count; the EY
 // rows of the workgroup take EY units per pass (rows past the last unit
 // march a copy that writes nothing).
-template <bool LM, bool DISS, int EX, int EY>
+template <bool LM, bool DISS, bool NC, int EX, int EY>
 __global__ void __launch_bounds__(EX* EY) k_batch(BatchInst* insts, const Params* __restrict__ params,
                                                   const int* __restrict__ order, int nsteps) {
   constexpr int NPOS = EX * EY;
@@ -68,7 +68,7 @@ __global__ void __launch_bounds__(EX* EY) k_batch(BatchInst* insts, const Params
   __shared__ unsigned long long badsh;
   const int k = order[blockIdx.x];
   BatchInst* I = &insts[k];
-  if ((I->lm != 0) != LM || (I->diss != 0) != DISS) return;  // another variant's instance
+  if ((I->lm != 0) != LM || (I->diss != 0) != DISS || (I->nc != 0) != NC) return;  // another variant's instance
   const Params& P = params[k];
   const int tid = threadIdx.x;
   const int py = tid / EX;
@@ -100,7 +100,7 @@ __global__ void __launch_bounds__(EX* EY) k_batch(BatchInst* insts, const Params
       const bool live = u < units;
       const int tx = live ? u % nxs : nxs;  // past the last segment: no output
       const int zs = live ? (u / nxs) * chunk : 0;
-      march_tile<2, LM, DISS, EX, EY>(P, src, dst, sm, tx, 0, zs, 0, chunk, lamx, 0.0, lamz, lmax, bad);
+      march_tile<2, LM, DISS, NC, EX, EY>(P, src, dst, sm, tx, 0, zs, 0, chunk, lamx, 0.0, lamz, lmax, bad);
     }
     rate = block_max<NPOS>(lmax, red);  // its barriers complete the new state
     t = t + dt;
@@ -157,18 +157,29 @@ int ars::batch_default_zc(const Params& P, int rows) {
 
 namespace {
 
+template <bool NC, int EY>
+void launch_rows_nc(ars_batch* b, ars::BatchInst* insts, const ars::Params* params, const int* order, int nsteps,
+                    const bool (&have)[2][2][2], hipStream_t s) {
+  const dim3 grid(b->n), block(BEX * EY);
+  if (have[NC][1][1])
+    hipLaunchKernelGGL((ars::k_batch<true, true, NC, BEX, EY>), grid, block, 0, s, insts, params, order, nsteps);
+  if (have[NC][1][0])
+    hipLaunchKernelGGL((ars::k_batch<true, false, NC, BEX, EY>), grid, block, 0, s, insts, params, order, nsteps);
+  if (have[NC][0][1])
+    hipLaunchKernelGGL((ars::k_batch<false, true, NC, BEX, EY>), grid, block, 0, s, insts, params, order, nsteps);
+  if (have[NC][0][0])
+    hipLaunchKernelGGL((ars::k_batch<false, false, NC, BEX, EY>), grid, block, 0, s, insts, params, order, nsteps);
+}
+
 template <int EY>
 void launch_rows(ars_batch* b, ars::BatchInst* insts, const ars::Params* params, const int* order, int nsteps,
                  hipStream_t s) {
-  const dim3 grid(b->n), block(BEX * EY);
-  // each instance is advanced by the variant matching its (theta,
-  // dissipation) flags; the other variants' workgroups return at once
-  bool have[2][2] = {{false, false}, {false, false}};
-  for (int k = 0; k < b->n; ++k) have[b->P[k].low_mach != 0][b->P[k].diss != 0] = true;
-  if (have[1][1]) hipLaunchKernelGGL((ars::k_batch<true, true, BEX, EY>), grid, block, 0, s, insts, params, order, nsteps);
-  if (have[1][0]) hipLaunchKernelGGL((ars::k_batch<true, false, BEX, EY>), grid, block, 0, s, insts, params, order, nsteps);
-  if (have[0][1]) hipLaunchKernelGGL((ars::k_batch<false, true, BEX, EY>), grid, block, 0, s, insts, params, order, nsteps);
-  if (have[0][0]) hipLaunchKernelGGL((ars::k_batch<false, false, BEX, EY>), grid, block, 0, s, insts, params, order, nsteps);
+  // each instance is advanced by the variant matching its (energy form,
+  // theta, dissipation) flags; the other variants' workgroups return at once
+  bool have[2][2][2] = {};
+  for (int k = 0; k < b->n; ++k) have[b->P[k].nc != 0][b->P[k].low_mach != 0][b->P[k].diss != 0] = true;
+  launch_rows_nc<false, EY>(b, insts, params, order, nsteps, have, s);
+  launch_rows_nc<true, EY>(b, insts, params, order, nsteps, have, s);
 }
 
 hipError_t launch_batch(ars_batch* b, void* table, int nsteps, hipStream_t s) {
@@ -281,6 +292,7 @@ int ars_batch_bind(ars_batch* b, double* d_states, double* d_tmps, void* d_table
     I.zc = b->zc[k];
     I.lm = b->P[k].low_mach;
     I.diss = b->P[k].diss;
+    I.nc = b->P[k].nc;
   }
   std::memcpy(h.data() + order_offset(b->n), b->order.data(), (size_t)b->n * sizeof(int));
   hipStream_t s = (hipStream_t)stream;

@@ -28,6 +28,7 @@ struct Params {
   int dt_mode;
   int low_mach;
   int diss;             // mu > 0 || kappa > 0
+  int nc;               // 1: non-conservative energy scheme (App. B)
 };
 
 // Workspace control block (first 256 bytes of the workspace).

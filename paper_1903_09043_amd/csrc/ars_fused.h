@@ -62,7 +62,7 @@ __device__ __forceinline__ bool wall_face_below(const Params& P, int q) {
 // segment of TX columns with its own tile and shift (plane p of the march
 // is plane zs + p of the grid), so a workgroup can advance several
 // segments or vertical chunks of one problem at once.
-template <int DIM, bool LM, bool DISS, int EX, int EY>
+template <int DIM, bool LM, bool DISS, bool NC, int EX, int EY>
 __device__ __forceinline__ void march_tile(const Params& P, const double* __restrict__ Uin,
                                            double* __restrict__ Uout, double* __restrict__ sm, const int tx,
                                            const int ty, const int zs, const int z0, const int z1,
@@ -125,6 +125,7 @@ __device__ __forceinline__ void march_tile(const Params& P, const double* __rest
   double zBus = 0, zBpi = 0, zBP = 0, zBS = 0;  // z face (p-1|p)
   double bt1[NV], bt2[NV];        // b~ of planes p-1, p-2
   double sb1 = 0.0, sb2 = 0.0;    // S-bar of planes p-1, p-2
+  double uS1 = 0.0, uS2 = 0.0;    // (uS)_i of planes p-1, p-2 (non-conservative energy)
   double GzLo[NV];                // z-face flux (p-3|p-2)
   double Fo1[3 * (DIM - 1)];      // own lateral acoustic faces of plane p-1
   double dX2[4];                  // tangential differences at plane p-2
@@ -215,7 +216,17 @@ __device__ __forceinline__ void march_tile(const Params& P, const double* __rest
       dpz = dpz - sb;
       const double Amz = lamz * dpz;
       AE = AE + lamz * (zBP - zAP);
-      const double calE = U1[NV - 1] + U1[0] * phi1;
+      double calE;
+      if (NC) {
+        // App. B: the energy excludes the potential and its acoustic update
+        // carries the source (uS)_i of the two vertical faces
+        const double uS = 0.5 * (zBus * zBS + zAus * zAS);
+        uS1 = uS;
+        AE = AE - lamz * uS;
+        calE = U1[NV - 1];
+      } else {
+        calE = U1[NV - 1] + U1[0] * phi1;
+      }
       const double iL = 1.0 / Lc;
       bt1[0] = U1[0] * iL;
       bt1[1] = (U1[1] - Amx) * iL;
@@ -413,7 +424,7 @@ __device__ __forceinline__ void march_tile(const Params& P, const double* __rest
       for (int v = 0; v < NV; ++v) {
         const double gxo = sm[(Ly::GX + v) * NPOS + tid];
         const double gxm = sm[(Ly::GX + v) * NPOS + pxm];
-        double s = (v == NV - 1) ? U2[NV - 1] + U2[0] * phi2 : U2[v];
+        double s = (v == NV - 1) ? (NC ? U2[NV - 1] : U2[NV - 1] + U2[0] * phi2) : U2[v];
         s = s - lamx * (gxo - gxm);
         if (DIM == 3) {
           const double gyo = sm[(Ly::GX + NV + v) * NPOS + tid];
@@ -422,9 +433,10 @@ __device__ __forceinline__ void march_tile(const Params& P, const double* __rest
         }
         s = s - lamz * (Gz[v] - GzLo[v]);
         if (v == 1 + Z) s = s + lamz * sb2;
+        if (NC && v == NV - 1) s = s + lamz * uS2;
         nb[v] = s;
       }
-      nb[NV - 1] = nb[NV - 1] - nb[0] * phi2;
+      if (!NC) nb[NV - 1] = nb[NV - 1] - nb[0] * phi2;  // relaxation step: E = calE - rho Phi
       const long long cell = col + plane_stride * (zs + o);
 #pragma unroll
       for (int v = 0; v < NV; ++v) Uout[cell + v * N] = nb[v];
@@ -463,6 +475,7 @@ __device__ __forceinline__ void march_tile(const Params& P, const double* __rest
     }
     zAus = zBus; zApi = zBpi; zAP = zBP; zAS = zBS;
     sb2 = sb1;
+    uS2 = uS1;
 #pragma unroll
     for (int i = 0; i < 3 * (DIM - 1); ++i) Fo1[i] = Fn[i];
 #pragma unroll

@@ -27,7 +27,7 @@
 
 namespace ars {
 
-template <int DIM, bool LM, bool DISS, int EX, int EY>
+template <int DIM, bool LM, bool DISS, bool NC, int EX, int EY>
 __global__ void __launch_bounds__(EX* EY) k_step_fused(Params P, const double* __restrict__ Uin,
                                                        double* __restrict__ Uout, StepIO io) {
   constexpr int NPOS = EX * EY;
@@ -70,7 +70,7 @@ __global__ void __launch_bounds__(EX* EY) k_step_fused(Params P, const double* _
     cur += z1 - z0;
     const int tx = (DIM == 3) ? tile % io.ntx : tile * EY + (int)threadIdx.x / EX;
     const int ty = (DIM == 3) ? tile / io.ntx : 0;
-    march_tile<DIM, LM, DISS, EX, EY>(P, Uin, Uout, sm, tx, ty, 0, z0, z1, lamx, lamy, lamz, lmax, badcell);
+    march_tile<DIM, LM, DISS, NC, EX, EY>(P, Uin, Uout, sm, tx, ty, 0, z0, z1, lamx, lamy, lamz, lmax, badcell);
   }
 
   // ---- workgroup reduction of the new-state rate, fault latch --------------
@@ -98,7 +98,7 @@ __global__ void __launch_bounds__(EX* EY) k_step_fused(Params P, const double* _
 // --------------------------------------------------------------------------
 // Host-side launch
 // --------------------------------------------------------------------------
-template <int DIM, bool LM, bool DISS, int EX, int EY>
+template <int DIM, bool LM, bool DISS, bool NC, int EX, int EY>
 static hipError_t launch_fused_t(const Params& P, const double* Uin, double* Uout, StepIO io, const TileShape& ts,
                                  hipStream_t s) {
   constexpr int TX = EX - 4;
@@ -112,7 +112,7 @@ static hipError_t launch_fused_t(const Params& P, const double* Uin, double* Uou
   static int occ = 0;  // resident blocks per CU of this instance
   if (occ == 0) {
     int o = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, k_step_fused<DIM, LM, DISS, EX, EY>, EX * EY, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, k_step_fused<DIM, LM, DISS, NC, EX, EY>, EX * EY, 0) !=
             hipSuccess ||
         o < 1)
       o = 1;
@@ -129,24 +129,28 @@ static hipError_t launch_fused_t(const Params& P, const double* Uin, double* Uou
   const long long by_chunk = (total + ts.zchunk - 1) / ts.zchunk;
   if (by_chunk < nwg) nwg = by_chunk;
   if (nwg < 1) nwg = 1;
-  hipLaunchKernelGGL((k_step_fused<DIM, LM, DISS, EX, EY>), dim3((unsigned)nwg), dim3(EX * EY), 0, s, P, Uin, Uout,
+  hipLaunchKernelGGL((k_step_fused<DIM, LM, DISS, NC, EX, EY>), dim3((unsigned)nwg), dim3(EX * EY), 0, s, P, Uin, Uout,
                      io);
   return hipGetLastError();
 }
 
+template <int DIM, bool NC, int EX, int EY>
+static hipError_t launch_variant(const Params& P, const double* Uin, double* Uout, StepIO io, const TileShape& ts,
+                                 hipStream_t s) {
+  const bool lm = P.low_mach != 0, ds = P.diss != 0;
+  if (lm && ds) return launch_fused_t<DIM, true, true, NC, EX, EY>(P, Uin, Uout, io, ts, s);
+  if (lm && !ds) return launch_fused_t<DIM, true, false, NC, EX, EY>(P, Uin, Uout, io, ts, s);
+  if (!lm && ds) return launch_fused_t<DIM, false, true, NC, EX, EY>(P, Uin, Uout, io, ts, s);
+  return launch_fused_t<DIM, false, false, NC, EX, EY>(P, Uin, Uout, io, ts, s);
+}
+
 hipError_t launch_step_fused(const Params& P, const double* Uin, double* Uout, StepIO io, const TileShape& ts,
                              hipStream_t s) {
-  const bool lm = P.low_mach != 0, ds = P.diss != 0;
-  if (P.dim == 2) {
-    if (lm && ds) return launch_fused_t<2, true, true, 64, 1>(P, Uin, Uout, io, ts, s);
-    if (lm && !ds) return launch_fused_t<2, true, false, 64, 1>(P, Uin, Uout, io, ts, s);
-    if (!lm && ds) return launch_fused_t<2, false, true, 64, 1>(P, Uin, Uout, io, ts, s);
-    return launch_fused_t<2, false, false, 64, 1>(P, Uin, Uout, io, ts, s);
-  }
-  if (lm && ds) return launch_fused_t<3, true, true, 32, 16>(P, Uin, Uout, io, ts, s);
-  if (lm && !ds) return launch_fused_t<3, true, false, 32, 16>(P, Uin, Uout, io, ts, s);
-  if (!lm && ds) return launch_fused_t<3, false, true, 32, 16>(P, Uin, Uout, io, ts, s);
-  return launch_fused_t<3, false, false, 32, 16>(P, Uin, Uout, io, ts, s);
+  if (P.dim == 2)
+    return P.nc ? launch_variant<2, true, 64, 1>(P, Uin, Uout, io, ts, s)
+                : launch_variant<2, false, 64, 1>(P, Uin, Uout, io, ts, s);
+  return P.nc ? launch_variant<3, true, 32, 16>(P, Uin, Uout, io, ts, s)
+              : launch_variant<3, false, 32, 16>(P, Uin, Uout, io, ts, s);
 }
 
 }  // namespace ars

@@ -22,7 +22,8 @@ enum {
   R_WALL = 28,                                                         // 3 axes wall flags (as doubles)
   R_L = 31, R_SB = 32, R_BT = 33,                                      // L, S-bar, 5 b~
   R_G = 38,                                                            // 3 axes x 5 fluxes
-  R_NFIELD = 53
+  R_US = 53,                                                           // (uS)_i (non-conservative energy)
+  R_NFIELD = 54
 };
 
 inline RefGrid make_grid(const Params& P) {

@@ -141,7 +141,17 @@ __global__ void k_ref_cell(Params P, RefGrid G, const double* __restrict__ d_dt,
     AE = (t == 0) ? term : AE + term;
   }
   const double rho = W[R_CONS * n + i];
-  const double calE = W[(R_CONS + NV - 1) * n + i] + rho * phi_at(P, qz - 2);
+  double calE;
+  if (P.nc) {
+    // App. B: energy without the potential, acoustic source (uS)_i
+    const int fz = R_FACE + 8;
+    const double uS = 0.5 * (W[(fz + 0) * n + i] * W[(fz + 3) * n + i] + W[(fz + 0) * n + mz] * W[(fz + 3) * n + mz]);
+    W[R_US * n + i] = uS;
+    AE = AE - lam[2] * uS;
+    calE = W[(R_CONS + NV - 1) * n + i];
+  } else {
+    calE = W[(R_CONS + NV - 1) * n + i] + rho * phi_at(P, qz - 2);
+  }
   const double iL = 1.0 / Lc;
   W[R_L * n + i] = Lc;
   W[R_SB * n + i] = sb;
@@ -245,16 +255,17 @@ __global__ void k_ref_update(Params P, RefGrid G, const double* __restrict__ d_d
   double nb[NV];
   for (int v = 0; v < NV; ++v) {
     double s = W[(R_CONS + v) * n + i];
-    if (v == NV - 1) s = s + W[R_CONS * n + i] * phic;
+    if (v == NV - 1 && !P.nc) s = s + W[R_CONS * n + i] * phic;
     for (int t = 0; t < DIM; ++t) {
       const int a = axes[t];
       const long long m = i - astride(G, a);
       s = s - lam[a] * (W[(R_G + 5 * a + v) * n + i] - W[(R_G + 5 * a + v) * n + m]);
     }
     if (v == DIM) s = s + lam[2] * W[R_SB * n + i];
+    if (v == NV - 1 && P.nc) s = s + lam[2] * W[R_US * n + i];
     nb[v] = s;
   }
-  nb[NV - 1] = nb[NV - 1] - nb[0] * phic;
+  if (!P.nc) nb[NV - 1] = nb[NV - 1] - nb[0] * phic;
   for (int v = 0; v < NV; ++v) Uout[c + v * P.ncell] = nb[v];
   const Prim<DIM> qn = cons_to_prim<DIM>(P, nb);
   double kin = nb[1] * qn.u[0];

@@ -20,6 +20,8 @@ typedef struct cfg_t {
   int32_t wall_noslip;
   int32_t thermal[2];
   double T_wall[2];
+  int32_t energy_form;
+  int32_t pad_;
 } cfg_t;
 int orc_validate(const cfg_t* c);
 int orc_init(const cfg_t* c, int problem, const double* prm, int nprm, uint64_t seed, double* U);

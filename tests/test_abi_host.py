@@ -137,3 +137,16 @@ def test_batch_host_side():
     assert create(cfgs + [W.rb([8, 8, 8], [1.0, 1.0, 1.0])[0]])[0] == A.EUNSUPPORTED
     assert create([dict(cfgs[0], cfl=0.0)])[0] == A.EINVAL
     assert L.ars_batch_create(0, None, C.byref(C.c_void_p())) == A.EINVAL
+
+
+def test_adjoint_rejects_nonconservative_energy():
+    """The reverse of the App. B energy form is not built: the adjoint entry
+    point says so before touching any device buffer."""
+    import ctypes as C
+    cfg, prob, prm, seed = W.rb([8, 6], [2.0, 1.0])
+    ctx = A.Context(dict(cfg, energy_form=1))
+    dummy = C.c_void_p(1)
+    rc = A.lib().ars_step_adjoint(ctx.h, dummy, dummy, C.c_void_p(2), dummy, None, dummy, None)
+    assert rc == A.EUNSUPPORTED
+    assert A.validate(dict(cfg, energy_form=2)) == A.EINVAL
+    assert O.validate(dict(cfg, energy_form=2)) != 0

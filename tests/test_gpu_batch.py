@@ -252,3 +252,16 @@ def test_batch_degenerate_instances(A):
             torch.cuda.synchronize()
             assert np.array_equal(B.view(k).cpu().numpy(), S.numpy()), (rows, k, c["n"])
             assert t[k] == S.t.item() and dt[k] == S.dt.item()
+
+
+def test_batch_nonconservative_instances(A):
+    """Instances with the App. B energy form beside conservative ones (two
+    variants of the batched kernel in one step call): each equals its
+    single-problem run bit for bit."""
+    import torch
+    setups = [W.rb([64, 32], [2.0, 1.0], Ra=2e3, seed=3, amp=1e-2), W.rb([30, 20], [2.0, 1.0], Ra=900, seed=4, amp=1e-2),
+              W.rb([128, 64], [2.0, 1.0], Ra=3e3, seed=5, amp=1e-2)]
+    setups = [(dict(c, energy_form=k % 2), p, q, s) for k, (c, p, q, s) in enumerate(setups)]
+    B = init_batch(A, setups)
+    B.step(40)
+    check_against_single(A, B, setups, 40, "energy forms")

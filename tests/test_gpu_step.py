@@ -370,3 +370,39 @@ def test_degenerate_shapes(A, name):
     S.step_ref(torch.tensor(log, dtype=torch.float64))
     torch.cuda.synchronize()
     assert bitwise(S.numpy(), U)
+
+
+NC_CASES = {
+    "nc_rb2d_ragged": (lambda: W.rb([100, 37], [2.0, 1.0], Ra=3e3, seed=11, amp=1e-2), 60, 7),
+    "nc_rb2d_thetaoff": (lambda: W.rb([64, 32], [2.0, 1.0], Ra=1e4, seed=1, amp=1e-2, low_mach=0), 60, None),
+    "nc_rb3d_ragged": (lambda: W.rb([37, 29, 23], [1.3, 1.0, 1.0], Ra=1e5, seed=4, amp=1e-2), 25, 6),
+    "nc_rb3d_thetaoff": (lambda: W.rb([20, 16, 12], [1.0, 1.0, 1.0], Ra=1e5, seed=2, amp=1e-2, low_mach=0), 25, None),
+}
+
+
+@pytest.mark.parametrize("name", list(NC_CASES))
+def test_nonconservative_energy_vs_oracle(A, name):
+    """The non-conservative energy scheme (App. B) on the GPU against the
+    oracle, with a flow added to the RB state, and fused == reference
+    kernels."""
+    import torch
+    make, nsteps, zc = NC_CASES[name]
+    cfg, prob, prm, seed = make()
+    cfg = dict(cfg, energy_form=1)
+    Uo0 = O.init(cfg, prob, prm, seed)
+    rng = np.random.default_rng(7)
+    D = cfg["dim"]
+    for k in range(D):
+        Uo0[1 + k] = 1e-2 * rng.standard_normal(Uo0[0].shape) * Uo0[0]
+    Uo0[-1] += 0.5 * sum(Uo0[1 + k] ** 2 for k in range(D)) / Uo0[0]
+    U, log, t, rc, fc = gpu_run(A, cfg, Uo0, nsteps, zc)
+    assert rc == 0, fc
+    r = O.run(cfg, Uo0, nsteps)
+    err = close(U, r["U"])
+    say(name, "max rel err", err, "bitwise", bitwise(U, r["U"]))
+    assert err <= 1e-12
+    S = A.Solver(cfg)
+    S.set_state(Uo0)
+    S.step_ref(torch.tensor(log, dtype=torch.float64))
+    torch.cuda.synchronize()
+    assert bitwise(S.numpy(), U)

@@ -506,3 +506,75 @@ def test_gresho_centre_cell():
     g = cfg["gamma"]
     p0 = 1.0 / (g * 1e-2 ** 2)
     assert U[3, 16, 16] == p0 / (g - 1.0)
+
+
+# ------------------------------------- non-conservative energy (App. B) ----
+@pytest.mark.parametrize("dim", [1, 2, 3])
+def test_nonconservative_equals_conservative_without_gravity(dim):
+    """With g = 0 there is no source S, no (uS) term and Phi = 0: the App. B
+    scheme is the conservative scheme, bit for bit."""
+    n = {1: [40], 2: [16, 12], 3: [8, 6, 5]}[dim]
+    cfg = base_cfg(dim, n, mu=2e-3, kappa=3e-3)
+    U = I.white_random(cfg, seed=3, amp=0.2)
+    a = O.run(cfg, U, 20)
+    b = O.run(dict(cfg, energy_form=1), U, 20)
+    assert a["status"] == 0 and b["status"] == 0
+    assert np.array_equal(a["U"], b["U"])
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_nonconservative_rb_base_at_rest(dim):
+    """App. B scheme at a discrete hydrostatic equilibrium: u* = 0 on every
+    face, [Pi*]_i = S-bar_i and (uS)_i = 0, so the RB base (viscous,
+    conducting, fixed-T walls) stays at rest to round-off."""
+    if dim == 2:
+        cfg, prob, prm, seed = W.config1()
+    else:
+        cfg, prob, prm, seed = W.rb([6, 5, 12], [1.0, 1.0, 1.0], Ra=1e5)
+    cfg = dict(cfg, energy_form=1)
+    U = O.init(cfg, prob, prm[:3] + [0.0], seed)
+    r = O.run(cfg, U, 300)
+    assert r["status"] == 0
+    u = np.sqrt(sum((r["U"][1 + k] / r["U"][0]) ** 2 for k in range(dim)))
+    assert u.max() <= 1e-12
+
+
+def test_nonconservative_isothermal_column():
+    """The isothermal column of Sec. 4.3 (Table 1 set-up, N = 128, t = 10)
+    with the App. B scheme: at rest to the round-off level of Table 1."""
+    N = 128
+    for lm, bound in ((0, 2.9e-14), (1, 1.4e-12)):
+        cfg = base_cfg(1, [N], [3.0], g=1.0, bc=[[1, 1]], low_mach=lm, energy_form=1)
+        U = O.init(cfg, W.PROB_ISOTHERMAL)
+        dt = O.dt(cfg, U)
+        nsteps = int(math.ceil(10.0 / dt))
+        r = O.run(cfg, U, nsteps)
+        assert r["status"] == 0
+        assert np.max(np.abs(r["U"][1] / r["U"][0])) <= bound
+
+
+def test_nonconservative_mass_and_energy():
+    """App. B with adiabatic walls and gravity: mass is conserved to
+    round-off (same flux form), the total energy sum(E + rho Phi) is not
+    (the scheme is not conservative for it) but its drift is small and
+    shrinks with resolution (both schemes are consistent)."""
+    drift = []
+    for n in (16, 32):
+        cfg = base_cfg(2, [n, n], [1.0, 1.0], g=1.0, mu=2e-3, kappa=3e-3, bc=[[0, 0], [1, 1]], thermal=[0, 0],
+                       energy_form=1)
+        U0 = O.init(cfg, W.PROB_RB, [1.0, 0.5, -1.0, 0.0])
+        x = (np.arange(n) + 0.5) / n
+        zc = (np.arange(n) + 0.5) / n
+        U = U0.copy()
+        U[1] = 0.05 * np.sin(2 * np.pi * x)[None, :] * np.sin(np.pi * zc)[:, None] * U[0]
+        U[3] = U0[3] + 0.5 * U[1] ** 2 / U[0]
+        phi = (zc * 1.0)[:, None] * np.ones((1, n))
+        m0, e0 = fsum(U[0]), fsum(U[3] + U[0] * phi)
+        dt = 0.5 * O.dt(cfg, U)
+        steps = int(round(0.2 / dt))
+        r = O.run(cfg, U, steps, dt_sched=[0.2 / steps] * steps)
+        assert r["status"] == 0
+        X = r["U"]
+        assert abs(fsum(X[0]) - m0) <= 1e-13 * m0
+        drift.append(abs(fsum(X[3] + X[0] * phi) - e0) / abs(e0))
+    assert drift[0] > 1e-12 and drift[1] < drift[0]
