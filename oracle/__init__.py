@@ -232,6 +232,38 @@ def diag(cfg: dict, U) -> dict:
     return dict(zip(DIAG_KEYS, out.tolist()))
 
 
+def spectrum(cfg: dict, U, kz: int) -> np.ndarray:
+    """Kinetic-energy spectrum of the horizontal plane kz (Sec. 4.5, 3D case:
+    the mid-plane spectrum figure; the paper gives no formula).  Reading:
+    w_c = sqrt(rho) u_c on the plane (all velocity components), its discrete
+    Fourier transform W_c(k) = sum_x w_c(x) exp(-2 pi i k.x / n) (numpy's
+    FFT, the library primitive), and E(s) = sum over integer wave vectors k
+    with round(|k|) = s of sum_c |W_c(k)|^2 / (2 N^2), N the number of cells
+    of the plane; so sum_s E(s) is the plane mean of rho |u|^2 / 2
+    (Parseval); one shell per integer s up to the largest round(|k|).  In 2D
+    the plane is a line and k = |k_x|."""
+    D = cfg["dim"]
+    U = np.asarray(U, dtype=np.float64)
+    rho = U[0][kz]
+    w = [np.sqrt(rho) * (U[1 + c][kz] / rho) for c in range(D)]
+    if D == 3:
+        ny, nx = rho.shape
+        kx = np.rint(np.fft.fftfreq(nx) * nx)
+        ky = np.rint(np.fft.fftfreq(ny) * ny)
+        kk = np.sqrt(ky[:, None] ** 2 + kx[None, :] ** 2)
+        P = sum(np.abs(np.fft.fft2(wc)) ** 2 for wc in w)
+        N = nx * ny
+    else:
+        nx = rho.shape[0]
+        kk = np.abs(np.rint(np.fft.fftfreq(nx) * nx))
+        P = sum(np.abs(np.fft.fft(wc)) ** 2 for wc in w)
+        N = nx
+    shell = np.rint(kk).astype(np.int64)
+    nshell = int(shell.max()) + 1
+    E = np.bincount(shell.ravel(), weights=P.ravel(), minlength=nshell)[:nshell]
+    return E / (2.0 * N * N)
+
+
 def splitmix64(seed: int, n: int) -> np.ndarray:
     out = np.zeros(n, dtype=np.uint64)
     lib().orc_splitmix64(C.c_uint64(seed), n, out.ctypes.data_as(C.POINTER(C.c_uint64)))

@@ -415,7 +415,6 @@ int step_impl(const orc_config& c, const S* U, S* Uout, double dt, S mu, S kappa
     for (int q2 = lo[2]; q2 < hi[2]; ++q2)
       for (int q1 = lo[1]; q1 < hi[1]; ++q1)
         for (int q0 = lo[0]; q0 < hi[0]; ++q0) {
-          int q[3] = {q0, q1, q2};
           long p = G.pad(q0, q1, q2);
           long pr = p + stride[d];
           const Face<S>& f = A.face[d][p];

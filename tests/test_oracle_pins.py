@@ -578,3 +578,74 @@ def test_nonconservative_mass_and_energy():
         assert abs(fsum(X[0]) - m0) <= 1e-13 * m0
         drift.append(abs(fsum(X[3] + X[0] * phi) - e0) / abs(e0))
     assert drift[0] > 1e-12 and drift[1] < drift[0]
+
+
+# ------------------------------------------------- mid-plane spectrum -----
+def test_spectrum_single_mode_and_parseval():
+    """Spectrum pins: a single Fourier mode u = A cos(2 pi (3 x + 4 y)) on a
+    plane of uniform density puts all its energy rho A^2 / 4 in shell 5
+    (|(3, 4)| = 5); for a random field the shells sum to the plane mean of
+    rho |u|^2 / 2 (Parseval), the corner wave vector (10, 6) of a 20 x 12
+    plane (|k| = 11.66) giving 13 shells."""
+    cfg = base_cfg(3, [32, 24, 4])
+    U = np.zeros((5, 4, 24, 32))
+    rho0, A0 = 1.3, 0.7
+    U[0] = rho0
+    y = (np.arange(24) / 24)[:, None]
+    x = (np.arange(32) / 32)[None, :]
+    U[1, 2] = rho0 * A0 * np.cos(2 * np.pi * (3 * x + 4 * y))
+    E = O.spectrum(cfg, U, 2)
+    assert E.shape == (21,)
+    assert abs(E[5] - rho0 * A0 ** 2 / 4) <= 1e-14
+    assert np.all(np.abs(np.delete(E, 5)) <= 1e-14)
+    cfg = base_cfg(3, [20, 12, 3])
+    rng = np.random.default_rng(3)
+    U = np.zeros((5, 3, 12, 20))
+    U[0] = rng.uniform(0.5, 1.5, U[0].shape)
+    for c in range(3):
+        U[1 + c] = rng.standard_normal(U[0].shape) * U[0]
+    E = O.spectrum(cfg, U, 1)
+    assert E.shape == (13,) and E[12] > 0
+    ke = np.mean(sum(U[1 + c][1] ** 2 for c in range(3)) / U[0][1]) / 2
+    assert abs(E.sum() - ke) <= 1e-12 * ke
+    # 2D: a line
+    cfg2 = base_cfg(2, [40, 6])
+    U2 = np.zeros((4, 6, 40))
+    U2[0] = 1.0
+    U2[2, 3] = 0.5 * np.sin(2 * np.pi * 7 * np.arange(40) / 40)
+    E2 = O.spectrum(cfg2, U2, 3)
+    assert E2.shape == (21,)
+    assert abs(E2[7] - 0.25 / 4) <= 1e-14 and abs(E2.sum() - E2[7]) <= 1e-14
+
+
+def test_spectrum_brute_force_tiny():
+    """The spectrum of a 5 x 6 plane (odd and even sides) against a direct
+    double sum over cells and wave numbers in plain Python, shells assigned
+    by comparing |k| with half-integers."""
+    nx, ny = 5, 6
+    cfg = base_cfg(3, [nx, ny, 2])
+    rng = np.random.default_rng(11)
+    U = np.zeros((5, 2, ny, nx))
+    U[0] = rng.uniform(0.5, 2.0, U[0].shape)
+    U[1:4] = rng.standard_normal((3, 2, ny, nx))
+    E = O.spectrum(cfg, U, 1)
+    ks = lambda n: [j if j <= (n - 1) // 2 else j - n for j in range(n)]
+    ref = {}
+    for kyv in ks(ny):
+        for kxv in ks(nx):
+            p = 0.0
+            for c in range(3):
+                re = im = 0.0
+                for yy in range(ny):
+                    for xx in range(nx):
+                        w = math.sqrt(U[0, 1, yy, xx]) * U[1 + c, 1, yy, xx] / U[0, 1, yy, xx]
+                        a = 2 * math.pi * (kxv * xx / nx + kyv * yy / ny)
+                        re += w * math.cos(a)
+                        im -= w * math.sin(a)
+                p += re * re + im * im
+            r = math.hypot(kxv, kyv)
+            s = next(s for s in range(10) if r < s + 0.5)
+            ref[s] = ref.get(s, 0.0) + p / (2 * (nx * ny) ** 2)
+    assert len(E) == max(ref) + 1
+    for s in range(len(E)):
+        assert abs(E[s] - ref.get(s, 0.0)) <= 1e-13 * max(1.0, abs(E[s]))
