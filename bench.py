@@ -25,6 +25,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+FP64_VALU_PEAK_TFS = 78.6  # MI355X FP64 vector (FMA counted as 2 flops)
 
 
 def kernel_hash():
@@ -107,6 +108,19 @@ def timed(torch, fn, stream=None):
     e1.record(stream)
     torch.cuda.synchronize()
     return e0.elapsed_time(e1)
+
+
+def spectrum_leg(torch, S, n, reps=20):
+    """Kinetic-energy spectrum of the middle horizontal plane of the stepped
+    state (ars_spectrum: direct DFT along x, then y, then shell sums).
+    Arithmetic: 4 flops per (kx, x) pair of the row transforms and 8 per
+    (ky, y) pair of the column transforms, for each of the 3 components."""
+    S.spectrum()
+    ms = timed(torch, lambda: [S.spectrum() for _ in range(reps)]) / reps
+    flops = 3 * n * n * (4 * n + 8 * n)
+    return {"plane": [n, n], "shells": int(S.spectrum().numel()), "ms_per_call": round(ms, 4),
+            "alu": {"achieved_TFLOPs": round(flops / (ms * 1e-3) / 1e12, 3), "peak": FP64_VALU_PEAK_TFS,
+                    "frac": round(flops / (ms * 1e-3) / 1e12 / FP64_VALU_PEAK_TFS, 4)}}
 
 
 def adjoint_leg(torch, A, W, nsteps=200, slots=16, reps=20):
@@ -296,6 +310,7 @@ def main():
                      "valu_view": valu_view(ms / args.steps, args.n)},
         "final_state": {"t": S.t.item(), "max_u": d["max_u"], "fault": d["fault"]},
     }
+    out["spectrum"] = spectrum_leg(torch, S, args.n)
     del S
     torch.cuda.empty_cache()
     if not args.no_adjoint:

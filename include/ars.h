@@ -222,6 +222,23 @@ int ars_kinetic_energy(ars_ctx* ctx, const double* d_state, double* d_grad, doub
 int ars_nusselt(ars_ctx* ctx, const double* d_state, int side, double* d_grad, double* d_nu, void* d_work,
                 void* stream);
 
+/* Kinetic-energy spectrum of the horizontal plane at index kz of the
+ * gravity axis (Sec. 4.5, 3D case, where it is taken on the middle plane,
+ * kz = n_z / 2): with w_c = sqrt(rho) u_c on the plane for every velocity
+ * component and W_c its discrete Fourier transform (kernel
+ * exp(-2 pi i k.x / n), integer wave numbers k_j = j for j < (n+1)/2, else
+ * j - n), d_spec[s] = sum over the k with round(|k|) = s of
+ * sum_c |W_c(k)|^2 / (2 N^2), N the cell count of the plane, for
+ * s < ars_spectrum_len(); the entries sum to the plane mean of
+ * rho |u|^2 / 2.  In 2D the plane is a line along x and s = |k_x|.
+ * d_work_spec: caller-owned device scratch of ars_workspace_bytes_spectrum
+ * bytes (no contents kept between calls).  ARS_EINVAL for a NULL pointer
+ * or kz outside [0, n_z); ARS_EUNSUPPORTED for a plane side above 2048.
+ * A cell with rho <= 0 makes the result NaN.  Deterministic; asynchronous. */
+int ars_spectrum_len(const ars_ctx* ctx); /* floor(|(n_x/2, n_y/2)| + 1/2) + 1 */
+size_t ars_workspace_bytes_spectrum(const ars_ctx* ctx);
+int ars_spectrum(ars_ctx* ctx, const double* d_state, int kz, double* d_spec, void* d_work_spec, void* stream);
+
 /* Binomial checkpointing plan (host only) for reversing n steps with s
  * snapshot slots, slot 0 holding U^0 and slots used as a stack.  Writes up
  * to cap actions of 4 int32 {op, step, arg, 0}:

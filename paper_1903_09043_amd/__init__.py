@@ -83,6 +83,9 @@ SIGNATURES = [
     ("ars_step_adjoint", C.c_int, [_VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
     ("ars_kinetic_energy", C.c_int, [_VP, _VP, _VP, _VP, _VP, _VP]),
     ("ars_nusselt", C.c_int, [_VP, _VP, C.c_int, _VP, _VP, _VP, _VP]),
+    ("ars_spectrum_len", C.c_int, [_VP]),
+    ("ars_workspace_bytes_spectrum", C.c_size_t, [_VP]),
+    ("ars_spectrum", C.c_int, [_VP, _VP, C.c_int, _VP, _VP, _VP]),
     ("ars_revolve_plan", C.c_int, [C.c_int, C.c_int, C.POINTER(C.c_int32), C.c_int, C.POINTER(C.c_int64)]),
     ("ars_revolve_cost", C.c_int64, [C.c_int, C.c_int]),
     ("ars_diagnostics", C.c_int, [_VP, _VP, _VP, C.POINTER(ArsDiag), _VP]),
@@ -336,6 +339,20 @@ class Solver:
         out = t.zeros(1, dtype=t.float64, device=self.device) if out is None else out
         _check(lib().ars_nusselt(self.ctx.h, _ptr(U), int(side), _ptr(grad) if grad is not None else None,
                                  _ptr(out), _ptr(self.work), self.stream), "ars_nusselt")
+        return out
+
+    def spectrum(self, kz=None, U=None, out=None):
+        """Device tensor of the kinetic-energy spectrum of the horizontal
+        plane kz (default: the middle plane n_z // 2), ``ars_spectrum``."""
+        t = self.torch
+        U = self.U if U is None else U
+        h = self.ctx.h
+        kz = int(self.cfg["n"][int(self.cfg["dim"]) - 1]) // 2 if kz is None else int(kz)
+        if getattr(self, "_wspec", None) is None:
+            self._wspec = t.empty(lib().ars_workspace_bytes_spectrum(h), dtype=t.uint8, device=self.device)
+        if out is None:
+            out = t.empty(lib().ars_spectrum_len(h), dtype=t.float64, device=self.device)
+        _check(lib().ars_spectrum(h, _ptr(U), kz, _ptr(out), _ptr(self._wspec), self.stream), "ars_spectrum")
         return out
 
     def diagnostics(self, raise_on_fault=True) -> dict:

@@ -458,6 +458,16 @@ int ars_nusselt(ars_ctx* ctx, const double* d_state, int side, double* d_grad, d
   return check(ars::launch_nusselt(ctx->P, side, C, d_state, d_grad, partials, d_nu, (hipStream_t)stream));
 }
 
+int ars_spectrum_len(const ars_ctx* ctx) { return ctx ? ars::spectrum_shells(ctx->P) : 0; }
+
+size_t ars_workspace_bytes_spectrum(const ars_ctx* ctx) { return ctx ? ars::spectrum_work_bytes(ctx->P) : 0; }
+
+int ars_spectrum(ars_ctx* ctx, const double* d_state, int kz, double* d_spec, void* d_work_spec, void* stream) {
+  if (!ctx || !d_state || !d_spec || !d_work_spec || kz < 0 || kz >= ctx->P.nz) return ARS_EINVAL;
+  if (!ars::spectrum_supported(ctx->P)) return ARS_EUNSUPPORTED;
+  return check(ars::launch_spectrum(ctx->P, d_state, kz, d_spec, d_work_spec, (hipStream_t)stream));
+}
+
 int ars_fault(ars_ctx* ctx, void* d_work, int64_t* fault_cell, void* stream) {
   if (!ctx || !d_work) return ARS_EINVAL;
   hipStream_t s = (hipStream_t)stream;

@@ -59,6 +59,10 @@ hipError_t launch_diag(const Params& P, const double* U, double* partials, doubl
 hipError_t launch_ke(const Params& P, const double* U, double* grad, double* partials, double* out, hipStream_t s);
 hipError_t launch_nusselt(const Params& P, int side, double C, const double* U, double* grad, double* partials,
                           double* out, hipStream_t s);
+int spectrum_shells(const Params& P);
+size_t spectrum_work_bytes(const Params& P);
+bool spectrum_supported(const Params& P);
+hipError_t launch_spectrum(const Params& P, const double* U, int kz, double* E, void* work, hipStream_t s);
 
 }  // namespace ars
 

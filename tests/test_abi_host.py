@@ -150,3 +150,28 @@ def test_adjoint_rejects_nonconservative_energy():
     assert rc == A.EUNSUPPORTED
     assert A.validate(dict(cfg, energy_form=2)) == A.EINVAL
     assert O.validate(dict(cfg, energy_form=2)) != 0
+
+
+def test_spectrum_host_side():
+    """Shell counts and scratch size of the plane spectrum, and its argument
+    checks, which return before any device use."""
+    import ctypes as C
+    L = A.lib()
+    base = dict(CFGS[2])
+    for n, shells in (([20, 12, 3], 13), ([32, 24, 4], 21), ([4, 4, 2], 4), ([1, 40, 3], 21), ([1, 1, 2], 1)):
+        ctx = A.Context(dict(base, n=n))
+        assert L.ars_spectrum_len(ctx.h) == shells
+        ref = len(O.spectrum(dict(base, n=n), np.ones((5, n[2], n[1], n[0])), 0))
+        assert ref == shells
+        assert L.ars_workspace_bytes_spectrum(ctx.h) == 7 * n[0] * n[1] * 8
+    ctx2 = A.Context(W.config1()[0])
+    assert L.ars_spectrum_len(ctx2.h) == 33
+    assert L.ars_workspace_bytes_spectrum(ctx2.h) == 5 * 64 * 8
+    d = C.c_void_p(1)
+    ctx = A.Context(dict(base, n=[16, 16, 8]))
+    assert L.ars_spectrum(ctx.h, d, 8, d, d, None) == A.EINVAL
+    assert L.ars_spectrum(ctx.h, d, -1, d, d, None) == A.EINVAL
+    assert L.ars_spectrum(ctx.h, None, 0, d, d, None) == A.EINVAL
+    assert L.ars_spectrum(ctx.h, d, 0, d, None, None) == A.EINVAL
+    big = A.Context(dict(base, n=[2049, 4, 2]))
+    assert L.ars_spectrum(big.h, d, 0, d, d, None) == A.EUNSUPPORTED
