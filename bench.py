@@ -123,7 +123,7 @@ def spectrum_leg(torch, S, n, reps=20):
                     "frac": round(flops / (ms * 1e-3) / 1e12 / FP64_VALU_PEAK_TFS, 4)}}
 
 
-def adjoint_leg(torch, A, W, nsteps=200, slots=16, reps=20):
+def adjoint_leg(torch, A, W, nsteps=200, slots=16, reps=20, end_to_end=True):
     """Adjoint/forward ratio on the 3D RB 128^3 workload: per step (one
     adjoint step vs one fused step, both warm, median of `reps`) and end to
     end (full gradient: forward, recomputation by the revolve plan and the
@@ -150,6 +150,9 @@ def adjoint_leg(torch, A, W, nsteps=200, slots=16, reps=20):
     fwd.sort()
     adj.sort()
     f_ms, a_ms = fwd[reps // 2], adj[reps // 2]
+    if not end_to_end:
+        return {"step_ms_forward": round(f_ms, 4), "step_ms_adjoint": round(a_ms, 4),
+                "ratio_per_step": round(a_ms / f_ms, 3)}
     # end to end
     mu = torch.tensor(cfg["mu"], dtype=torch.float64, requires_grad=True)
     ka = torch.tensor(cfg["kappa"], dtype=torch.float64, requires_grad=True)
@@ -228,7 +231,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
-    ap.add_argument("--only", choices=["adjoint", "batch", "batch-kernel"], default=None,
+    ap.add_argument("--only", choices=["adjoint", "adjoint-step", "batch", "batch-kernel"], default=None,
                     help="run one side leg alone (profiling); prints its JSON object")
     ap.add_argument("--zchunk", type=int, default=0)
     ap.add_argument("--mode", choices=["step", "copy"], default="step",
@@ -244,6 +247,9 @@ def main():
 
     if args.only == "adjoint":
         print(json.dumps({"adjoint": adjoint_leg(torch, A, W)}), flush=True)
+        return
+    if args.only == "adjoint-step":
+        print(json.dumps({"adjoint": adjoint_leg(torch, A, W, reps=5, end_to_end=False)}), flush=True)
         return
     if args.only == "batch":
         print(json.dumps({"batch": batch_leg(torch, A, W)}), flush=True)

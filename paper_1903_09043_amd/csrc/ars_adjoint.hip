@@ -7,12 +7,13 @@
 // phase kernels on the padded grid; the reverse sweep then runs the phases
 // backwards, each as a gather (a face or a cell collects every contribution
 // it receives, in a fixed order), so the result is deterministic:
-//   (update + flux)^T per face, all axes in one pass (transport + viscous +
-//   heat; the face flux adjoint is formed from lam^{n+1} on the fly)
-//   -> acoustic cell^T -> (face solver^T + primitive gather), each face's
-//   reverse evaluated by both of its cells -> fold onto interior cells of
-//   (wall ghost + primitive)^T evaluated at the cell and at each of its
-//   periodic / outflow images.
+//   (update + flux)^T per face, all axes, and the acoustic cell^T, in one
+//   pass (transport + viscous + heat; the face flux adjoint is formed from
+//   lam^{n+1} on the fly) -> (face solver^T + primitive gather), each face's
+//   reverse evaluated by both of its cells, with (primitive)^T and the fold
+//   into lam^n done in place for cells two or more cells from every
+//   boundary -> for the other cells, the fold of (wall ghost + primitive)^T
+//   evaluated at the cell and at each of its periodic / outflow images.
 // Only small per-face and per-cell adjoints go through memory between the
 // passes; quantities a later pass can form from its inputs are recomputed.
 // Non-smooth operations differentiate the branch the forward step took
@@ -109,11 +110,12 @@ __device__ __forceinline__ void face_gbar(const Params& P, const RefGrid& G, con
     Gb[v] = lama * (nbar<DIM>(P, G, io, rx, ry, rz, v) - nbar<DIM>(P, G, io, qx, qy, qz, v));
 }
 
-// ------------------------------------------------------- K2: flux^T --------
+// ------------------------------------------------------- K1: flux^T --------
 template <int DIM, bool DISS>
 __device__ __forceinline__ void adj_flux_face(const Params& P, const RefGrid& G, const AdjIO& io, int a,
                                               double lama, long long i, int qx, int qy, int qz,
-                                              double* __restrict__ W, double& mu_acc, double& kappa_acc) {
+                                              double* __restrict__ W, double& mu_acc, double& kappa_acc,
+                                              double* btb) {
   constexpr int NV = DIM + 2;
   const long long n = G.npad;
   if (!flux_range<DIM>(G, a, qx, qy, qz)) {
@@ -134,7 +136,12 @@ __device__ __forceinline__ void adj_flux_face(const Params& P, const RefGrid& G,
   double usb = 0.0;
   double pib = Gb[1 + dn];
   if (!wall) {
-    // (the b~ adjoint Gb * u* of the upwind cell is formed by the cell pass)
+    // b~ adjoint Gb u* of the upwind cell: kept here when it is this cell;
+    // the right cell gathers it from this face itself
+    if (us >= 0.0) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) btb[v] += Gb[v] * us;
+    }
     const long long up = us >= 0.0 ? i : j;
     for (int v = 0; v < NV - 1; ++v) usb += Gb[v] * W[(R_BT + v) * n + up];
     const double bE = W[(R_BT + NV - 1) * n + up];
@@ -233,82 +240,16 @@ __device__ __forceinline__ void adj_flux_face(const Params& P, const RefGrid& G,
   }
 }
 
-// One thread per padded cell, its three +faces; with dissipation the mu and
-// kappa partials of the block are summed in a fixed order into
-// partial[2 block + 0 / 1].
-template <int DIM, bool DISS>
-__global__ void __launch_bounds__(256) k_adj_flux(Params P, RefGrid G, AdjIO io, double* __restrict__ W,
-                                                  double* __restrict__ partial) {
-  __shared__ double sh[2][256];
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  double mu_acc = 0.0, kappa_acc = 0.0;
-  if (i < G.npad) {
-    int qx, qy, qz;
-    decode(G, i, qx, qy, qz);
-    const double dt = *io.dt;
-#pragma unroll
-    for (int t = 0; t < DIM; ++t) {
-      const int a = axis_of<DIM>(t);
-      adj_flux_face<DIM, DISS>(P, G, io, a, dt / P.dx[a], i, qx, qy, qz, W, mu_acc, kappa_acc);
-    }
-  }
-  if (!DISS) return;
-  sh[0][threadIdx.x] = mu_acc;
-  sh[1][threadIdx.x] = kappa_acc;
-  __syncthreads();
-  for (int w = 128; w >= 1; w >>= 1) {
-    if ((int)threadIdx.x < w) {
-      sh[0][threadIdx.x] += sh[0][threadIdx.x + w];
-      sh[1][threadIdx.x] += sh[1][threadIdx.x + w];
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    partial[2 * blockIdx.x] = sh[0][0];
-    partial[2 * blockIdx.x + 1] = sh[1][0];
-  }
-}
-
-// ------------------------------------------------- K3: acoustic cell^T -----
+// ------------------------------------------------ K1: acoustic cell^T -----
+// Reverse of b~ = (b - A)/L at cell i from btb, the b~ adjoint gathered from
+// the faces the cell is upwind of: adjoints of L, A (the A_CB fields) and the
+// direct conserved-value adjoint (A_CONSB).
 template <int DIM>
-__global__ void k_adj_cell(Params P, RefGrid G, AdjIO io, double* __restrict__ W) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= G.npad) return;
+__device__ __forceinline__ void adj_cell_values(const Params& P, const RefGrid& G, const AdjIO& io,
+                                                double* __restrict__ W, long long i, int qx, int qy, int qz,
+                                                double lamz, const double* btb) {
   constexpr int NV = DIM + 2;
-  int qx, qy, qz;
-  decode(G, i, qx, qy, qz);
   const long long n = G.npad;
-  if (!cell_range<DIM>(G, qx, qy, qz)) {
-    for (int v = 0; v < 5; ++v) W[(A_CONSB + v) * n + i] = 0.0;  // no acoustic cell values here
-    return;
-  }
-  const double dt = *io.dt;
-  const double lamz = dt / P.dx[2];
-  double btb[NV];
-  for (int v = 0; v < NV; ++v) btb[v] = 0.0;
-  for (int t = 0; t < DIM; ++t) {
-    const int a = axis_of<DIM>(t);
-    const double lama = dt / P.dx[a];
-    double Gb[NV];
-    // c as the left (upwind) cell of face (a, c): b~ adjoint Gb u*
-    if (flux_range<DIM>(G, a, qx, qy, qz) && W[(R_WALL + a) * n + i] == 0.0) {
-      const double us = W[(R_FACE + 4 * a) * n + i];
-      if (us >= 0.0) {
-        face_gbar<DIM>(P, G, io, a, lama, qx, qy, qz, Gb);
-        for (int v = 0; v < NV; ++v) btb[v] += Gb[v] * us;
-      }
-    }
-    // c as the right (upwind) cell of face (a, c - e_a)
-    const long long m = i - astride(G, a);
-    const int mx = qx - (a == 0), my = qy - (a == 1), mz = qz - (a == 2);
-    if (flux_range<DIM>(G, a, mx, my, mz) && W[(R_WALL + a) * n + m] == 0.0) {
-      const double us = W[(R_FACE + 4 * a) * n + m];
-      if (!(us >= 0.0)) {
-        face_gbar<DIM>(P, G, io, a, lama, mx, my, mz, Gb);
-        for (int v = 0; v < NV; ++v) btb[v] += Gb[v] * us;
-      }
-    }
-  }
   const double iL = 1.0 / W[R_L * n + i];
   double consb[NV], Ab[NV];
   double Lb = 0.0;
@@ -332,7 +273,195 @@ __global__ void k_adj_cell(Params P, RefGrid G, AdjIO io, double* __restrict__ W
   for (int v = 0; v < 5; ++v) W[(A_CONSB + v) * n + i] = v < NV ? consb[v] : 0.0;
 }
 
-// ------------------------------------------------------ K4: face solver^T --
+// One thread per padded cell: the reverse of its three +faces (flux and,
+// with dissipation, viscous and heat fluxes), then the acoustic cell
+// reverse of the cell, whose b~ adjoint gathers, axis by axis, the +face
+// (where this cell is upwind, u* >= 0) and the -face (u* < 0; its Gb is
+// formed again from lam^{n+1}).  With dissipation the mu and kappa partials
+// of the block are summed in a fixed order into partial[2 block + 0 / 1].
+template <int DIM, bool DISS>
+__global__ void __launch_bounds__(256) k_adj_flux(Params P, RefGrid G, AdjIO io, double* __restrict__ W,
+                                                  double* __restrict__ partial) {
+  __shared__ double sh[2][256];
+  constexpr int NV = DIM + 2;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  double mu_acc = 0.0, kappa_acc = 0.0;
+  if (i < G.npad) {
+    const long long n = G.npad;
+    int qx, qy, qz;
+    decode(G, i, qx, qy, qz);
+    const double dt = *io.dt;
+    const bool cell = cell_range<DIM>(G, qx, qy, qz);
+    double btb[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) btb[v] = 0.0;
+#pragma unroll
+    for (int t = 0; t < DIM; ++t) {
+      const int a = axis_of<DIM>(t);
+      const double lama = dt / P.dx[a];
+      adj_flux_face<DIM, DISS>(P, G, io, a, lama, i, qx, qy, qz, W, mu_acc, kappa_acc, btb);
+      // c as the right (upwind) cell of face (a, c - e_a)
+      if (cell) {
+        const long long m = i - astride(G, a);
+        const int mx = qx - (a == 0), my = qy - (a == 1), mz = qz - (a == 2);
+        if (flux_range<DIM>(G, a, mx, my, mz) && W[(R_WALL + a) * n + m] == 0.0) {
+          const double us = W[(R_FACE + 4 * a) * n + m];
+          if (!(us >= 0.0)) {
+            double Gb[NV];
+            face_gbar<DIM>(P, G, io, a, lama, mx, my, mz, Gb);
+            for (int v = 0; v < NV; ++v) btb[v] += Gb[v] * us;
+          }
+        }
+      }
+    }
+    if (cell) {
+      adj_cell_values<DIM>(P, G, io, W, i, qx, qy, qz, dt / P.dx[2], btb);
+    } else {
+      for (int v = 0; v < 5; ++v) W[(A_CONSB + v) * n + i] = 0.0;  // no acoustic cell values here
+    }
+  }
+  if (!DISS) return;
+  sh[0][threadIdx.x] = mu_acc;
+  sh[1][threadIdx.x] = kappa_acc;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      sh[0][threadIdx.x] += sh[0][threadIdx.x + w];
+      sh[1][threadIdx.x] += sh[1][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    partial[2 * blockIdx.x] = sh[0][0];
+    partial[2 * blockIdx.x + 1] = sh[1][0];
+  }
+}
+
+// ------------------------------- (wall ghost + primitives)^T (K2, K3) -----
+template <int DIM>
+__device__ void ghost_reverse(const Params& P, const double* W, long long n, long long gi, long long ci, int side,
+                              double& rho_b, double* u_b, double& T_b) {
+  // forward ghost values (stored at the ghost position) and interior values
+  const double gr = W[R_R * n + gi], gc = W[R_C * n + gi], gic = W[R_IC * n + gi], grho = W[R_RHO * n + gi];
+  const double gp = W[R_P * n + gi], Tg = W[R_T * n + gi];
+  const double Ti = W[R_T * n + ci], rhoi = W[R_RHO * n + ci];
+  const double dphi = (side == 0) ? phi_at(P, -1) - phi_at(P, 0) : phi_at(P, P.nz) - phi_at(P, P.nz - 1);
+  const double hd = 0.5 * dphi;
+  const double den = Tg + hd;
+  const double b_rho = W[(A_PB + 0) * n + gi], b_p = W[(A_PB + 4) * n + gi], b_rc = W[(A_PB + 5) * n + gi];
+  const double b_irc = W[(A_PB + 6) * n + gi], b_ic = W[(A_PB + 7) * n + gi], b_T = W[(A_PB + 8) * n + gi];
+  double rb = b_irc * gic;
+  const double icb = b_ic + b_irc * gr;
+  double cb = -icb * gic * gic;
+  double rhob = b_rho + b_rc * gc;
+  cb += b_rc * grho;
+  const double Xb = cb * 0.5 / gc;
+  double pb = b_p + Xb * P.gamma * gr;
+  rb += Xb * P.gamma * gp;
+  rhob += -rb * gr * gr;
+  rhob += pb * Tg;
+  double Tgb = b_T + pb * grho;
+  const double numb = rhob / den;
+  const double denb = -rhob * grho / den;
+  Tgb += denb;
+  rho_b += numb * (Ti - hd);
+  double Tib = numb * rhoi;
+  Tib += (P.thermal[side] == TH_FIXED) ? -Tgb : Tgb;
+  T_b += Tib;
+  for (int k = 0; k < DIM; ++k) {
+    const double ub = W[(A_PB + 1 + k) * n + gi];
+    const bool flip = P.noslip ? true : (k == DIM - 1);
+    u_b[k] += flip ? -ub : ub;
+  }
+}
+
+// Conserved-value adjoint of padded position i (vertical index qz) from its
+// primitive adjoints, the reverse of the wall ghosts it builds and the
+// direct adjoint through b~.  Wall ghost positions carry none (their
+// adjoint goes to the interior cell they are built from).  Evaluated by the
+// fold for every image of an interior cell.
+// pb: the primitive adjoints of position i (rho, u_0, u_1, u_2, p, rho c,
+// 1/(rho c), 1/c, T), i not a wall ghost.
+template <int DIM>
+__device__ __forceinline__ void prim_reverse_at(const Params& P, const RefGrid& G, const double* __restrict__ W,
+                                                long long i, int qz, const double* pb, double* Ub) {
+  constexpr int NV = DIM + 2;
+  const long long n = G.npad;
+  const bool wlo = P.bcz[0] == BC_WALL, whi = P.bcz[1] == BC_WALL;
+  double rho_b = pb[0];
+  double u_b[3];
+  for (int k = 0; k < DIM; ++k) u_b[k] = pb[1 + k];
+  double p_b = pb[4];
+  const double rc_b = pb[5];
+  const double irc_b = pb[6];
+  const double ic_b = pb[7];
+  double T_b = pb[8];
+  // wall ghosts built from this cell (both ghost layers)
+  const long long sz = astride(G, 2);
+  if (wlo && qz == 2) {
+    ghost_reverse<DIM>(P, W, n, i - sz, i, 0, rho_b, u_b, T_b);
+    ghost_reverse<DIM>(P, W, n, i - 2 * sz, i, 0, rho_b, u_b, T_b);
+  }
+  if (whi && qz == G.Pz - 3) {
+    ghost_reverse<DIM>(P, W, n, i + sz, i, 1, rho_b, u_b, T_b);
+    ghost_reverse<DIM>(P, W, n, i + 2 * sz, i, 1, rho_b, u_b, T_b);
+  }
+  // primitives of this cell from its conserved values
+  const double r = W[R_R * n + i], c = W[R_C * n + i], ic = W[R_IC * n + i], p = W[R_P * n + i];
+  const double rho = W[R_RHO * n + i];
+  double rb = irc_b * ic;
+  const double icb = ic_b + irc_b * r;
+  double cb = -icb * ic * ic;
+  rho_b += rc_b * c;
+  cb += rc_b * rho;
+  p_b += T_b * r;
+  rb += T_b * p;
+  const double Xb = cb * 0.5 / c;
+  p_b += Xb * P.gamma * r;
+  rb += Xb * P.gamma * p;
+  const double Eb = P.gm1 * p_b;
+  const double kinb = -P.gm1 * p_b;
+  double mb[3];
+  for (int k = 0; k < DIM; ++k) {
+    const double uk = W[ufield(DIM, k) * n + i];
+    const double mk = W[(R_CONS + 1 + k) * n + i];
+    mb[k] = 0.5 * kinb * uk;
+    const double ubt = u_b[k] + 0.5 * kinb * mk;
+    mb[k] += ubt * r;
+    rb += ubt * mk;
+  }
+  rho_b += -rb * r * r;
+  Ub[0] = rho_b;
+  for (int k = 0; k < DIM; ++k) Ub[1 + k] = mb[k];
+  Ub[NV - 1] = Eb;
+  for (int v = 0; v < NV; ++v) Ub[v] += W[(A_CONSB + v) * n + i];
+}
+
+template <int DIM>
+__device__ __forceinline__ void prim_reverse(const Params& P, const RefGrid& G, const double* __restrict__ W,
+                                             long long i, int qz, double* Ub) {
+  constexpr int NV = DIM + 2;
+  const long long n = G.npad;
+  const bool ghost = (qz < 2 && P.bcz[0] == BC_WALL) || (qz >= G.Pz - 2 && P.bcz[1] == BC_WALL);
+  if (ghost) {
+    for (int v = 0; v < NV; ++v) Ub[v] = 0.0;
+    return;
+  }
+  double pb[9];
+  for (int k = 0; k < 9; ++k) pb[k] = W[(A_PB + k) * n + i];
+  prim_reverse_at<DIM>(P, G, W, i, qz, pb, Ub);
+}
+
+// A cell at least two cells from every boundary of the box: the padded
+// grid holds no image of it (periodic or outflow copy, wall ghost) and it
+// builds no wall ghost, so its conserved-value adjoint is its own
+// primitive reverse and is folded where its primitive adjoints are formed.
+template <int DIM>
+__device__ __forceinline__ bool bulk_cell(const Params& P, int x, int y, int z) {
+  return x >= 2 && x < P.nx - 2 && z >= 2 && z < P.nz - 2 && (DIM == 2 || (y >= 2 && y < P.ny - 2));
+}
+
+// ------------------------------------------------------ K2: face solver^T --
 // Reverse of the face solver of face (a, L = i = (qx, qy, qz)) (requires
 // L + e_a inside the padded grid): adjoints of (rho, u_n, p, rho c,
 // 1/(rho c), 1/c) of the left cell into bl[6] and of the right cell into
@@ -447,7 +576,7 @@ __device__ __forceinline__ void face_reverse(const Params& P, const RefGrid& G, 
   br[5] = cRb;
 }
 
-// ---------------------------------------------- K5: primitive gather ------
+// ---------------------------------------------- K2: primitive gather ------
 template <int DIM, bool DISS, bool LM>
 __global__ void k_adj_pgather(Params P, RefGrid G, AdjIO io, double* __restrict__ W) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -526,121 +655,21 @@ __global__ void k_adj_pgather(Params P, RefGrid G, AdjIO io, double* __restrict_
       }
     }
   }
-  W[(A_PB + 0) * n + i] = rho;
-  W[(A_PB + 1) * n + i] = u[0];
-  W[(A_PB + 2) * n + i] = u[1];
-  W[(A_PB + 3) * n + i] = u[2];
-  W[(A_PB + 4) * n + i] = p;
-  W[(A_PB + 5) * n + i] = rc;
-  W[(A_PB + 6) * n + i] = irc;
-  W[(A_PB + 7) * n + i] = ic;
-  W[(A_PB + 8) * n + i] = T;
-}
-
-// ------------------------------------- K6: (wall ghost + primitives)^T -----
-template <int DIM>
-__device__ void ghost_reverse(const Params& P, const double* W, long long n, long long gi, long long ci, int side,
-                              double& rho_b, double* u_b, double& T_b) {
-  // forward ghost values (stored at the ghost position) and interior values
-  const double gr = W[R_R * n + gi], gc = W[R_C * n + gi], gic = W[R_IC * n + gi], grho = W[R_RHO * n + gi];
-  const double gp = W[R_P * n + gi], Tg = W[R_T * n + gi];
-  const double Ti = W[R_T * n + ci], rhoi = W[R_RHO * n + ci];
-  const double dphi = (side == 0) ? phi_at(P, -1) - phi_at(P, 0) : phi_at(P, P.nz) - phi_at(P, P.nz - 1);
-  const double hd = 0.5 * dphi;
-  const double den = Tg + hd;
-  const double b_rho = W[(A_PB + 0) * n + gi], b_p = W[(A_PB + 4) * n + gi], b_rc = W[(A_PB + 5) * n + gi];
-  const double b_irc = W[(A_PB + 6) * n + gi], b_ic = W[(A_PB + 7) * n + gi], b_T = W[(A_PB + 8) * n + gi];
-  double rb = b_irc * gic;
-  const double icb = b_ic + b_irc * gr;
-  double cb = -icb * gic * gic;
-  double rhob = b_rho + b_rc * gc;
-  cb += b_rc * grho;
-  const double Xb = cb * 0.5 / gc;
-  double pb = b_p + Xb * P.gamma * gr;
-  rb += Xb * P.gamma * gp;
-  rhob += -rb * gr * gr;
-  rhob += pb * Tg;
-  double Tgb = b_T + pb * grho;
-  const double numb = rhob / den;
-  const double denb = -rhob * grho / den;
-  Tgb += denb;
-  rho_b += numb * (Ti - hd);
-  double Tib = numb * rhoi;
-  Tib += (P.thermal[side] == TH_FIXED) ? -Tgb : Tgb;
-  T_b += Tib;
-  for (int k = 0; k < DIM; ++k) {
-    const double ub = W[(A_PB + 1 + k) * n + gi];
-    const bool flip = P.noslip ? true : (k == DIM - 1);
-    u_b[k] += flip ? -ub : ub;
-  }
-}
-
-// Conserved-value adjoint of padded position i (vertical index qz) from its
-// primitive adjoints, the reverse of the wall ghosts it builds and the
-// direct adjoint through b~.  Wall ghost positions carry none (their
-// adjoint goes to the interior cell they are built from).  Evaluated by the
-// fold for every image of an interior cell.
-template <int DIM>
-__device__ __forceinline__ void prim_reverse(const Params& P, const RefGrid& G, const double* __restrict__ W,
-                                             long long i, int qz, double* Ub) {
-  constexpr int NV = DIM + 2;
-  const long long n = G.npad;
-  const bool wlo = P.bcz[0] == BC_WALL, whi = P.bcz[1] == BC_WALL;
-  const bool ghost = (qz < 2 && wlo) || (qz >= G.Pz - 2 && whi);
-  if (ghost) {
-    for (int v = 0; v < NV; ++v) Ub[v] = 0.0;
+  const double pb[9] = {rho, u[0], u[1], u[2], p, rc, irc, ic, T};
+  const int x = qx - 2, y = DIM == 3 ? qy - 2 : 0, z = qz - 2;
+  if (interior_cell<DIM>(G, qx, qy, qz) && bulk_cell<DIM>(P, x, y, z)) {
+    // lam^n = lam^{n+1} + the cell's conserved-value adjoint
+    constexpr int NV = DIM + 2;
+    double Ub[NV];
+    prim_reverse_at<DIM>(P, G, W, i, qz, pb, Ub);
+    const long long c = x + (long long)P.nx * (y + (long long)P.ny * z);
+    for (int v = 0; v < NV; ++v) io.lam0[c + v * P.ncell] = io.lam1[c + v * P.ncell] + Ub[v];
     return;
   }
-  double rho_b = W[(A_PB + 0) * n + i];
-  double u_b[3];
-  for (int k = 0; k < DIM; ++k) u_b[k] = W[(A_PB + 1 + k) * n + i];
-  double p_b = W[(A_PB + 4) * n + i];
-  const double rc_b = W[(A_PB + 5) * n + i];
-  const double irc_b = W[(A_PB + 6) * n + i];
-  const double ic_b = W[(A_PB + 7) * n + i];
-  double T_b = W[(A_PB + 8) * n + i];
-  // wall ghosts built from this cell (both ghost layers)
-  const long long sz = astride(G, 2);
-  if (wlo && qz == 2) {
-    ghost_reverse<DIM>(P, W, n, i - sz, i, 0, rho_b, u_b, T_b);
-    ghost_reverse<DIM>(P, W, n, i - 2 * sz, i, 0, rho_b, u_b, T_b);
-  }
-  if (whi && qz == G.Pz - 3) {
-    ghost_reverse<DIM>(P, W, n, i + sz, i, 1, rho_b, u_b, T_b);
-    ghost_reverse<DIM>(P, W, n, i + 2 * sz, i, 1, rho_b, u_b, T_b);
-  }
-  // primitives of this cell from its conserved values
-  const double r = W[R_R * n + i], c = W[R_C * n + i], ic = W[R_IC * n + i], p = W[R_P * n + i];
-  const double rho = W[R_RHO * n + i];
-  double rb = irc_b * ic;
-  const double icb = ic_b + irc_b * r;
-  double cb = -icb * ic * ic;
-  rho_b += rc_b * c;
-  cb += rc_b * rho;
-  p_b += T_b * r;
-  rb += T_b * p;
-  const double Xb = cb * 0.5 / c;
-  p_b += Xb * P.gamma * r;
-  rb += Xb * P.gamma * p;
-  const double Eb = P.gm1 * p_b;
-  const double kinb = -P.gm1 * p_b;
-  double mb[3];
-  for (int k = 0; k < DIM; ++k) {
-    const double uk = W[ufield(DIM, k) * n + i];
-    const double mk = W[(R_CONS + 1 + k) * n + i];
-    mb[k] = 0.5 * kinb * uk;
-    const double ubt = u_b[k] + 0.5 * kinb * mk;
-    mb[k] += ubt * r;
-    rb += ubt * mk;
-  }
-  rho_b += -rb * r * r;
-  Ub[0] = rho_b;
-  for (int k = 0; k < DIM; ++k) Ub[1 + k] = mb[k];
-  Ub[NV - 1] = Eb;
-  for (int v = 0; v < NV; ++v) Ub[v] += W[(A_CONSB + v) * n + i];
+  for (int k = 0; k < 9; ++k) W[(A_PB + k) * n + i] = pb[k];
 }
 
-// ------------------------------------------------ K7: fold onto interior ----
+// ------------------------------------------------ K3: fold onto interior ----
 __device__ __forceinline__ int images(int ia, int n, const int* bc, bool wallaxis, int* out) {
   int k = 0;
   out[k++] = ia + 2;
@@ -653,16 +682,71 @@ __device__ __forceinline__ int images(int ia, int n, const int* bc, bool wallaxi
   return k;
 }
 
+// The cells that are not bulk cells, enumerated plane by plane: the two
+// bottom and two top planes whole, and of every other plane the rows below
+// and above the inner band whole and, in the band, the four cells nearest
+// the x boundaries.  Any axis too short for an inner range makes every
+// plane whole.
+__host__ __device__ __forceinline__ long long inner_len(int n) { return n > 4 ? n - 4 : 0; }
+
+template <int DIM>
+__host__ __device__ __forceinline__ long long boundary_count(const Params& P) {
+  const long long yi = DIM == 3 ? inner_len(P.ny) : P.ny;
+  return P.ncell - inner_len(P.nx) * yi * inner_len(P.nz);
+}
+
+template <int DIM>
+__device__ __forceinline__ void boundary_cell(const Params& P, long long k, int& x, int& y, int& z) {
+  const long long nx = P.nx, A = nx * P.ny;
+  const long long xi = inner_len(P.nx), zi = inner_len(P.nz);
+  const long long yi = DIM == 3 ? inner_len(P.ny) : P.ny;
+  const long long ylo = DIM == 3 ? 2 : 0;
+  const long long Rg = A - xi * yi;
+  long long r;
+  if (zi == 0 || Rg == A || k < 2 * A) {
+    z = (int)(k / A);
+    r = k % A;
+    x = (int)(r % nx);
+    y = (int)(r / nx);
+    return;
+  }
+  k -= 2 * A;
+  if (k >= zi * Rg) {
+    k -= zi * Rg;
+    z = (int)(P.nz - 2 + k / A);
+    r = k % A;
+    x = (int)(r % nx);
+    y = (int)(r / nx);
+    return;
+  }
+  z = (int)(2 + k / Rg);
+  r = k % Rg;
+  if (r < ylo * nx) {
+    x = (int)(r % nx);
+    y = (int)(r / nx);
+    return;
+  }
+  r -= ylo * nx;
+  if (r < 4 * yi) {
+    const int j = (int)(r % 4);
+    x = j < 2 ? j : (int)(nx - 4 + j);
+    y = (int)(ylo + r / 4);
+    return;
+  }
+  r -= 4 * yi;
+  x = (int)(r % nx);
+  y = (int)(ylo + yi + r / nx);
+}
+
 template <int DIM>
 __global__ void k_adj_fold(Params P, RefGrid G, AdjIO io, const double* __restrict__ W) {
-  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= P.ncell) return;
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= boundary_count<DIM>(P)) return;
   constexpr int NV = DIM + 2;
   const long long n = G.npad;
-  const int x = (int)(c % P.nx);
-  const long long r = c / P.nx;
-  const int y = (int)(r % P.ny);
-  const int z = (int)(r / P.ny);
+  int x, y, z;
+  boundary_cell<DIM>(P, k, x, y, z);
+  const long long c = x + (long long)P.nx * (y + (long long)P.ny * z);
   int ix[5], iy[5], iz[5];
   const int nxi = images(x, P.nx, P.bcx, false, ix);
   int nyi = 1;
@@ -684,7 +768,7 @@ __global__ void k_adj_fold(Params P, RefGrid G, AdjIO io, const double* __restri
   for (int v = 0; v < NV; ++v) io.lam0[c + v * P.ncell] = acc[v];
 }
 
-// ----------------------------------------------- K8: parameter reduction ----
+// ----------------------------------------------- K4: parameter reduction ----
 // Sum of the per-block partials in a fixed order (thread-strided, then a
 // tree), added to pgrad.
 __global__ void __launch_bounds__(256) k_adj_params_final(int nb, const double* partial, double* pgrad) {
@@ -725,7 +809,6 @@ static hipError_t adjoint_t(const Params& P, const double* Un, const double* lam
     hipLaunchKernelGGL((k_adj_flux<DIM, true>), dim3(nb), dim3(bs), 0, s, P, G, io, W, partial);
   else
     hipLaunchKernelGGL((k_adj_flux<DIM, false>), dim3(nb), dim3(bs), 0, s, P, G, io, W, partial);
-  hipLaunchKernelGGL(k_adj_cell<DIM>, dim3(nb), dim3(bs), 0, s, P, G, io, W);
   if (P.diss && P.low_mach)
     hipLaunchKernelGGL((k_adj_pgather<DIM, true, true>), dim3(nb), dim3(bs), 0, s, P, G, io, W);
   else if (P.diss)
@@ -734,8 +817,9 @@ static hipError_t adjoint_t(const Params& P, const double* Un, const double* lam
     hipLaunchKernelGGL((k_adj_pgather<DIM, false, true>), dim3(nb), dim3(bs), 0, s, P, G, io, W);
   else
     hipLaunchKernelGGL((k_adj_pgather<DIM, false, false>), dim3(nb), dim3(bs), 0, s, P, G, io, W);
-  const unsigned nc = (unsigned)((P.ncell + bs - 1) / bs);
-  hipLaunchKernelGGL(k_adj_fold<DIM>, dim3(nc), dim3(bs), 0, s, P, G, io, W);
+  // the cells next to a boundary (the primitive gather folded the others)
+  const unsigned nc = (unsigned)((boundary_count<DIM>(P) + bs - 1) / bs);
+  if (nc > 0) hipLaunchKernelGGL(k_adj_fold<DIM>, dim3(nc), dim3(bs), 0, s, P, G, io, W);
   if (P.diss && pgrad) hipLaunchKernelGGL(k_adj_params_final, dim3(1), dim3(256), 0, s, (int)nb, partial, pgrad);
   return hipGetLastError();
 }

@@ -97,9 +97,30 @@ __global__ void __launch_bounds__(256) k_spec_cols(Params P, int c, const double
   }
 }
 
+// Largest k >= 0 with 4 k^2 < q (q > 0), from a floating estimate corrected
+// in integers.
+__device__ __forceinline__ long long kmax_below(long long q) {
+  long long k = (long long)sqrt((double)q * 0.25);
+  while (k > 0 && 4 * k * k >= q) --k;
+  while (4 * (k + 1) * (k + 1) < q) ++k;
+  return k;
+}
+
+// Power of the wave vectors (kx, ky) of one row with |kx| = k, both signs
+// where the FFT order holds them (+k at index k if k < (n+1)/2; -k at index
+// n - k if 1 <= k <= n/2).
+__device__ __forceinline__ double row_pair(const double* __restrict__ row, int n, long long k) {
+  double s = 0.0;
+  if (k < (n + 1) / 2) s += row[k];
+  if (k >= 1 && k <= n / 2) s += row[n - k];
+  return s;
+}
+
 // Shell sums: block s adds Pw over the wave vectors with round(|k|) = s,
 // i.e. (2s - 1)^2 < 4 |k|^2 < (2s + 1)^2 (4 |k|^2 is even, so no bound is
-// ever met exactly), and stores the sum / (2 N^2).
+// ever met exactly), and stores the sum / (2 N^2).  Thread t takes the rows
+// t, t + 256, ...; in a row it walks only the |kx| of the annulus, in
+// increasing order; a fixed tree then adds the threads: deterministic.
 __global__ void __launch_bounds__(256) k_spec_shells(Params P, const double* __restrict__ Pw, double* __restrict__ E) {
   __shared__ double red[256];
   const int nx = P.nx, ny = P.ny, s = blockIdx.x;
@@ -107,11 +128,14 @@ __global__ void __launch_bounds__(256) k_spec_shells(Params P, const double* __r
   const long long hi = (2LL * s + 1) * (2LL * s + 1);
   const long long lo = s == 0 ? -1 : (2LL * s - 1) * (2LL * s - 1);
   double acc = 0.0;
-  for (long long f = threadIdx.x; f < N; f += blockDim.x) {
-    const long long kx = fft_wavenumber((int)(f % nx), nx);
-    const long long ky = fft_wavenumber((int)(f / nx), ny);
-    const long long q4 = 4 * (kx * kx + ky * ky);
-    if (q4 > lo && q4 < hi) acc += Pw[f];
+  for (int y = threadIdx.x; y < ny; y += blockDim.x) {
+    const long long ky = fft_wavenumber(y, ny);
+    const long long r = 4 * ky * ky;
+    if (r >= hi) continue;
+    const long long kb = kmax_below(hi - r);                    // 4 kx^2 < hi - r
+    const long long ka = lo - r < 0 ? 0 : kmax_below(lo - r + 1) + 1;  // 4 kx^2 > lo - r
+    const double* row = Pw + (long long)y * nx;
+    for (long long k = ka; k <= kb; ++k) acc += row_pair(row, nx, k);
   }
   red[threadIdx.x] = acc;
   __syncthreads();
