@@ -79,6 +79,20 @@ def config5(n=128):
     return rb([n, n, n], [1.0, 1.0, 1.0], Ra=1e5)
 
 
+def rb3d_weak(n=64, low_mach=1, chi=1.1, m=0.1, Ra=6.5e5, Pr=1.0, amp=1e-3, seed=0):
+    """The 3D convection run of Sec. 4.5 whose middle-plane kinetic-energy
+    spectrum the paper shows: polytropic index m = 0.1, Ra = 6.5e5, fixed-T
+    walls, unit cube, periodic x/y.  The paper calls the stratification
+    weak but gives no density ratio for 3D; the 2D weak case's chi = 1.1 is
+    taken: T_top / T_bottom = chi^(-1/m) and g = (m + 1)(T_bottom - T_top)
+    (R = 1, unit depth), so that the linear-T base is the m polytrope with
+    that density ratio.  Pr (not given) = 1."""
+    T_top = chi ** (-1.0 / m)
+    g = (m + 1.0) * (1.0 - T_top)
+    return rb([n, n, n], [1.0, 1.0, 1.0], Ra=Ra, Pr=Pr, low_mach=low_mach, seed=seed, amp=amp, T_bottom=1.0,
+              T_top=T_top, g=g)
+
+
 def splitmix64(state):
     """One SplitMix64 step (published definition); returns (new_state, out)."""
     M = (1 << 64) - 1
