@@ -79,6 +79,20 @@ def config5(n=128):
     return rb([n, n, n], [1.0, 1.0, 1.0], Ra=1e5)
 
 
+def rb2d_weak(n=32, Ra=2000.0, low_mach=1, chi=1.1, m=1.3, Pr=1.0, amp=1e-4, seed=1):
+    """The 2D onset runs of Sec. 4.5: weak stratification chi = 1.1 and
+    m = 1.3 (close to the adiabatic gradient), so the convective flows are
+    slow.  Box [0, 2] x [0, 1] with 2n x n cells (the paper gives 128^2 and
+    no box), fixed-T walls (the paper imposes the heat flux at the bottom, a
+    wall kind this library does not have), seeded temperature noise (the
+    paper starts near the fundamental velocity mode).  T_top / T_bottom =
+    chi^(-1/m), g = (m + 1)(T_bottom - T_top)."""
+    T_top = chi ** (-1.0 / m)
+    g = (m + 1.0) * (1.0 - T_top)
+    return rb([2 * n, n], [2.0, 1.0], Ra=Ra, Pr=Pr, low_mach=low_mach, seed=seed, amp=amp, T_bottom=1.0,
+              T_top=T_top, g=g)
+
+
 def rb3d_weak(n=64, low_mach=1, chi=1.1, m=0.1, Ra=6.5e5, Pr=1.0, amp=1e-3, seed=0):
     """The 3D convection run of Sec. 4.5 whose middle-plane kinetic-energy
     spectrum the paper shows: polytropic index m = 0.1, Ra = 6.5e5, fixed-T
