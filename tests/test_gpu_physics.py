@@ -194,3 +194,37 @@ def test_gresho_error_vs_mach_512():
     # is four orders of magnitude smaller and the vortex keeps its energy
     assert off[-1][0] > 0.9 * 0.2513
     assert on[-1][0] < 1e-3 * off[-1][0] and on[-1][1] > 0.999
+
+
+@pytest.mark.parametrize("N", [128, 256, 512, 1024, 2048, 4096])
+def test_isothermal_column_table1_gpu(N):
+    """Table 1 (Sec. 4.3) at every size the paper prints: the isothermal
+    atmosphere p = rho = exp(-z) on [0, 3] (a column of N cells, one cell
+    wide and periodic across), walls at both ends, run to t = 10; the
+    maximum velocity stays at the printed round-off level, with the
+    correction (theta = Ma) and without (theta = 1).  Bound: 10x the table,
+    as the oracle's pin (which covers N <= 1024)."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1903_09043_amd as A
+    table = {128: (2.9e-15, 1.4e-13), 256: (8.1e-15, 5.7e-13), 512: (1.5e-14, 1.1e-12),
+             1024: (2.2e-14, 2.2e-12), 2048: (4.7e-14, 1.6e-12), 4096: (1.1e-13, 4.0e-12)}
+    for lm in (0, 1):
+        cfg = dict(dim=2, n=[1, N], L=[3.0 / N, 3.0], gamma=5.0 / 3.0, g=1.0, mu=0.0, kappa=0.0, K=1.1, cfl=0.4,
+                   low_mach=lm, dt_mode=0, bc=[[W.BC_PERIODIC, W.BC_PERIODIC], [W.BC_WALL, W.BC_WALL]],
+                   wall_noslip=1, thermal=[W.TH_ADIABATIC, W.TH_ADIABATIC], T_wall=[1.0, 1.0])
+        S = A.Solver(cfg).init(W.PROB_ISOTHERMAL)
+        S.step(int(10.0 / S.dt.item()) - 1)
+        while True:
+            rest = 10.0 - S.t.item()
+            if rest <= 0.0:
+                break
+            S.compute_dt()
+            S.step_sched(torch.tensor([min(S.dt.item(), rest)], dtype=torch.float64))
+        rc, fc = S.fault()
+        assert rc == 0, fc
+        U = S.U
+        umax = float(torch.max(torch.sqrt(U[1] ** 2 + U[2] ** 2) / U[0]))
+        say(f"N {N} theta {'Ma' if lm else '1'}: t {S.t.item():.6f}, max |u| {umax:.2e} (table {table[N][lm]:.1e})")
+        assert umax <= 10 * table[N][lm], (N, lm, umax)
