@@ -123,7 +123,9 @@ typedef struct ars_diag {
 
 typedef struct ars_ctx ars_ctx;
 
-/* Host-only check of a configuration (no device needed). */
+/* Host-only check of a configuration (no device needed).  ARS_EINVAL for
+ * an out-of-range field or more than 2^31 cells (a 1290^3 grid; its state
+ * pair takes 172 GB of the 288 GB of one MI355X). */
 int ars_validate(const ars_config* cfg);
 
 /* Create / destroy a context (host memory only; no device allocation).

@@ -249,6 +249,8 @@ class Solver:
         self.ctx = Context(cfg)
         self.cfg = self.ctx.cfg
         self.device = torch.device(device)
+        if self.device.index is None:
+            self.device = torch.device(self.device.type, torch.cuda.current_device())
         shape = state_shape(cfg)
         self.U = torch.zeros(shape, dtype=torch.float64, device=self.device)
         self.tmp = torch.empty_like(self.U)
@@ -261,6 +263,18 @@ class Solver:
     @property
     def stream(self):
         return C.c_void_p(self.torch.cuda.current_stream(self.device).cuda_stream)
+
+    def _arg(self, x, n, name):
+        """Device pointer of a caller tensor after checking what the C ABI
+        assumes of it: FP64, contiguous, on this solver's device, and at
+        least n elements (a kernel would otherwise read or write past it)."""
+        if x is None:
+            return None
+        t = self.torch
+        if not isinstance(x, t.Tensor) or x.dtype != t.float64 or not x.is_contiguous() or x.device != self.device \
+                or x.numel() < n:
+            raise ValueError(f"{name}: need a contiguous float64 tensor of >= {n} elements on {self.device}")
+        return _ptr(x)
 
     def init(self, problem: int, params=(), seed: int = 0):
         p = np.asarray(list(params) + [0.0], dtype=np.float64)
@@ -316,8 +330,10 @@ class Solver:
             lam_n = t.empty_like(lam_np1)
         dt = dt.to(self.device, t.float64).reshape(-1)
         w = self.adjoint_workspace()
-        _check(lib().ars_step_adjoint(self.ctx.h, _ptr(U_n), _ptr(lam_np1), _ptr(lam_n), _ptr(dt),
-                                      _ptr(param_grad) if param_grad is not None else None, _ptr(w), self.stream),
+        L = self.ctx.state_len
+        _check(lib().ars_step_adjoint(self.ctx.h, self._arg(U_n, L, "U_n"), self._arg(lam_np1, L, "lam_np1"),
+                                      self._arg(lam_n, L, "lam_n"), self._arg(dt, 1, "dt"),
+                                      self._arg(param_grad, 2, "param_grad"), _ptr(w), self.stream),
                "ars_step_adjoint")
         return lam_n
 
@@ -327,8 +343,10 @@ class Solver:
         t = self.torch
         U = self.U if U is None else U
         out = t.zeros(1, dtype=t.float64, device=self.device) if out is None else out
-        _check(lib().ars_kinetic_energy(self.ctx.h, _ptr(U), _ptr(grad) if grad is not None else None, _ptr(out),
-                                        _ptr(self.work), self.stream), "ars_kinetic_energy")
+        L = self.ctx.state_len
+        _check(lib().ars_kinetic_energy(self.ctx.h, self._arg(U, L, "U"), self._arg(grad, L, "grad"),
+                                        self._arg(out, 1, "out"), _ptr(self.work), self.stream),
+               "ars_kinetic_energy")
         return out
 
     def nusselt(self, side=0, U=None, grad=None, out=None):
@@ -337,8 +355,9 @@ class Solver:
         t = self.torch
         U = self.U if U is None else U
         out = t.zeros(1, dtype=t.float64, device=self.device) if out is None else out
-        _check(lib().ars_nusselt(self.ctx.h, _ptr(U), int(side), _ptr(grad) if grad is not None else None,
-                                 _ptr(out), _ptr(self.work), self.stream), "ars_nusselt")
+        L = self.ctx.state_len
+        _check(lib().ars_nusselt(self.ctx.h, self._arg(U, L, "U"), int(side), self._arg(grad, L, "grad"),
+                                 self._arg(out, 1, "out"), _ptr(self.work), self.stream), "ars_nusselt")
         return out
 
     def spectrum(self, kz=None, U=None, out=None):
@@ -350,9 +369,11 @@ class Solver:
         kz = int(self.cfg["n"][int(self.cfg["dim"]) - 1]) // 2 if kz is None else int(kz)
         if getattr(self, "_wspec", None) is None:
             self._wspec = t.empty(lib().ars_workspace_bytes_spectrum(h), dtype=t.uint8, device=self.device)
+        ns = lib().ars_spectrum_len(h)
         if out is None:
-            out = t.empty(lib().ars_spectrum_len(h), dtype=t.float64, device=self.device)
-        _check(lib().ars_spectrum(h, _ptr(U), kz, _ptr(out), _ptr(self._wspec), self.stream), "ars_spectrum")
+            out = t.empty(ns, dtype=t.float64, device=self.device)
+        _check(lib().ars_spectrum(h, self._arg(U, self.ctx.state_len, "U"), kz, self._arg(out, ns, "out"),
+                                  _ptr(self._wspec), self.stream), "ars_spectrum")
         return out
 
     def diagnostics(self, raise_on_fault=True) -> dict:

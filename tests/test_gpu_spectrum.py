@@ -109,3 +109,32 @@ def test_spectrum_max_plane(A):
     cfg = cfg_of(3, [2048, 2048, 2])
     U = I.white_random(cfg, 24, amp=0.3)
     check(gpu_spectrum(A, cfg, U, 1), O.spectrum(cfg, U, 1))
+
+
+def test_binding_rejects_bad_tensors(A):
+    """The binding checks caller tensors before passing their pointers to
+    the C ABI (the kernels would read past a short or mistyped buffer): no
+    kernel runs for any of these calls."""
+    import torch
+    cfg = cfg_of(3, [16, 12, 8])
+    S = A.Solver(cfg)
+    S.set_state(I.white_random(cfg, 1))
+    good = S.U.clone()
+    bad = [good.float(), good.transpose(1, 2), good.reshape(-1)[:-1], good.cpu()]
+    for U in bad:
+        with pytest.raises(ValueError):
+            S.spectrum(U=U)
+        with pytest.raises(ValueError):
+            S.kinetic_energy(U=U)
+    with pytest.raises(ValueError):
+        S.spectrum(out=torch.empty(3, dtype=torch.float64, device="cuda"))
+    lam = torch.zeros_like(good)
+    with pytest.raises(ValueError):
+        S.step_adjoint(good, lam.reshape(-1)[:-1], torch.tensor([1e-3], dtype=torch.float64))
+    with pytest.raises(ValueError):
+        S.step_adjoint(good, lam, torch.tensor([1e-3], dtype=torch.float64),
+                       param_grad=torch.zeros(1, dtype=torch.float64, device="cuda"))
+    # and the good tensors pass
+    E = S.spectrum(U=good)
+    torch.cuda.synchronize()
+    assert torch.isfinite(E).all()
