@@ -60,8 +60,10 @@ def gpu_adjoint(A, cfg, U, lam, dt):
     return out.cpu().numpy(), pg.cpu().numpy()
 
 
+# the *_bulk cases are wide enough in every direction to hold cells two or
+# more cells from every boundary, whose reverse is folded in place
 CASES = ["rb2d_walls", "rb2d_thetaoff_freeslip", "rb3d_walls", "periodic2d_inviscid", "outflow2d_viscous",
-         "periodic3d_viscous"]
+         "periodic3d_viscous", "rb3d_walls_bulk", "periodic3d_bulk"]
 
 
 def make_case(name):
@@ -75,7 +77,14 @@ def make_case(name):
     if name == "rb3d_walls":
         cfg, prob, prm, seed = W.rb([5, 4, 6], [1.0, 1.0, 1.0], Ra=1e4, seed=5, amp=1e-3)
         return cfg, perturbed(cfg, prob, prm, seed)
+    if name == "rb3d_walls_bulk":
+        cfg, prob, prm, seed = W.rb([6, 5, 7], [1.0, 1.0, 1.0], Ra=1e4, seed=9, amp=1e-3)
+        return cfg, perturbed(cfg, prob, prm, seed)
     base = dict(gamma=5.0 / 3.0, g=0.0, K=1.1, cfl=0.4, dt_mode=0, wall_noslip=1, thermal=[0, 0], T_wall=[1.0, 1.0])
+    if name == "periodic3d_bulk":
+        cfg = dict(base, dim=3, n=[7, 6, 5], L=[1.0, 1.0, 1.0], mu=3e-3, kappa=4e-3, low_mach=1,
+                   bc=[[0, 0], [0, 0], [0, 0]])
+        return cfg, I.white_random(cfg, seed=10, amp=0.2)
     if name == "periodic2d_inviscid":
         cfg = dict(base, dim=2, n=[8, 7], L=[1.0, 1.0], mu=0.0, kappa=0.0, low_mach=1, bc=[[0, 0], [0, 0]])
         return cfg, I.white_random(cfg, seed=6, amp=0.2)
