@@ -96,8 +96,8 @@ __device__ __forceinline__ void march_tile(const Params& P, const double* __rest
   const int pxpym = (DIM == 3 && px + 1 < EX && py > 0) ? tid - EX + 1 : tid;
   const int pxmyp = (DIM == 3 && px > 0 && py + 1 < EY) ? tid + EX - 1 : tid;
   // Positions that own a lateral face some output cell needs, and positions
-  // of output cells (tile interior); with 2 rows of 32 per wave the halo
-  // rows form whole waves, which then skip those stages.
+  // of output cells (tile interior); the first and the last wave of a 3D
+  // tile hold only halo rows and skip those stages.
   const bool inx1 = px >= 1 && px <= EX - 3;
   const bool inx2 = px >= 2 && px <= EX - 3;
   const bool iny1 = (DIM == 2) || (py >= 1 && py <= EY - 3);

@@ -33,7 +33,8 @@ __global__ void __launch_bounds__(EX* EY) k_step_fused(Params P, const double* _
   constexpr int NPOS = EX * EY;
   using Ly = FusedLayout<DIM>;
   __shared__ double sm[Ly::TOTAL * NPOS];
-  __shared__ double red[NPOS / 64];
+  constexpr int NW = (NPOS + 63) / 64;  // waves (the last one partial if 64 does not divide NPOS)
+  __shared__ double red[NW];
 
   const int tid = threadIdx.x;
   // time step of this step
@@ -80,16 +81,28 @@ __global__ void __launch_bounds__(EX* EY) k_step_fused(Params P, const double* _
   }
   if (io.rate_out) {
     double m = lmax;
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-      const double o2 = __shfl_xor(m, off, 64);
-      m = o2 > m ? o2 : m;
+    if (NPOS % 64 != 0) {
+      // a partial last wave has no lanes past NPOS to shuffle with: gather
+      // every position's rate into wave 0 through LDS (free after the march)
+      __syncthreads();
+      sm[tid] = lmax;
+      __syncthreads();
+      m = 0.0;
+      if (tid < 64)
+        for (int j = tid; j < NPOS; j += 64) m = sm[j] > m ? sm[j] : m;
     }
-    if ((tid & 63) == 0) red[tid >> 6] = m;
+    if (NPOS % 64 == 0 || tid < 64) {
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) {
+        const double o2 = __shfl_xor(m, off, 64);
+        m = o2 > m ? o2 : m;
+      }
+      if ((tid & 63) == 0) red[tid >> 6] = m;
+    }
     __syncthreads();
     if (tid == 0) {
       double mm = red[0];
-      for (int w = 1; w < NPOS / 64; ++w) mm = red[w] > mm ? red[w] : mm;
+      for (int w = 1; w < (NPOS % 64 == 0 ? NW : 1); ++w) mm = red[w] > mm ? red[w] : mm;
       atomic_max_rate(io.rate_out, mm);
     }
   }
@@ -149,8 +162,8 @@ hipError_t launch_step_fused(const Params& P, const double* Uin, double* Uout, S
   if (P.dim == 2)
     return P.nc ? launch_variant<2, true, 64, 1>(P, Uin, Uout, io, ts, s)
                 : launch_variant<2, false, 64, 1>(P, Uin, Uout, io, ts, s);
-  return P.nc ? launch_variant<3, true, 32, 16>(P, Uin, Uout, io, ts, s)
-              : launch_variant<3, false, 32, 16>(P, Uin, Uout, io, ts, s);
+  return P.nc ? launch_variant<3, true, 36, 14>(P, Uin, Uout, io, ts, s)
+              : launch_variant<3, false, 36, 14>(P, Uin, Uout, io, ts, s);
 }
 
 }  // namespace ars
