@@ -188,7 +188,14 @@ __device__ __forceinline__ void march_tile(const Params& P, const double* __rest
 #pragma unroll
       for (int k = 0; k < DIM; ++k) sm[(Ly::DZ + k) * NPOS + tid] = q0.u[k] - u2[k];
     }
-    __syncthreads();  // ---------------------------------------------- bar 1
+    // Step 2a needs only the -x/-y faces of plane p-1 (published before the
+    // previous barrier) and this column's z faces, so it may run before or
+    // after bar 1.  3D runs it after bar 1 and publishes F behind a second
+    // barrier (this balances the work between barriers against the
+    // halo-only waves); 2D runs it before bar 1 and needs no second barrier
+    // (both orders measured on both).
+    constexpr bool EARLY_L = (DIM == 2);
+    if constexpr (!EARLY_L) __syncthreads();  // -------------------------- bar 1
 
     // ================= step 2a: acoustic cell values of plane p-1 ===========
     const bool doL = (p - 1 >= z0 - 1) && (p - 1 <= z1) && (UNI || needL);
@@ -245,6 +252,8 @@ __device__ __forceinline__ void march_tile(const Params& P, const double* __rest
         badcell = min(badcell, cell);
       }
     }
+    if constexpr (EARLY_L) __syncthreads();  // --------------------------- bar 1
+
     // ================= step 2b: own lateral acoustic faces of plane p =======
     double Fn[3 * (DIM - 1)];
     const bool doA = (p >= z0 - 1) && (p <= z1);
@@ -260,7 +269,7 @@ __device__ __forceinline__ void march_tile(const Params& P, const double* __rest
 #pragma unroll
       for (int i = 0; i < 3 * (DIM - 1); ++i) Fn[i] = 0.0;
     }
-    __syncthreads();  // ---------------------------------------------- bar 2
+    if constexpr (!EARLY_L) __syncthreads();  // ------------------------- bar 1b
 
     // ================= step 3 ==============================================
 #pragma unroll
@@ -450,7 +459,7 @@ __device__ __forceinline__ void march_tile(const Params& P, const double* __rest
       const bool ok = (nb[0] > 0.0) && (qn.p > 0.0) && isfinite(nb[0]) && isfinite(qn.p) && isfinite(kin);
       if (!ok) badcell = min(badcell, (unsigned long long)cell);
     }
-    __syncthreads();  // ---------------------------------------------- bar 3
+    __syncthreads();  // ---------------------------------------------- bar 2
 
     // ================= step 4: publish lateral fluxes of plane p-1 ==========
     if (doG && (UNI || needGx)) {
