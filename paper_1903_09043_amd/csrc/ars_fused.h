@@ -7,6 +7,23 @@
 
 namespace ars {
 
+// Synchronisation of the march between its LDS stages.  A 3D tile shares
+// LDS between all waves of the workgroup: a workgroup barrier.  In 2D every
+// row segment is one wave (64 positions) whose LDS slots and neighbours
+// never leave that wave, so ordering the wave's own LDS accesses is enough:
+// a wave-scope fence around a wave barrier (no inter-wave wait; the waves
+// of a batched workgroup march independently between step barriers).
+template <int DIM>
+__device__ __forceinline__ void plane_sync() {
+  if constexpr (DIM == 3) {
+    __syncthreads();
+  } else {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+}
+
 template <int DIM>
 struct FusedLayout;
 template <>
@@ -77,6 +94,7 @@ __device__ __forceinline__ void march_tile(const Params& P, const double* __rest
   // branch-free; 3D keeps the per-position guards that let whole halo
   // waves skip stages.
   constexpr bool UNI = (DIM == 2);
+  static_assert(DIM == 3 || EX == 64, "a 2D row segment is exactly one wave (plane_sync relies on it)");
   constexpr int TY = (DIM == 3) ? EY - 4 : 1;
   constexpr int Z = DIM - 1;  // index of the vertical velocity component
   using Ly = FusedLayout<DIM>;
@@ -195,7 +213,7 @@ __device__ __forceinline__ void march_tile(const Params& P, const double* __rest
     // halo-only waves); 2D runs it before bar 1 and needs no second barrier
     // (both orders measured on both).
     constexpr bool EARLY_L = (DIM == 2);
-    if constexpr (!EARLY_L) __syncthreads();  // -------------------------- bar 1
+    if constexpr (!EARLY_L) plane_sync<DIM>();  // ------------------------ bar 1
 
     // ================= step 2a: acoustic cell values of plane p-1 ===========
     const bool doL = (p - 1 >= z0 - 1) && (p - 1 <= z1) && (UNI || needL);
@@ -252,7 +270,7 @@ __device__ __forceinline__ void march_tile(const Params& P, const double* __rest
         badcell = min(badcell, cell);
       }
     }
-    if constexpr (EARLY_L) __syncthreads();  // --------------------------- bar 1
+    if constexpr (EARLY_L) plane_sync<DIM>();  // ------------------------- bar 1
 
     // ================= step 2b: own lateral acoustic faces of plane p =======
     double Fn[3 * (DIM - 1)];
@@ -269,7 +287,7 @@ __device__ __forceinline__ void march_tile(const Params& P, const double* __rest
 #pragma unroll
       for (int i = 0; i < 3 * (DIM - 1); ++i) Fn[i] = 0.0;
     }
-    if constexpr (!EARLY_L) __syncthreads();  // ------------------------- bar 1b
+    if constexpr (!EARLY_L) plane_sync<DIM>();  // ----------------------- bar 1b
 
     // ================= step 3 ==============================================
 #pragma unroll
@@ -459,7 +477,7 @@ __device__ __forceinline__ void march_tile(const Params& P, const double* __rest
       const bool ok = (nb[0] > 0.0) && (qn.p > 0.0) && isfinite(nb[0]) && isfinite(qn.p) && isfinite(kin);
       if (!ok) badcell = min(badcell, (unsigned long long)cell);
     }
-    __syncthreads();  // ---------------------------------------------- bar 2
+    plane_sync<DIM>();  // -------------------------------------------- bar 2
 
     // ================= step 4: publish lateral fluxes of plane p-1 ==========
     if (doG && (UNI || needGx)) {
