@@ -25,7 +25,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
-FP64_VALU_PEAK_TFS = 78.6  # MI355X FP64 vector (FMA counted as 2 flops)
+FP64_MFMA_PEAK_TFS = 78.6  # MI355X dense FP64 matrix cores
 
 
 def kernel_hash():
@@ -112,15 +112,16 @@ def timed(torch, fn, stream=None):
 
 def spectrum_leg(torch, S, n, reps=20):
     """Kinetic-energy spectrum of the middle horizontal plane of the stepped
-    state (ars_spectrum: direct DFT along x, then y, then shell sums).
-    Arithmetic: 4 flops per (kx, x) pair of the row transforms and 8 per
-    (ky, y) pair of the column transforms, for each of the 3 components."""
+    state (ars_spectrum: dense DFT along x, then y, on the FP64 matrix
+    cores, then shell sums).  Arithmetic: 4 flops per (kx, x) pair of the
+    row transforms and 8 per (ky, y) pair of the column transforms, for
+    each of the 3 components."""
     S.spectrum()
     ms = timed(torch, lambda: [S.spectrum() for _ in range(reps)]) / reps
     flops = 3 * n * n * (4 * n + 8 * n)
     return {"plane": [n, n], "shells": int(S.spectrum().numel()), "ms_per_call": round(ms, 4),
-            "alu": {"achieved_TFLOPs": round(flops / (ms * 1e-3) / 1e12, 3), "peak": FP64_VALU_PEAK_TFS,
-                    "frac": round(flops / (ms * 1e-3) / 1e12 / FP64_VALU_PEAK_TFS, 4)}}
+            "mfma": {"achieved_TFLOPs": round(flops / (ms * 1e-3) / 1e12, 3), "peak": FP64_MFMA_PEAK_TFS,
+                     "frac": round(flops / (ms * 1e-3) / 1e12 / FP64_MFMA_PEAK_TFS, 4)}}
 
 
 def adjoint_leg(torch, A, W, nsteps=200, slots=16, reps=20, end_to_end=True):

@@ -8,11 +8,15 @@
 // j - n), N the cell count of the plane; sum_s E(s) is then the plane mean of
 // rho |u|^2 / 2 (Parseval).  In 2D the plane is a line along x.
 //
-// The transform is a direct DFT, rows then columns, with the twiddle table
-// of each length in LDS and the exponent k x reduced modulo n exactly in
-// integers; the plane is at most 2048 x 2048, so the O(N (n_x + n_y)) cost
-// stays in the milliseconds.  Shell sums visit the plane in a fixed order
-// and reduce through a fixed tree: the result is deterministic.
+// The transform is a dense DFT, rows then columns, and a DFT is a matrix
+// product: the row transform is W (n_y x n_x) times the n_x x n_x twiddle
+// matrix, the column transform the n_y x n_y twiddle matrix times X, so
+// both run on the FP64 matrix cores (v_mfma_f64_16x16x4f64: one wave
+// accumulates a 16 x 16 tile over K in steps of 4).  The twiddle matrices
+// are never stored: entry (k, x) is read from an LDS table of
+// exp(-2 pi i j / n) at j = k x mod n, the exponent carried exactly in
+// integers.  Shell sums visit the plane in a fixed order and reduce
+// through a fixed tree: the result is deterministic.
 #include "ars_dev.h"
 #include "ars_internal.h"
 
@@ -32,68 +36,125 @@ __device__ __forceinline__ void fill_twiddles(double* tw, int n) {
   }
 }
 
-// Row transforms: block (y, c) loads w_c on row y of the plane and writes
-// X_c(y, kx) = sum_x w_c(x, y) exp(-2 pi i kx x / nx).
-__global__ void __launch_bounds__(256) k_spec_rows(Params P, const double* __restrict__ U, int kz,
-                                                   double* __restrict__ Xr, double* __restrict__ Xi) {
-  extern __shared__ double sm[];
-  const int nx = P.nx, y = blockIdx.x, c = blockIdx.y;
-  double* w = sm;
-  double* tw = sm + nx;
-  const long long base = ((long long)kz * P.ny + y) * nx;
-  for (int x = threadIdx.x; x < nx; x += blockDim.x) {
-    const double rho = U[base + x];
-    const double m = U[(long long)(1 + c) * P.ncell + base + x];
-    w[x] = sqrt(rho) * (m / rho);
-  }
-  fill_twiddles(tw, nx);
-  __syncthreads();
-  const long long o = ((long long)c * P.ny + y) * nx;
-  for (int kx = threadIdx.x; kx < nx; kx += blockDim.x) {
-    double ar = 0.0, ai = 0.0;
-    int e = 0;  // kx x mod nx
-    for (int x = 0; x < nx; ++x) {
-      ar += w[x] * tw[e];
-      ai += w[x] * tw[nx + e];
-      e += kx;
-      if (e >= nx) e -= nx;
-    }
-    Xr[o + kx] = ar;
-    Xi[o + kx] = ai;
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+// One 16 x 16 x 4 FP64 matrix step: C (16 x 16) += A (16 x 4) B (4 x 16).
+// Lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16]; it holds
+// C[l / 16 + 4 r][l % 16] in element r.
+__device__ __forceinline__ dbl4 mma16(double a, double b, dbl4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// w_c = sqrt(rho) u_c on the plane, W[c][y][x].
+__global__ void __launch_bounds__(256) k_spec_w(Params P, const double* __restrict__ U, int kz,
+                                                double* __restrict__ W) {
+  const long long N = (long long)P.nx * P.ny;
+  const long long base = (long long)kz * N;
+  for (long long f = (long long)blockIdx.x * blockDim.x + threadIdx.x; f < N * P.dim;
+       f += (long long)gridDim.x * blockDim.x) {
+    const int c = (int)(f / N);
+    const long long i = f - c * N;
+    const double rho = U[base + i];
+    const double m = U[(long long)(1 + c) * P.ncell + base + i];
+    W[f] = sqrt(rho) * (m / rho);
   }
 }
 
-// Column transforms of component c: block kx loads X_c(., kx) and adds
-// |Y_c(ky, kx)|^2 to Pw(ky, kx) (stored when c == 0), with
-// Y_c(ky, kx) = sum_y X_c(y, kx) exp(-2 pi i ky y / ny).  The components are
-// launched in order, so Pw = |Y_0|^2 + |Y_1|^2 + |Y_2|^2 in that order.
-__global__ void __launch_bounds__(256) k_spec_cols(Params P, int c, const double* __restrict__ Xr,
-                                                   const double* __restrict__ Xi, double* __restrict__ Pw) {
-  extern __shared__ double sm[];
-  const int nx = P.nx, ny = P.ny, kx = blockIdx.x;
-  double* vr = sm;
-  double* vi = sm + ny;
-  double* tw = sm + 2 * ny;
-  const long long o = (long long)c * ny * nx;
-  for (int y = threadIdx.x; y < ny; y += blockDim.x) {
-    vr[y] = Xr[o + (long long)y * nx + kx];
-    vi[y] = Xi[o + (long long)y * nx + kx];
+// Row transforms X_c = W_c T_x, T_x(x, k) = exp(-2 pi i k x / n_x): block
+// (kx group of 64, row tile of 16, component c), wave w the 16 x 16 tile of
+// rows y0.. and wave numbers k0 = 64 bx + 16 w ..; real and imaginary
+// parts in two accumulators.  Out-of-range rows, columns and K entries
+// contribute zeros.
+__global__ void __launch_bounds__(256) k_spec_rows(Params P, const double* __restrict__ W, double* __restrict__ Xr,
+                                                   double* __restrict__ Xi) {
+  extern __shared__ double tw[];
+  const int nx = P.nx, ny = P.ny, c = blockIdx.z;
+  fill_twiddles(tw, nx);
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i = lane & 15, q = lane >> 4;
+  const int y0 = blockIdx.y * 16, k0 = blockIdx.x * 64 + wave * 16;
+  const int y = y0 + i, k = k0 + i;  // A row of this lane, B column of this lane
+  const double* Wr = W + ((long long)c * ny + (y < ny ? y : 0)) * nx;
+  const int dk = (int)((4LL * k) % nx);
+  int e = (int)(((long long)k * q) % nx);  // k x mod n_x at x = q
+  dbl4 ar = {0.0, 0.0, 0.0, 0.0}, ai = {0.0, 0.0, 0.0, 0.0};
+  // K in blocks of 8 steps: all operand loads of a block are issued before
+  // its 16 matrix steps
+  for (int x0 = 0; x0 < nx; x0 += 32) {
+    double a[8], br[8], bi[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int x = x0 + 4 * j + q;
+      const bool in = x < nx;
+      a[j] = (in && y < ny) ? Wr[x] : 0.0;
+      br[j] = (in && k < nx) ? tw[e] : 0.0;
+      bi[j] = (in && k < nx) ? tw[nx + e] : 0.0;
+      e += dk;
+      if (e >= nx) e -= nx;
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      ar = mma16(a[j], br[j], ar);
+      ai = mma16(a[j], bi[j], ai);
+    }
   }
+  const int kc = k0 + i;  // output column of this lane
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int yo = y0 + q + 4 * r;
+    if (yo < ny && kc < nx) {
+      const long long o = ((long long)c * ny + yo) * nx + kc;
+      Xr[o] = ar[r];
+      Xi[o] = ai[r];
+    }
+  }
+}
+
+// Column transforms Y_c = T_y X_c, T_y(ky, y) = exp(-2 pi i ky y / n_y),
+// and Pc[c](ky, k) = |Y_c(ky, k)|^2: block (k group of 64, ky tile of 16,
+// component c), wave w the 16 x 16 tile of ky0.. and k0 = 64 bx + 16 w ..
+__global__ void __launch_bounds__(256) k_spec_cols(Params P, const double* __restrict__ Xr,
+                                                   const double* __restrict__ Xi, double* __restrict__ Pc) {
+  extern __shared__ double tw[];
+  const int nx = P.nx, ny = P.ny, c = blockIdx.z;
   fill_twiddles(tw, ny);
   __syncthreads();
-  for (int ky = threadIdx.x; ky < ny; ky += blockDim.x) {
-    double ar = 0.0, ai = 0.0;
-    int e = 0;
-    for (int y = 0; y < ny; ++y) {
-      const double cr = tw[e], ci = tw[ny + e];
-      ar += vr[y] * cr - vi[y] * ci;
-      ai += vr[y] * ci + vi[y] * cr;
-      e += ky;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i = lane & 15, q = lane >> 4;
+  const int ky0 = blockIdx.y * 16, k0 = blockIdx.x * 64 + wave * 16;
+  const int ky = ky0 + i, k = k0 + i;  // A row (ky) and B column (k) of this lane
+  const long long o = (long long)c * ny * nx;
+  const int dky = (int)((4LL * ky) % ny);
+  int e = (int)(((long long)ky * q) % ny);  // ky y mod n_y at y = q
+  dbl4 yr = {0.0, 0.0, 0.0, 0.0}, yi = {0.0, 0.0, 0.0, 0.0};
+  for (int y0 = 0; y0 < ny; y0 += 32) {
+    double tr[8], ti[8], xr[8], xi[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int y = y0 + 4 * j + q;
+      const bool in = y < ny;
+      tr[j] = (in && ky < ny) ? tw[e] : 0.0;
+      ti[j] = (in && ky < ny) ? tw[ny + e] : 0.0;
+      const bool bk = in && k < nx;
+      xr[j] = bk ? Xr[o + (long long)y * nx + k] : 0.0;
+      xi[j] = bk ? Xi[o + (long long)y * nx + k] : 0.0;
+      e += dky;
       if (e >= ny) e -= ny;
     }
-    const double p = ar * ar + ai * ai;
-    const long long q = (long long)ky * nx + kx;
-    Pw[q] = c == 0 ? p : Pw[q] + p;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      // (tr + i ti)(xr + i xi)
+      yr = mma16(tr[j], xr[j], yr);
+      yr = mma16(-ti[j], xi[j], yr);
+      yi = mma16(tr[j], xi[j], yi);
+      yi = mma16(ti[j], xr[j], yi);
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int kyo = ky0 + q + 4 * r;
+    if (kyo < ny && k < nx) Pc[o + (long long)kyo * nx + k] = yr[r] * yr[r] + yi[r] * yi[r];
   }
 }
 
@@ -109,19 +170,28 @@ __device__ __forceinline__ long long kmax_below(long long q) {
 // Power of the wave vectors (kx, ky) of one row with |kx| = k, both signs
 // where the FFT order holds them (+k at index k if k < (n+1)/2; -k at index
 // n - k if 1 <= k <= n/2).
-__device__ __forceinline__ double row_pair(const double* __restrict__ row, int n, long long k) {
+// The power of wave vector index f: |Y_0|^2 + |Y_1|^2 (+ |Y_2|^2), summed in
+// component order.
+__device__ __forceinline__ double power_at(const double* __restrict__ Pc, long long N, int D, long long f) {
+  double p = Pc[f];
+  for (int c = 1; c < D; ++c) p = p + Pc[c * N + f];
+  return p;
+}
+
+__device__ __forceinline__ double row_pair(const double* __restrict__ Pc, long long N, int D, long long row, int n,
+                                           long long k) {
   double s = 0.0;
-  if (k < (n + 1) / 2) s += row[k];
-  if (k >= 1 && k <= n / 2) s += row[n - k];
+  if (k < (n + 1) / 2) s += power_at(Pc, N, D, row + k);
+  if (k >= 1 && k <= n / 2) s += power_at(Pc, N, D, row + n - k);
   return s;
 }
 
-// Shell sums: block s adds Pw over the wave vectors with round(|k|) = s,
+// Shell sums: block s adds the power over the wave vectors with round(|k|) = s,
 // i.e. (2s - 1)^2 < 4 |k|^2 < (2s + 1)^2 (4 |k|^2 is even, so no bound is
 // ever met exactly), and stores the sum / (2 N^2).  Thread t takes the rows
 // t, t + 256, ...; in a row it walks only the |kx| of the annulus, in
 // increasing order; a fixed tree then adds the threads: deterministic.
-__global__ void __launch_bounds__(256) k_spec_shells(Params P, const double* __restrict__ Pw, double* __restrict__ E) {
+__global__ void __launch_bounds__(256) k_spec_shells(Params P, const double* __restrict__ Pc, double* __restrict__ E) {
   __shared__ double red[256];
   const int nx = P.nx, ny = P.ny, s = blockIdx.x;
   const long long N = (long long)nx * ny;
@@ -134,8 +204,7 @@ __global__ void __launch_bounds__(256) k_spec_shells(Params P, const double* __r
     if (r >= hi) continue;
     const long long kb = kmax_below(hi - r);                    // 4 kx^2 < hi - r
     const long long ka = lo - r < 0 ? 0 : kmax_below(lo - r + 1) + 1;  // 4 kx^2 > lo - r
-    const double* row = Pw + (long long)y * nx;
-    for (long long k = ka; k <= kb; ++k) acc += row_pair(row, nx, k);
+    for (long long k = ka; k <= kb; ++k) acc += row_pair(Pc, N, P.dim, (long long)y * nx, nx, k);
   }
   red[threadIdx.x] = acc;
   __syncthreads();
@@ -153,22 +222,24 @@ int spectrum_shells(const Params& P) {
 
 size_t spectrum_work_bytes(const Params& P) {
   const size_t N = (size_t)P.nx * (size_t)P.ny;
-  return (size_t)(2 * P.dim + 1) * N * sizeof(double);
+  return (size_t)(4 * P.dim) * N * sizeof(double);
 }
 
 bool spectrum_supported(const Params& P) { return P.nx <= SPEC_MAXN && P.ny <= SPEC_MAXN; }
 
 hipError_t launch_spectrum(const Params& P, const double* U, int kz, double* E, void* work, hipStream_t s) {
   const long long N = (long long)P.nx * P.ny;
-  double* Xr = (double*)work;
+  double* Wp = (double*)work;
+  double* Xr = Wp + (long long)P.dim * N;
   double* Xi = Xr + (long long)P.dim * N;
-  double* Pw = Xi + (long long)P.dim * N;
-  hipLaunchKernelGGL(k_spec_rows, dim3((unsigned)P.ny, (unsigned)P.dim), dim3(256),
-                     (size_t)3 * P.nx * sizeof(double), s, P, U, kz, Xr, Xi);
-  for (int c = 0; c < P.dim; ++c)
-    hipLaunchKernelGGL(k_spec_cols, dim3((unsigned)P.nx), dim3(256), (size_t)4 * P.ny * sizeof(double), s, P, c,
-                       Xr, Xi, Pw);
-  hipLaunchKernelGGL(k_spec_shells, dim3((unsigned)spectrum_shells(P)), dim3(256), 0, s, P, Pw, E);
+  double* Pc = Xi + (long long)P.dim * N;
+  long long nb = (N * P.dim + 255) / 256;
+  if (nb > 4096) nb = 4096;
+  hipLaunchKernelGGL(k_spec_w, dim3((unsigned)nb), dim3(256), 0, s, P, U, kz, Wp);
+  const dim3 g((unsigned)((P.nx + 63) / 64), (unsigned)((P.ny + 15) / 16), (unsigned)P.dim);
+  hipLaunchKernelGGL(k_spec_rows, g, dim3(256), (size_t)2 * P.nx * sizeof(double), s, P, Wp, Xr, Xi);
+  hipLaunchKernelGGL(k_spec_cols, g, dim3(256), (size_t)2 * P.ny * sizeof(double), s, P, Xr, Xi, Pc);
+  hipLaunchKernelGGL(k_spec_shells, dim3((unsigned)spectrum_shells(P)), dim3(256), 0, s, P, Pc, E);
   return hipGetLastError();
 }
 

@@ -163,10 +163,10 @@ def test_spectrum_host_side():
         assert L.ars_spectrum_len(ctx.h) == shells
         ref = len(O.spectrum(dict(base, n=n), np.ones((5, n[2], n[1], n[0])), 0))
         assert ref == shells
-        assert L.ars_workspace_bytes_spectrum(ctx.h) == 7 * n[0] * n[1] * 8
+        assert L.ars_workspace_bytes_spectrum(ctx.h) == 12 * n[0] * n[1] * 8
     ctx2 = A.Context(W.config1()[0])
     assert L.ars_spectrum_len(ctx2.h) == 33
-    assert L.ars_workspace_bytes_spectrum(ctx2.h) == 5 * 64 * 8
+    assert L.ars_workspace_bytes_spectrum(ctx2.h) == 8 * 64 * 8
     d = C.c_void_p(1)
     ctx = A.Context(dict(base, n=[16, 16, 8]))
     assert L.ars_spectrum(ctx.h, d, 8, d, d, None) == A.EINVAL
