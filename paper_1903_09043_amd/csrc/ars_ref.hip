@@ -65,39 +65,46 @@ __global__ void k_ref_prim(Params P, RefGrid G, const double* __restrict__ U, do
 }
 
 
+// Acoustic faces (a, i | i + e_a) of padded cell i for every active axis
+// (one launch: the cell's own primitives are loaded once).
 template <int DIM, bool LM>
-__global__ void k_ref_face(Params P, RefGrid G, int a, double* __restrict__ W) {
+__global__ void k_ref_face(Params P, RefGrid G, double* __restrict__ W) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= G.npad) return;
   int qx, qy, qz;
   decode(G, i, qx, qy, qz);
-  const int qa = a == 0 ? qx : (a == 1 ? qy : qz);
-  const int Pa = a == 0 ? G.Px : (a == 1 ? G.Py : G.Pz);
-  if (qa + 1 >= Pa) return;
   const long long n = G.npad;
-  const long long j = i + astride(G, a);
-  const int k = (a == 2) ? DIM - 1 : a;  // normal velocity component
-  const int uf = ufield(DIM, k);
-  double us, pi, Pf, S = 0.0;
-  int wall = 0;
-  if (a == 2) {
-    wall = (qz == 1 && P.bcz[0] == BC_WALL) || (qz == P.nz + 1 && P.bcz[1] == BC_WALL);
-    Prim<DIM> L, R;
-    L.rho = W[R_RHO * n + i]; L.rc = W[R_RC * n + i]; L.irc = W[R_IRC * n + i]; L.ic = W[R_IC * n + i];
-    L.p = W[R_P * n + i]; L.u[DIM - 1] = W[uf * n + i];
-    R.rho = W[R_RHO * n + j]; R.rc = W[R_RC * n + j]; R.irc = W[R_IRC * n + j]; R.ic = W[R_IC * n + j];
-    R.p = W[R_P * n + j]; R.u[DIM - 1] = W[uf * n + j];
-    face_vert<LM, DIM>(P, L, R, phi_at(P, qz + 1 - 2) - phi_at(P, qz - 2), wall != 0, us, pi, Pf, S);
-  } else {
-    face_lat<LM>(P, W[R_RC * n + i], W[R_IRC * n + i], W[R_IC * n + i], W[R_P * n + i], W[uf * n + i],
-                 W[R_RC * n + j], W[R_IRC * n + j], W[R_IC * n + j], W[R_P * n + j], W[uf * n + j], us, pi, Pf);
+  const double rhoL = W[R_RHO * n + i], rcL = W[R_RC * n + i], ircL = W[R_IRC * n + i], icL = W[R_IC * n + i];
+  const double pL = W[R_P * n + i];
+#pragma unroll
+  for (int t = 0; t < DIM; ++t) {
+    const int a = t == DIM - 1 ? 2 : t;
+    const int qa = a == 0 ? qx : (a == 1 ? qy : qz);
+    const int Pa = a == 0 ? G.Px : (a == 1 ? G.Py : G.Pz);
+    if (qa + 1 >= Pa) continue;
+    const long long j = i + astride(G, a);
+    const int k = (a == 2) ? DIM - 1 : a;  // normal velocity component
+    const int uf = ufield(DIM, k);
+    double us, pi, Pf, S = 0.0;
+    int wall = 0;
+    if (a == 2) {
+      wall = (qz == 1 && P.bcz[0] == BC_WALL) || (qz == P.nz + 1 && P.bcz[1] == BC_WALL);
+      Prim<DIM> L, R;
+      L.rho = rhoL; L.rc = rcL; L.irc = ircL; L.ic = icL; L.p = pL; L.u[DIM - 1] = W[uf * n + i];
+      R.rho = W[R_RHO * n + j]; R.rc = W[R_RC * n + j]; R.irc = W[R_IRC * n + j]; R.ic = W[R_IC * n + j];
+      R.p = W[R_P * n + j]; R.u[DIM - 1] = W[uf * n + j];
+      face_vert<LM, DIM>(P, L, R, phi_at(P, qz + 1 - 2) - phi_at(P, qz - 2), wall != 0, us, pi, Pf, S);
+    } else {
+      face_lat<LM>(P, rcL, ircL, icL, pL, W[uf * n + i], W[R_RC * n + j], W[R_IRC * n + j], W[R_IC * n + j],
+                   W[R_P * n + j], W[uf * n + j], us, pi, Pf);
+    }
+    const int f = R_FACE + 4 * a;
+    W[(f + 0) * n + i] = us;
+    W[(f + 1) * n + i] = pi;
+    W[(f + 2) * n + i] = Pf;
+    W[(f + 3) * n + i] = S;
+    W[(R_WALL + a) * n + i] = (double)wall;
   }
-  const int f = R_FACE + 4 * a;
-  W[(f + 0) * n + i] = us;
-  W[(f + 1) * n + i] = pi;
-  W[(f + 2) * n + i] = Pf;
-  W[(f + 3) * n + i] = S;
-  W[(R_WALL + a) * n + i] = (double)wall;
 }
 
 template <int DIM>
@@ -286,16 +293,12 @@ static hipError_t ref_t(const Params& P, const double* Uin, double* Uout, void* 
   const int bs = 256;
   const unsigned nb = (unsigned)((G.npad + bs - 1) / bs);
   hipLaunchKernelGGL(k_ref_prim<DIM>, dim3(nb), dim3(bs), 0, s, P, G, Uin, W);
-  const int axes[3] = {0, 1, 2};
-  for (int t = 0; t < 3; ++t) {
-    const int a = axes[t];
-    if (DIM == 2 && a == 1) continue;
-    if (P.low_mach)
-      hipLaunchKernelGGL((k_ref_face<DIM, true>), dim3(nb), dim3(bs), 0, s, P, G, a, W);
-    else
-      hipLaunchKernelGGL((k_ref_face<DIM, false>), dim3(nb), dim3(bs), 0, s, P, G, a, W);
-  }
+  if (P.low_mach)
+    hipLaunchKernelGGL((k_ref_face<DIM, true>), dim3(nb), dim3(bs), 0, s, P, G, W);
+  else
+    hipLaunchKernelGGL((k_ref_face<DIM, false>), dim3(nb), dim3(bs), 0, s, P, G, W);
   hipLaunchKernelGGL(k_ref_cell<DIM>, dim3(nb), dim3(bs), 0, s, P, G, d_dt, W);
+  const int axes[3] = {0, 1, 2};
   for (int t = 0; t < 3; ++t) {
     const int a = axes[t];
     if (DIM == 2 && a == 1) continue;
@@ -316,13 +319,10 @@ static hipError_t ref_forward_t(const Params& P, const double* Uin, void* wref, 
   const int bs = 256;
   const unsigned nb = (unsigned)((G.npad + bs - 1) / bs);
   hipLaunchKernelGGL(k_ref_prim<DIM>, dim3(nb), dim3(bs), 0, s, P, G, Uin, W);
-  for (int a = 0; a < 3; ++a) {
-    if (DIM == 2 && a == 1) continue;
-    if (P.low_mach)
-      hipLaunchKernelGGL((k_ref_face<DIM, true>), dim3(nb), dim3(bs), 0, s, P, G, a, W);
-    else
-      hipLaunchKernelGGL((k_ref_face<DIM, false>), dim3(nb), dim3(bs), 0, s, P, G, a, W);
-  }
+  if (P.low_mach)
+    hipLaunchKernelGGL((k_ref_face<DIM, true>), dim3(nb), dim3(bs), 0, s, P, G, W);
+  else
+    hipLaunchKernelGGL((k_ref_face<DIM, false>), dim3(nb), dim3(bs), 0, s, P, G, W);
   hipLaunchKernelGGL(k_ref_cell<DIM>, dim3(nb), dim3(bs), 0, s, P, G, d_dt, W);
   return hipGetLastError();
 }
