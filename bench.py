@@ -21,6 +21,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -75,7 +77,6 @@ def valu_view(ms_per_launch, n):
 
 
 def cpu_baseline(cfg, prob, prm, seed, budget_s=12.0):
-    import numpy as np
     import oracle as O
     U = O.init(cfg, prob, prm, seed)
     ncell = 1
@@ -91,9 +92,18 @@ def cpu_baseline(cfg, prob, prm, seed, budget_s=12.0):
         if el >= budget_s or steps >= 50:
             break
     del U
+    model = "unknown CPU"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return dict(value=ncell * steps / el / 1e6, unit="Mcell-updates/s", cores=O.num_threads(), kind="oracle",
                 sample=f"{steps} oracle step(s) of the same 256^3 workload ({ncell} cells each), "
-                       f"{el:.1f} s on {O.num_threads()} host thread(s)")
+                       f"{el:.1f} s on {O.num_threads()} host thread(s) of {os.cpu_count()} ({model})")
 
 
 def timed(torch, fn, stream=None):
@@ -174,6 +184,24 @@ def adjoint_leg(torch, A, W, nsteps=200, slots=16, reps=20, end_to_end=True):
             "forward_run_ms": round(fwd_ms, 2), "gradient_ms": round(grad_ms, 2),
             "ratio_end_to_end": round(grad_ms / fwd_ms, 3),
             "recomputed_forward_steps": int(A.revolve_cost(nsteps, slots)), "gradient_finite": ok}
+
+
+def small_configs_leg(torch, A, W):
+    """Throughput of the two cache-resident single-problem workloads (no
+    roofline claim: their states fit in L2 / MALL): 2D RB 64x32 for 1000
+    steps (launch-bound) and the 2D Gresho vortex 1024^2 for 5000 steps with
+    and without the low-Mach correction."""
+    out = {}
+    for name, (cfg, prob, prm, seed), n in (("rb2d_64x32", W.config1(), 1000),
+                                           ("gresho_1024_theta_on", W.config3(low_mach=1), 5000),
+                                           ("gresho_1024_theta_off", W.config3(low_mach=0), 5000)):
+        S = A.Solver(cfg).init(prob, prm, seed)
+        S.step(20)
+        ms = timed(torch, lambda: S.step(n))
+        cells = int(np.prod(cfg["n"]))
+        out[name] = {"steps": n, "ms": round(ms, 2), "Mcell_per_s": round(cells * n / (ms * 1e-3) / 1e6, 1)}
+        del S
+    return out
 
 
 def batch_leg(torch, A, W, nsteps=500, loop=True):
@@ -318,6 +346,7 @@ def main():
         "final_state": {"t": S.t.item(), "max_u": d["max_u"], "fault": d["fault"]},
     }
     out["spectrum"] = spectrum_leg(torch, S, args.n)
+    out["small_configs"] = small_configs_leg(torch, A, W)
     del S
     torch.cuda.empty_cache()
     if not args.no_adjoint:
