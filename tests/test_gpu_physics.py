@@ -228,3 +228,58 @@ def test_isothermal_column_table1_gpu(N):
         umax = float(torch.max(torch.sqrt(U[1] ** 2 + U[2] ** 2) / U[0]))
         say(f"N {N} theta {'Ma' if lm else '1'}: t {S.t.item():.6f}, max |u| {umax:.2e} (table {table[N][lm]:.1e})")
         assert umax <= 10 * table[N][lm], (N, lm, umax)
+
+
+def shock_tube_l1(A, torch, nx, lm, WL, WR, tend, gamma=1.4):
+    """L1 density error at t_end against the exact Riemann solution of a
+    tube along x (outflow ends; two cells across, periodic)."""
+    from tests import exact_riemann as ER
+    from tests import inputs as I
+    cfg = dict(dim=2, n=[nx, 2], L=[1.0, 2.0 / nx], gamma=gamma, g=0.0, mu=0.0, kappa=0.0, K=1.1, cfl=0.4,
+               low_mach=lm, dt_mode=0, bc=[[W.BC_OUTFLOW, W.BC_OUTFLOW], [W.BC_PERIODIC, W.BC_PERIODIC]],
+               wall_noslip=1, thermal=[0, 0], T_wall=[1.0, 1.0])
+    x = (np.arange(nx) + 0.5) / nx
+    left = np.broadcast_to(x < 0.5, (2, nx))
+    rho = np.where(left, WL[0], WR[0])
+    u = np.where(left, WL[1], WR[1])
+    p = np.where(left, WL[2], WR[2])
+    S = A.Solver(cfg).set_state(I.prim_to_state(cfg, rho, [u, np.zeros_like(u)], p))
+    # most of the run with device-chosen CFL steps (the wave speeds only grow
+    # here, so these end before t_end), the rest one step at a time
+    S.step(max(int(0.9 * tend / S.dt.item()), 0))
+    assert S.t.item() < tend
+    while True:
+        rest = tend - S.t.item()
+        if rest <= 1e-15:
+            break
+        S.compute_dt()
+        S.step_sched(torch.tensor([min(S.dt.item(), rest)], dtype=torch.float64))
+    rc, fc = S.fault()
+    assert rc == 0, fc
+    re, _, _ = ER.profile(WL, WR, gamma, x, 0.5, tend)
+    U = S.numpy()
+    assert np.array_equal(U[0, 0], U[0, 1])  # the two rows stay identical
+    return float(np.mean(np.abs(U[0, 0] - re)))
+
+
+def test_shock_tubes_converge_gpu():
+    """Sec. 4.1 on the GPU at the paper's nx = 100 and up to 6400: Sod's
+    tube and the colliding double shock converge to the exact Riemann
+    solution at first-order-scheme rates, and the low-Mach correction
+    hardly changes Sod's result."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1903_09043_amd as A
+    sod = ((1.0, 0.0, 1.0), (0.125, 0.0, 0.1), 0.2)
+    two = ((1.0, 1.0, 1.0), (1.0, -1.0, 1.0), 0.15)
+    for name, (WL, WR, tend) in (("sod", sod), ("double shock", two)):
+        ns = [100, 400, 1600, 6400]
+        errs = [shock_tube_l1(A, torch, n, 1, WL, WR, tend) for n in ns]
+        orders = [np.log(errs[i] / errs[i + 1]) / np.log(4.0) for i in range(len(ns) - 1)]
+        say(name, "L1 density errors", ["%.3e" % e for e in errs], "orders", np.round(orders, 3))
+        assert all(0.45 <= o <= 1.15 for o in orders), orders
+    e_on = shock_tube_l1(A, torch, 100, 1, *sod)
+    e_off = shock_tube_l1(A, torch, 100, 0, *sod)
+    say("sod nx = 100: theta on", e_on, "off", e_off)
+    assert abs(e_on - e_off) <= 0.25 * e_off and e_on < 0.03
