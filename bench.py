@@ -260,6 +260,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-small", action="store_true", help="skip the cache-resident configs")
     ap.add_argument("--only", choices=["adjoint", "adjoint-step", "batch", "batch-kernel"], default=None,
                     help="run one side leg alone (profiling); prints its JSON object")
     ap.add_argument("--zchunk", type=int, default=0)
@@ -346,7 +347,8 @@ def main():
         "final_state": {"t": S.t.item(), "max_u": d["max_u"], "fault": d["fault"]},
     }
     out["spectrum"] = spectrum_leg(torch, S, args.n)
-    out["small_configs"] = small_configs_leg(torch, A, W)
+    if not args.no_small:
+        out["small_configs"] = small_configs_leg(torch, A, W)
     del S
     torch.cuda.empty_cache()
     if not args.no_adjoint:
