@@ -45,10 +45,11 @@
 // cases (uniform state, contact advection, shear wave, heat flux), exact
 // Riemann solutions, the low-Mach behaviour of Sec. 4.2, geometric
 // invariants, finite differences of the tangent-linear model and the
-// dot-product identity of the dense adjoint.  Parity unpinned: the CFL
-// rate and dt (orc_max_rate, orc_dt: the paper prints no formula, the rule
-// here is a reading) and the diagnostics (orc_diag: definitions without
-// printed values); for these only the GPU-versus-oracle comparison applies.
+// dot-product identity of the dense adjoint, closed forms of the
+// diagnostics (uniform states, the gravitational energy of a uniform column,
+// Nu = 1 for the conductive profile).  Parity unpinned: the CFL rate and dt
+// (orc_max_rate, orc_dt: the paper prints no formula, the rule here is a
+// reading); for these only the GPU-versus-oracle comparison applies.
 //
 // State layout: SoA, var-major: [rho, m_0 .. m_{D-1}, E][cell],
 // cell = i + n0*(j + n1*k), E = rho e + rho |u|^2 / 2 (no gravity).

@@ -649,3 +649,41 @@ def test_spectrum_brute_force_tiny():
     assert len(E) == max(ref) + 1
     for s in range(len(E)):
         assert abs(E[s] - ref.get(s, 0.0)) <= 1e-13 * max(1.0, abs(E[s]))
+
+
+# ------------------------------------------------------- diagnostics -----
+def test_diagnostics_closed_forms():
+    """The diagnostics (Sec. 4 quantities) on states whose sums have closed
+    forms: a uniform moving state (mass rho V, momentum rho u V, kinetic
+    rho |u|^2 V / 2, internal p V / (gamma - 1), every cell's speed and Mach
+    number equal), the gravitational energy of a uniform density in a
+    column (rho g (L_z / 2) V: the cell-centre sum of a linear potential is
+    exact), and the Nusselt numbers of the conductive RB base (1 at both
+    walls, the normalisation of the definition)."""
+    g_ = 5.0 / 3.0
+    cfg = base_cfg(3, [5, 4, 3], [1.0, 2.0, 0.5])
+    rho0, u0, p0 = 1.7, np.array([0.3, -0.4, 1.2]), 2.5
+    shape = (3, 4, 5)
+    U = I.prim_to_state(cfg, np.full(shape, rho0), [np.full(shape, u) for u in u0], np.full(shape, p0))
+    d = O.diag(cfg, U)
+    V = 1.0 * 2.0 * 0.5
+    sp = float(np.sqrt(np.sum(u0 ** 2)))
+    want = dict(mass=rho0 * V, mom0=rho0 * u0[0] * V, mom1=rho0 * u0[1] * V, mom2=rho0 * u0[2] * V,
+                e_kin=0.5 * rho0 * sp ** 2 * V, e_int=p0 / (g_ - 1.0) * V, e_grav=0.0, max_u=sp, mean_u=sp,
+                max_mach=sp / np.sqrt(g_ * p0 / rho0))
+    want["e_total"] = want["e_kin"] + want["e_int"]
+    for k, w in want.items():
+        assert abs(d[k] - w) <= 1e-13 * max(abs(w), 1.0), (k, d[k], w)
+    # gravitational energy of a uniform density between walls
+    cfg = base_cfg(2, [6, 10], [1.5, 3.0], g=0.7, bc=[[0, 0], [1, 1]])
+    U = I.prim_to_state(cfg, np.full((10, 6), rho0), [np.zeros((10, 6))] * 2, np.full((10, 6), p0))
+    d = O.diag(cfg, U)
+    V = 1.5 * 3.0
+    assert abs(d["e_grav"] - rho0 * 0.7 * 1.5 * V) <= 1e-13 * rho0 * 0.7 * 1.5 * V
+    assert abs(d["e_total"] - (p0 / (g_ - 1.0) * V + rho0 * 0.7 * 1.5 * V)) <= 1e-13 * d["e_total"]
+    # conductive RB base: Nu = 1 at both walls
+    cfg, prob, prm, seed = W.rb([8, 6, 12], [1.0, 1.0, 1.0], Ra=1e4)
+    U = O.init(cfg, prob, [prm[0], prm[1], prm[2], 0.0], seed)
+    d = O.diag(cfg, U)
+    assert abs(d["nu_bot"] - 1.0) <= 1e-11 and abs(d["nu_top"] - 1.0) <= 1e-11, (d["nu_bot"], d["nu_top"])
+    assert d["max_u"] == 0.0 and d["e_kin"] == 0.0
