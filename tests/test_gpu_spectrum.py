@@ -62,7 +62,9 @@ def check(g, o):
     (3, [96, 80, 6], 3, "smooth"),
     (3, [300, 2, 3], 1, "white"),        # two-cell side
     (3, [1, 40, 3], 0, "white"),         # one-cell side
+    (3, [1000, 750, 3], 1, "smooth"),    # ragged 16 x 16 matrix tiles in both directions, large
     (2, [257, 9], 4, "white"),           # 2D: a line
+    (2, [2048, 5], 2, "white"),          # 2D: the longest line
     (2, [1, 4], 3, "white"),             # a single cell
 ])
 def test_spectrum_vs_oracle(A, dim, n, kz, kind):
