@@ -65,105 +65,120 @@ __global__ void k_ref_prim(Params P, RefGrid G, const double* __restrict__ U, do
 }
 
 
-// Acoustic faces (a, i | i + e_a) of padded cell i for every active axis
-// (one launch: the cell's own primitives are loaded once).
+// Acoustic face (a, l | l + e_a) from the stored primitives of its two cells
+// (lz: vertical padded index of l).
 template <int DIM, bool LM>
-__global__ void k_ref_face(Params P, RefGrid G, double* __restrict__ W) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= G.npad) return;
-  int qx, qy, qz;
-  decode(G, i, qx, qy, qz);
+__device__ __forceinline__ void ref_face_at(const Params& P, const RefGrid& G, const double* __restrict__ W,
+                                            long long l, int lz, int a, double& us, double& pi, double& Pf,
+                                            double& S, int& wall) {
   const long long n = G.npad;
-  const double rhoL = W[R_RHO * n + i], rcL = W[R_RC * n + i], ircL = W[R_IRC * n + i], icL = W[R_IC * n + i];
-  const double pL = W[R_P * n + i];
-#pragma unroll
-  for (int t = 0; t < DIM; ++t) {
-    const int a = t == DIM - 1 ? 2 : t;
-    const int qa = a == 0 ? qx : (a == 1 ? qy : qz);
-    const int Pa = a == 0 ? G.Px : (a == 1 ? G.Py : G.Pz);
-    if (qa + 1 >= Pa) continue;
-    const long long j = i + astride(G, a);
-    const int k = (a == 2) ? DIM - 1 : a;  // normal velocity component
-    const int uf = ufield(DIM, k);
-    double us, pi, Pf, S = 0.0;
-    int wall = 0;
-    if (a == 2) {
-      wall = (qz == 1 && P.bcz[0] == BC_WALL) || (qz == P.nz + 1 && P.bcz[1] == BC_WALL);
-      Prim<DIM> L, R;
-      L.rho = rhoL; L.rc = rcL; L.irc = ircL; L.ic = icL; L.p = pL; L.u[DIM - 1] = W[uf * n + i];
-      R.rho = W[R_RHO * n + j]; R.rc = W[R_RC * n + j]; R.irc = W[R_IRC * n + j]; R.ic = W[R_IC * n + j];
-      R.p = W[R_P * n + j]; R.u[DIM - 1] = W[uf * n + j];
-      face_vert<LM, DIM>(P, L, R, phi_at(P, qz + 1 - 2) - phi_at(P, qz - 2), wall != 0, us, pi, Pf, S);
-    } else {
-      face_lat<LM>(P, rcL, ircL, icL, pL, W[uf * n + i], W[R_RC * n + j], W[R_IRC * n + j], W[R_IC * n + j],
-                   W[R_P * n + j], W[uf * n + j], us, pi, Pf);
-    }
-    const int f = R_FACE + 4 * a;
-    W[(f + 0) * n + i] = us;
-    W[(f + 1) * n + i] = pi;
-    W[(f + 2) * n + i] = Pf;
-    W[(f + 3) * n + i] = S;
-    W[(R_WALL + a) * n + i] = (double)wall;
+  const long long r = l + astride(G, a);
+  const int k = (a == 2) ? DIM - 1 : a;  // normal velocity component
+  const int uf = ufield(DIM, k);
+  S = 0.0;
+  wall = 0;
+  if (a == 2) {
+    wall = (lz == 1 && P.bcz[0] == BC_WALL) || (lz == P.nz + 1 && P.bcz[1] == BC_WALL);
+    Prim<DIM> L, R;
+    L.rho = W[R_RHO * n + l]; L.rc = W[R_RC * n + l]; L.irc = W[R_IRC * n + l]; L.ic = W[R_IC * n + l];
+    L.p = W[R_P * n + l]; L.u[DIM - 1] = W[uf * n + l];
+    R.rho = W[R_RHO * n + r]; R.rc = W[R_RC * n + r]; R.irc = W[R_IRC * n + r]; R.ic = W[R_IC * n + r];
+    R.p = W[R_P * n + r]; R.u[DIM - 1] = W[uf * n + r];
+    face_vert<LM, DIM>(P, L, R, phi_at(P, lz + 1 - 2) - phi_at(P, lz - 2), wall != 0, us, pi, Pf, S);
+  } else {
+    face_lat<LM>(P, W[R_RC * n + l], W[R_IRC * n + l], W[R_IC * n + l], W[R_P * n + l], W[uf * n + l],
+                 W[R_RC * n + r], W[R_IRC * n + r], W[R_IC * n + r], W[R_P * n + r], W[uf * n + r], us, pi, Pf);
   }
 }
 
-template <int DIM>
-__global__ void k_ref_cell(Params P, RefGrid G, const double* __restrict__ d_dt, double* __restrict__ W) {
+// Padded cell i: its acoustic +faces for every active axis (stored), then,
+// in the cell range [1, P - 1) of every active axis, its acoustic cell
+// values L, S-bar and b~ (Sec. 2.1.2-2.1.3), the -faces formed again from
+// the stored primitives instead of read back (one pass instead of a face
+// pass and a cell pass).
+template <int DIM, bool LM>
+__global__ void k_ref_face_cell(Params P, RefGrid G, const double* __restrict__ d_dt, double* __restrict__ W) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= G.npad) return;
   constexpr int NV = DIM + 2;
   int qx, qy, qz;
   decode(G, i, qx, qy, qz);
-  if (qx < 1 || qx >= G.Px - 1 || qz < 1 || qz >= G.Pz - 1) return;
-  if (DIM == 3 && (qy < 1 || qy >= G.Py - 1)) return;
   const long long n = G.npad;
-  const double dt = *d_dt;
-  const double lam[3] = {dt / P.dx[0], DIM == 3 ? dt / P.dx[1] : 0.0, dt / P.dx[2]};
   // active axes in order: x, (y), z
   const int axes[3] = {0, DIM == 3 ? 1 : 2, 2};
-  double Lc = 1.0;
+  // All faces are formed before anything is stored, so the primitive loads
+  // they share (this cell's) are not repeated behind the stores.
+  double pus[3], ppi[3], pP[3], pS[3];  // own +faces
+  int pw[3];
+#pragma unroll
   for (int t = 0; t < DIM; ++t) {
     const int a = axes[t];
-    const long long m = i - astride(G, a);
-    const int f = R_FACE + 4 * a;
-    Lc = Lc + lam[a] * (W[(f + 0) * n + i] - W[(f + 0) * n + m]);
+    const int qa = a == 0 ? qx : (a == 1 ? qy : qz);
+    const int Pa = a == 0 ? G.Px : (a == 1 ? G.Py : G.Pz);
+    pus[t] = ppi[t] = pP[t] = pS[t] = 0.0;
+    pw[t] = 0;
+    if (qa + 1 < Pa) ref_face_at<DIM, LM>(P, G, W, i, qz, a, pus[t], ppi[t], pP[t], pS[t], pw[t]);
   }
-  const long long mz = i - astride(G, 2);
-  const double sb = 0.5 * (W[(R_FACE + 8 + 3) * n + i] + W[(R_FACE + 8 + 3) * n + mz]);
+  const bool cell = qx >= 1 && qx < G.Px - 1 && qz >= 1 && qz < G.Pz - 1 && (DIM == 2 || (qy >= 1 && qy < G.Py - 1));
+  double mus[3], mpi[3], mP[3], mS[3];  // -faces (a, i - e_a | i)
+  double rho = 0.0, mom[3] = {0.0, 0.0, 0.0}, E0 = 0.0;
+  if (cell) {
+#pragma unroll
+    for (int t = 0; t < DIM; ++t) {
+      const int a = axes[t];
+      int wall;
+      ref_face_at<DIM, LM>(P, G, W, i - astride(G, a), qz - (a == 2), a, mus[t], mpi[t], mP[t], mS[t], wall);
+    }
+    rho = W[R_CONS * n + i];
+    for (int k = 0; k < DIM; ++k) mom[k] = W[(R_CONS + 1 + k) * n + i];
+    E0 = W[(R_CONS + NV - 1) * n + i];
+  }
+#pragma unroll
+  for (int t = 0; t < DIM; ++t) {
+    const int a = axes[t];
+    const int qa = a == 0 ? qx : (a == 1 ? qy : qz);
+    const int Pa = a == 0 ? G.Px : (a == 1 ? G.Py : G.Pz);
+    if (qa + 1 >= Pa) continue;
+    const int f = R_FACE + 4 * a;
+    W[(f + 0) * n + i] = pus[t];
+    W[(f + 1) * n + i] = ppi[t];
+    W[(f + 2) * n + i] = pP[t];
+    W[(f + 3) * n + i] = pS[t];
+    W[(R_WALL + a) * n + i] = (double)pw[t];
+  }
+  if (!cell) return;
+  const double dt = *d_dt;
+  const double lam[3] = {dt / P.dx[0], DIM == 3 ? dt / P.dx[1] : 0.0, dt / P.dx[2]};
+  constexpr int TZ = DIM - 1;  // slot of the vertical axis
+  double Lc = 1.0;
+  for (int t = 0; t < DIM; ++t) Lc = Lc + lam[axes[t]] * (pus[t] - mus[t]);
+  const double sb = 0.5 * (pS[TZ] + mS[TZ]);
   double Am[3];
   for (int t = 0; t < DIM; ++t) {
-    const int a = axes[t];
-    const long long m = i - astride(G, a);
-    const int f = R_FACE + 4 * a;
-    double dpi = W[(f + 1) * n + i] - W[(f + 1) * n + m];
-    if (a == 2) dpi = dpi - sb;
-    Am[t] = lam[a] * dpi;
+    double dpi = ppi[t] - mpi[t];
+    if (axes[t] == 2) dpi = dpi - sb;
+    Am[t] = lam[axes[t]] * dpi;
   }
   double AE = 0.0;
   for (int t = 0; t < DIM; ++t) {
-    const int a = axes[t];
-    const long long m = i - astride(G, a);
-    const int f = R_FACE + 4 * a;
-    const double term = lam[a] * (W[(f + 2) * n + i] - W[(f + 2) * n + m]);
+    const double term = lam[axes[t]] * (pP[t] - mP[t]);
     AE = (t == 0) ? term : AE + term;
   }
-  const double rho = W[R_CONS * n + i];
   double calE;
   if (P.nc) {
     // App. B: energy without the potential, acoustic source (uS)_i
-    const int fz = R_FACE + 8;
-    const double uS = 0.5 * (W[(fz + 0) * n + i] * W[(fz + 3) * n + i] + W[(fz + 0) * n + mz] * W[(fz + 3) * n + mz]);
+    const double uS = 0.5 * (pus[TZ] * pS[TZ] + mus[TZ] * mS[TZ]);
     W[R_US * n + i] = uS;
     AE = AE - lam[2] * uS;
-    calE = W[(R_CONS + NV - 1) * n + i];
+    calE = E0;
   } else {
-    calE = W[(R_CONS + NV - 1) * n + i] + rho * phi_at(P, qz - 2);
+    calE = E0 + rho * phi_at(P, qz - 2);
   }
   const double iL = 1.0 / Lc;
   W[R_L * n + i] = Lc;
   W[R_SB * n + i] = sb;
   W[R_BT * n + i] = rho * iL;
-  for (int k = 0; k < DIM; ++k) W[(R_BT + 1 + k) * n + i] = (W[(R_CONS + 1 + k) * n + i] - Am[k]) * iL;
+  for (int k = 0; k < DIM; ++k) W[(R_BT + 1 + k) * n + i] = (mom[k] - Am[k]) * iL;
   W[(R_BT + NV - 1) * n + i] = (calE - AE) * iL;
 }
 
@@ -294,10 +309,9 @@ static hipError_t ref_t(const Params& P, const double* Uin, double* Uout, void* 
   const unsigned nb = (unsigned)((G.npad + bs - 1) / bs);
   hipLaunchKernelGGL(k_ref_prim<DIM>, dim3(nb), dim3(bs), 0, s, P, G, Uin, W);
   if (P.low_mach)
-    hipLaunchKernelGGL((k_ref_face<DIM, true>), dim3(nb), dim3(bs), 0, s, P, G, W);
+    hipLaunchKernelGGL((k_ref_face_cell<DIM, true>), dim3(nb), dim3(bs), 0, s, P, G, d_dt, W);
   else
-    hipLaunchKernelGGL((k_ref_face<DIM, false>), dim3(nb), dim3(bs), 0, s, P, G, W);
-  hipLaunchKernelGGL(k_ref_cell<DIM>, dim3(nb), dim3(bs), 0, s, P, G, d_dt, W);
+    hipLaunchKernelGGL((k_ref_face_cell<DIM, false>), dim3(nb), dim3(bs), 0, s, P, G, d_dt, W);
   const int axes[3] = {0, 1, 2};
   for (int t = 0; t < 3; ++t) {
     const int a = axes[t];
@@ -320,10 +334,9 @@ static hipError_t ref_forward_t(const Params& P, const double* Uin, void* wref, 
   const unsigned nb = (unsigned)((G.npad + bs - 1) / bs);
   hipLaunchKernelGGL(k_ref_prim<DIM>, dim3(nb), dim3(bs), 0, s, P, G, Uin, W);
   if (P.low_mach)
-    hipLaunchKernelGGL((k_ref_face<DIM, true>), dim3(nb), dim3(bs), 0, s, P, G, W);
+    hipLaunchKernelGGL((k_ref_face_cell<DIM, true>), dim3(nb), dim3(bs), 0, s, P, G, d_dt, W);
   else
-    hipLaunchKernelGGL((k_ref_face<DIM, false>), dim3(nb), dim3(bs), 0, s, P, G, W);
-  hipLaunchKernelGGL(k_ref_cell<DIM>, dim3(nb), dim3(bs), 0, s, P, G, d_dt, W);
+    hipLaunchKernelGGL((k_ref_face_cell<DIM, false>), dim3(nb), dim3(bs), 0, s, P, G, d_dt, W);
   return hipGetLastError();
 }
 
