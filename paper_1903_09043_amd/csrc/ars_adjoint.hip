@@ -129,7 +129,7 @@ __device__ __forceinline__ void adj_flux_face(const Params& P, const RefGrid& G,
   const int f = R_FACE + 4 * a;
   const double us = W[(f + 0) * n + i];
   const double pi = W[(f + 1) * n + i];
-  const bool wall = W[(R_WALL + a) * n + i] != 0.0;
+  const bool wall = ref_wall(P, a, qz);
   const int dn = comp_of<DIM>(a);
   double Gb[NV];
   face_gbar<DIM>(P, G, io, a, lama, qx, qy, qz, Gb);
@@ -304,7 +304,7 @@ __global__ void __launch_bounds__(256) k_adj_flux(Params P, RefGrid G, AdjIO io,
       if (cell) {
         const long long m = i - astride(G, a);
         const int mx = qx - (a == 0), my = qy - (a == 1), mz = qz - (a == 2);
-        if (flux_range<DIM>(G, a, mx, my, mz) && W[(R_WALL + a) * n + m] == 0.0) {
+        if (flux_range<DIM>(G, a, mx, my, mz) && !ref_wall(P, a, mz)) {
           const double us = W[(R_FACE + 4 * a) * n + m];
           if (!(us >= 0.0)) {
             double Gb[NV];
@@ -493,7 +493,7 @@ __device__ __forceinline__ void face_reverse(const Params& P, const RefGrid& G, 
   // forward face values
   const double us = W[(f + 0) * n + i];
   const double pi = W[(f + 1) * n + i];
-  const bool wall = W[(R_WALL + a) * n + i] != 0.0;
+  const bool wall = ref_wall(P, a, qz);
   const int uf = ufield(DIM, dn);
   const double rhoL = W[R_RHO * n + i], rhoR = W[R_RHO * n + j];
   const double uL = W[uf * n + i], uR = W[uf * n + j];

@@ -19,11 +19,10 @@ enum {
   R_RHO = 0, R_R, R_UX, R_UY, R_UZ, R_P, R_C, R_RC, R_T, R_IC, R_IRC,  // primitives (11)
   R_CONS = 11,                                                         // 5 conserved
   R_FACE = 16,                                                         // 3 axes x (us, pi, P, S)
-  R_WALL = 28,                                                         // 3 axes wall flags (as doubles)
-  R_L = 31, R_SB = 32, R_BT = 33,                                      // L, S-bar, 5 b~
-  R_G = 38,                                                            // 3 axes x 5 fluxes
-  R_US = 53,                                                           // (uS)_i (non-conservative energy)
-  R_NFIELD = 54
+  R_L = 28, R_SB = 29, R_BT = 30,                                      // L, S-bar, 5 b~
+  R_G = 35,                                                            // 3 axes x 5 fluxes
+  R_US = 50,                                                           // (uS)_i (non-conservative energy)
+  R_NFIELD = 51
 };
 
 inline RefGrid make_grid(const Params& P) {
@@ -49,6 +48,14 @@ __device__ __forceinline__ long long astride(const RefGrid& G, int a) {
   return a == 0 ? 1 : (a == 1 ? (long long)G.Px : (long long)G.Px * G.Py);
 }
 
+
+// Whether face (a, l | l + e_a) is a wall (lz: vertical padded index of l):
+// only the vertical axis has walls, between the last ghost and the first
+// interior plane at the bottom and between the last interior and the first
+// ghost plane at the top.
+__device__ __forceinline__ bool ref_wall(const Params& P, int a, int lz) {
+  return a == 2 && ((lz == 1 && P.bcz[0] == BC_WALL) || (lz == P.nz + 1 && P.bcz[1] == BC_WALL));
+}
 
 // velocity component k (0..DIM-1) -> primitive field
 __device__ __forceinline__ int ufield(int DIM, int k) { return k == DIM - 1 ? R_UZ : (k == 0 ? R_UX : R_UY); }

@@ -70,21 +70,20 @@ __global__ void k_ref_prim(Params P, RefGrid G, const double* __restrict__ U, do
 template <int DIM, bool LM>
 __device__ __forceinline__ void ref_face_at(const Params& P, const RefGrid& G, const double* __restrict__ W,
                                             long long l, int lz, int a, double& us, double& pi, double& Pf,
-                                            double& S, int& wall) {
+                                            double& S) {
   const long long n = G.npad;
   const long long r = l + astride(G, a);
   const int k = (a == 2) ? DIM - 1 : a;  // normal velocity component
   const int uf = ufield(DIM, k);
   S = 0.0;
-  wall = 0;
   if (a == 2) {
-    wall = (lz == 1 && P.bcz[0] == BC_WALL) || (lz == P.nz + 1 && P.bcz[1] == BC_WALL);
+    const bool wall = ref_wall(P, a, lz);
     Prim<DIM> L, R;
     L.rho = W[R_RHO * n + l]; L.rc = W[R_RC * n + l]; L.irc = W[R_IRC * n + l]; L.ic = W[R_IC * n + l];
     L.p = W[R_P * n + l]; L.u[DIM - 1] = W[uf * n + l];
     R.rho = W[R_RHO * n + r]; R.rc = W[R_RC * n + r]; R.irc = W[R_IRC * n + r]; R.ic = W[R_IC * n + r];
     R.p = W[R_P * n + r]; R.u[DIM - 1] = W[uf * n + r];
-    face_vert<LM, DIM>(P, L, R, phi_at(P, lz + 1 - 2) - phi_at(P, lz - 2), wall != 0, us, pi, Pf, S);
+    face_vert<LM, DIM>(P, L, R, phi_at(P, lz + 1 - 2) - phi_at(P, lz - 2), wall, us, pi, Pf, S);
   } else {
     face_lat<LM>(P, W[R_RC * n + l], W[R_IRC * n + l], W[R_IC * n + l], W[R_P * n + l], W[uf * n + l],
                  W[R_RC * n + r], W[R_IRC * n + r], W[R_IC * n + r], W[R_P * n + r], W[uf * n + r], us, pi, Pf);
@@ -109,15 +108,13 @@ __global__ void k_ref_face_cell(Params P, RefGrid G, const double* __restrict__ 
   // All faces are formed before anything is stored, so the primitive loads
   // they share (this cell's) are not repeated behind the stores.
   double pus[3], ppi[3], pP[3], pS[3];  // own +faces
-  int pw[3];
 #pragma unroll
   for (int t = 0; t < DIM; ++t) {
     const int a = axes[t];
     const int qa = a == 0 ? qx : (a == 1 ? qy : qz);
     const int Pa = a == 0 ? G.Px : (a == 1 ? G.Py : G.Pz);
     pus[t] = ppi[t] = pP[t] = pS[t] = 0.0;
-    pw[t] = 0;
-    if (qa + 1 < Pa) ref_face_at<DIM, LM>(P, G, W, i, qz, a, pus[t], ppi[t], pP[t], pS[t], pw[t]);
+    if (qa + 1 < Pa) ref_face_at<DIM, LM>(P, G, W, i, qz, a, pus[t], ppi[t], pP[t], pS[t]);
   }
   const bool cell = qx >= 1 && qx < G.Px - 1 && qz >= 1 && qz < G.Pz - 1 && (DIM == 2 || (qy >= 1 && qy < G.Py - 1));
   double mus[3], mpi[3], mP[3], mS[3];  // -faces (a, i - e_a | i)
@@ -126,8 +123,7 @@ __global__ void k_ref_face_cell(Params P, RefGrid G, const double* __restrict__ 
 #pragma unroll
     for (int t = 0; t < DIM; ++t) {
       const int a = axes[t];
-      int wall;
-      ref_face_at<DIM, LM>(P, G, W, i - astride(G, a), qz - (a == 2), a, mus[t], mpi[t], mP[t], mS[t], wall);
+      ref_face_at<DIM, LM>(P, G, W, i - astride(G, a), qz - (a == 2), a, mus[t], mpi[t], mP[t], mS[t]);
     }
     rho = W[R_CONS * n + i];
     for (int k = 0; k < DIM; ++k) mom[k] = W[(R_CONS + 1 + k) * n + i];
@@ -144,7 +140,6 @@ __global__ void k_ref_face_cell(Params P, RefGrid G, const double* __restrict__ 
     W[(f + 1) * n + i] = ppi[t];
     W[(f + 2) * n + i] = pP[t];
     W[(f + 3) * n + i] = pS[t];
-    W[(R_WALL + a) * n + i] = (double)pw[t];
   }
   if (!cell) return;
   const double dt = *d_dt;
@@ -205,7 +200,7 @@ __global__ void k_ref_flux(Params P, RefGrid G, int a, double* __restrict__ W) {
   const int f = R_FACE + 4 * a;
   const double us = W[(f + 0) * n + i];
   const double pi = W[(f + 1) * n + i];
-  const bool wall = W[(R_WALL + a) * n + i] != 0.0;
+  const bool wall = ref_wall(P, a, q[2]);
   const int dn = (a == 2) ? DIM - 1 : a;  // normal velocity component index
   double tr[NV];
   if (wall) {
