@@ -167,7 +167,13 @@ __device__ __forceinline__ void march_tile(const Params& P, const double* __rest
     for (int v = 0; v < NV; ++v) Unx[v] = base[v * N];
   }
 
-  for (int p = z0 - 2; p <= z1 + 1; ++p) {
+  // One plane of the march.  In 3D the loop below takes two planes per trip
+  // so that the rotation of the vertical window between them is a renaming
+  // of registers, not a copy (the loop holds barriers, which the compiler's
+  // own unrolling does not take; measured 1 % faster in 3D, 1 % slower for
+  // the 2D row segments, which keep one plane per trip); z0 and z1 are
+  // uniform over the workgroup, so every wave takes the same trips.
+  auto plane = [&](const int p) __attribute__((always_inline)) {
     // ================= step 1: primitives of plane p ========================
     double Uc[NV];
 #pragma unroll
@@ -507,6 +513,16 @@ __device__ __forceinline__ void march_tile(const Params& P, const double* __rest
     for (int i = 0; i < 3 * (DIM - 1); ++i) Fo1[i] = Fn[i];
 #pragma unroll
     for (int i = 0; i < 4; ++i) dX2[i] = dX1[i];
+  };
+  int p = z0 - 2;
+  if constexpr (DIM == 3) {
+    for (; p + 1 <= z1 + 1; p += 2) {
+      plane(p);
+      plane(p + 1);
+    }
+    if (p <= z1 + 1) plane(p);
+  } else {
+    for (; p <= z1 + 1; ++p) plane(p);
   }
 
 }
