@@ -1,7 +1,7 @@
 // ars_ref.hip -- the same explicit step as separate phase kernels on padded
 // arrays (two ghost layers), each phase one thread per cell or face:
-//   ghosts + primitives -> acoustic faces -> acoustic cell values (L, b~)
-//   -> total face fluxes -> update (+ relaxation E = calE - rho Phi).
+//   ghosts + primitives -> acoustic faces and cell values (L, b~), one
+//   pass -> total face fluxes -> update (+ relaxation E = calE - rho Phi).
 // It stores every intermediate in the workspace and exists to check the
 // fused kernels bit for bit (and to expose the intermediates to tests).
 #include "ars_dev.h"
@@ -92,9 +92,9 @@ __device__ __forceinline__ void ref_face_at(const Params& P, const RefGrid& G, c
 
 // Padded cell i: its acoustic +faces for every active axis (stored), then,
 // in the cell range [1, P - 1) of every active axis, its acoustic cell
-// values L, S-bar and b~ (Sec. 2.1.2-2.1.3), the -faces formed again from
-// the stored primitives instead of read back (one pass instead of a face
-// pass and a cell pass).
+// values L, S-bar and b~ (acoustic step, Sec. 2.1.2), with the -faces
+// formed again from the stored primitives instead of read back (one pass
+// instead of a face pass and a cell pass).
 template <int DIM, bool LM>
 __global__ void k_ref_face_cell(Params P, RefGrid G, const double* __restrict__ d_dt, double* __restrict__ W) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
