@@ -774,7 +774,23 @@ __global__ void k_adj_fold(Params P, RefGrid G, AdjIO io, const double* __restri
 __global__ void __launch_bounds__(256) k_adj_params_final(int nb, const double* partial, double* pgrad) {
   __shared__ double sh[2][256];
   double a = 0.0, b = 0.0;
-  for (int k = threadIdx.x; k < nb; k += blockDim.x) {
+  const int bd = blockDim.x;
+  int k = threadIdx.x;
+  // eight trips' loads in flight together, then added in trip order
+  for (; k + 7 * bd < nb; k += 8 * bd) {
+    double x[8], y[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      x[j] = partial[2 * (k + j * bd)];
+      y[j] = partial[2 * (k + j * bd) + 1];
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      a += x[j];
+      b += y[j];
+    }
+  }
+  for (; k < nb; k += bd) {
     a += partial[2 * k];
     b += partial[2 * k + 1];
   }

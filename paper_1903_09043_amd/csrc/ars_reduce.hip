@@ -198,7 +198,16 @@ __global__ void __launch_bounds__(256) k_ke(Params P, double dV, const double* _
 __global__ void k_ke_final(int nb, double dV, const double* partials, double* out) {
   if (threadIdx.x == 0) {
     double a = 0.0;
-    for (int b = 0; b < nb; ++b) a += partials[b];
+    int b = 0;
+    // eight loads in flight together, then added in order
+    for (; b + 8 <= nb; b += 8) {
+      double x[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) x[j] = partials[b + j];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) a += x[j];
+    }
+    for (; b < nb; ++b) a += partials[b];
     *out = a * dV;
   }
 }
@@ -265,7 +274,16 @@ __global__ void __launch_bounds__(256) k_nu(Params P, int side, double C, const 
 __global__ void k_nu_final(int nb, double C, const double* partials, double* out) {
   if (threadIdx.x == 0) {
     double a = 0.0;
-    for (int b = 0; b < nb; ++b) a += partials[b];
+    int b = 0;
+    // eight loads in flight together, then added in order
+    for (; b + 8 <= nb; b += 8) {
+      double x[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) x[j] = partials[b + j];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) a += x[j];
+    }
+    for (; b < nb; ++b) a += partials[b];
     *out = a * C;
   }
 }
