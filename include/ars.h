@@ -88,8 +88,8 @@ enum {
  *             1: the non-conservative energy scheme of App. B (energy
  *             without the potential, source (uS)_i = (u*_{i+1/2} S_{i+1/2} +
  *             u*_{i-1/2} S_{i-1/2})/2 along the gravity axis, no relaxation
- *             step).  With g = 0 the two coincide.  The adjoint step
- *             supports energy_form 0 only.
+ *             step).  With g = 0 the two coincide.  Every entry point,
+ *             the adjoint step included, takes both forms.
  */
 typedef struct ars_config {
   int32_t dim;

@@ -30,8 +30,8 @@ enum {
   A_VL = A_FB + 6,         // 3 axes x (u_0, u_1, u_2, T) viscous adjoint to the left cell
   A_VR = A_VL + 12,        // same, right cell
   A_VT = A_VR + 12,        // 3 axes x (2 tangential axes x 2) tangential-gradient adjoints
-  A_CB = A_VT + 12,        // L, Am_0, Am_1, Am_2, AE, S-bar adjoints per cell
-  A_CONSB = A_CB + 6,      // 5: adjoint of the cell's conserved values through b~
+  A_CB = A_VT + 12,        // L, Am_0, Am_1, Am_2, AE, S-bar, (uS)_i adjoints per cell
+  A_CONSB = A_CB + 7,      // 5: adjoint of the cell's conserved values through b~
   A_PB = A_CONSB + 5,      // rho, u_0, u_1, u_2, p, rho c, 1/(rho c), 1/c, T
   A_NFIELD = A_PB + 9
 };
@@ -85,8 +85,10 @@ __device__ __forceinline__ bool flux_range(const RefGrid& G, int a, int qx, int 
 
 // ------------------------------------------------ update^T (helpers) -----
 // nb_v(c) = b_v(c) [+ rho Phi for E] - sum_a lam_a (G_v(a,c) - G_v(a,c-e_a))
-// [+ lam_z S-bar(c) for m_z];  E' = nb_E - nb_rho Phi.  The adjoint of nb
-// at an interior padded cell, zero elsewhere:
+// [+ lam_z S-bar(c) for m_z];  E' = nb_E - nb_rho Phi.  In the energy form
+// of App. B there is no potential in E and no relaxation, and nb_E carries
+// + lam_z (uS)_c instead.  The adjoint of nb at an interior padded cell,
+// zero elsewhere:
 template <int DIM>
 __device__ __forceinline__ double nbar(const Params& P, const RefGrid& G, const AdjIO& io, int x, int y, int z,
                                        int v) {
@@ -94,7 +96,7 @@ __device__ __forceinline__ double nbar(const Params& P, const RefGrid& G, const 
   if (!interior_cell<DIM>(G, x, y, z)) return 0.0;
   const long long c = (x - 2) + (long long)P.nx * ((DIM == 3 ? y - 2 : 0) + (long long)P.ny * (z - 2));
   const double lr = io.lam1[c], lE = io.lam1[c + (NV - 1) * P.ncell];
-  if (v == 0) return lr - phi_at(P, z - 2) * lE;
+  if (v == 0) return P.nc ? lr : lr - phi_at(P, z - 2) * lE;
   if (v == NV - 1) return lE;
   return io.lam1[c + v * P.ncell];
 }
@@ -259,17 +261,21 @@ __device__ __forceinline__ void adj_cell_values(const Params& P, const RefGrid& 
     Lb += btb[v] * W[(R_BT + v) * n + i];
   }
   Lb = -Lb * iL;
-  // calE = E + rho Phi
-  consb[0] += phi_at(P, qz - 2) * consb[NV - 1];
+  // calE = E + rho Phi (App. B: calE = E)
+  if (!P.nc) consb[0] += phi_at(P, qz - 2) * consb[NV - 1];
   double sbb = -lamz * Ab[DIM];  // A for the vertical momentum: lam_z ((Pi+ - Pi-) - S-bar)
+  // App. B: A_E = ... - lam_z (uS)_i, and the update adds + lam_z (uS)_i to E
+  double uSb = -lamz * Ab[NV - 1];
   if (interior_cell<DIM>(G, qx, qy, qz)) {
     const long long c = (qx - 2) + (long long)P.nx * ((DIM == 3 ? qy - 2 : 0) + (long long)P.ny * (qz - 2));
     sbb += lamz * io.lam1[c + DIM * P.ncell];  // + lam_z S-bar in the update of m_z
+    uSb += lamz * io.lam1[c + (NV - 1) * P.ncell];
   }
   W[(A_CB + 0) * n + i] = Lb;
   for (int k = 0; k < 3; ++k) W[(A_CB + 1 + k) * n + i] = k < DIM ? Ab[1 + k] : 0.0;
   W[(A_CB + 4) * n + i] = Ab[NV - 1];
   W[(A_CB + 5) * n + i] = sbb;
+  if (P.nc) W[(A_CB + 6) * n + i] = uSb;
   for (int v = 0; v < 5; ++v) W[(A_CONSB + v) * n + i] = v < NV ? consb[v] : 0.0;
 }
 
@@ -477,11 +483,13 @@ __device__ __forceinline__ void face_reverse(const Params& P, const RefGrid& G, 
   double usb = W[(A_FB + 2 * a + 0) * n + i];
   double pib = W[(A_FB + 2 * a + 1) * n + i];
   double Pb = 0.0, Sb = 0.0;
+  double uSb = 0.0;  // App. B: (uS) adjoints of the two cells, (uS)_c = (u* S)_up / 2 + (u* S)_down / 2
   if (cell_range<DIM>(G, qx, qy, qz)) {
     usb += lama * W[(A_CB + 0) * n + i];
     pib += lama * W[(A_CB + 1 + dn) * n + i];
     Pb += lama * W[(A_CB + 4) * n + i];
     if (a == 2) Sb += 0.5 * W[(A_CB + 5) * n + i];
+    if (a == 2 && P.nc) uSb += 0.5 * W[(A_CB + 6) * n + i];
   }
   const int rx = qx + (a == 0), ry = qy + (a == 1), rz = qz + (a == 2);
   if (cell_range<DIM>(G, rx, ry, rz)) {
@@ -489,10 +497,15 @@ __device__ __forceinline__ void face_reverse(const Params& P, const RefGrid& G, 
     pib -= lama * W[(A_CB + 1 + dn) * n + j];
     Pb -= lama * W[(A_CB + 4) * n + j];
     if (a == 2) Sb += 0.5 * W[(A_CB + 5) * n + j];
+    if (a == 2 && P.nc) uSb += 0.5 * W[(A_CB + 6) * n + j];
   }
   // forward face values
   const double us = W[(f + 0) * n + i];
   const double pi = W[(f + 1) * n + i];
+  if (a == 2 && P.nc) {
+    usb += uSb * W[(f + 3) * n + i];
+    Sb += uSb * us;
+  }
   const bool wall = ref_wall(P, a, qz);
   const int uf = ufield(DIM, dn);
   const double rhoL = W[R_RHO * n + i], rhoR = W[R_RHO * n + j];

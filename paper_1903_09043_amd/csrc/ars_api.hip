@@ -430,7 +430,6 @@ int ars_step_adjoint(ars_ctx* ctx, const double* d_state_n, const double* d_lam_
                      const double* d_dt, double* d_param_grad, void* d_work_adj, void* stream) {
   if (!ctx || !d_state_n || !d_lam_np1 || !d_lam_n || !d_dt || !d_work_adj || d_lam_n == d_lam_np1)
     return ARS_EINVAL;
-  if (ctx->P.nc) return ARS_EUNSUPPORTED;  // the reverse of the App. B energy form is not built
   return check(ars::launch_step_adjoint(ctx->P, d_state_n, d_lam_np1, d_lam_n, d_dt, d_param_grad, d_work_adj,
                                         (hipStream_t)stream));
 }

@@ -139,17 +139,22 @@ def test_batch_host_side():
     assert L.ars_batch_create(0, None, C.byref(C.c_void_p())) == A.EINVAL
 
 
-def test_adjoint_rejects_nonconservative_energy():
-    """The reverse of the App. B energy form is not built: the adjoint entry
-    point says so before touching any device buffer."""
+def test_energy_form_validation():
+    """Both energy forms (the relaxed total energy and App. B) are valid
+    configurations for every entry point, the adjoint included; any other
+    value is rejected by the library and by the oracle, and the adjoint
+    entry point checks its pointers before touching any device buffer."""
     import ctypes as C
     cfg, prob, prm, seed = W.rb([8, 6], [2.0, 1.0])
-    ctx = A.Context(dict(cfg, energy_form=1))
-    dummy = C.c_void_p(1)
-    rc = A.lib().ars_step_adjoint(ctx.h, dummy, dummy, C.c_void_p(2), dummy, None, dummy, None)
-    assert rc == A.EUNSUPPORTED
+    assert A.validate(dict(cfg, energy_form=1)) == A.OK
     assert A.validate(dict(cfg, energy_form=2)) == A.EINVAL
     assert O.validate(dict(cfg, energy_form=2)) != 0
+    ctx = A.Context(dict(cfg, energy_form=1))
+    dummy = C.c_void_p(1)
+    rc = A.lib().ars_step_adjoint(ctx.h, dummy, dummy, dummy, dummy, None, dummy, None)
+    assert rc == A.EINVAL  # d_lam_n aliases d_lam_np1
+    rc = A.lib().ars_step_adjoint(ctx.h, dummy, None, C.c_void_p(2), dummy, None, dummy, None)
+    assert rc == A.EINVAL
 
 
 def test_spectrum_host_side():

@@ -63,10 +63,20 @@ def gpu_adjoint(A, cfg, U, lam, dt):
 # the *_bulk cases are wide enough in every direction to hold cells two or
 # more cells from every boundary, whose reverse is folded in place
 CASES = ["rb2d_walls", "rb2d_thetaoff_freeslip", "rb3d_walls", "periodic2d_inviscid", "outflow2d_viscous",
-         "periodic3d_viscous", "rb3d_walls_bulk", "periodic3d_bulk"]
+         "periodic3d_viscous", "rb3d_walls_bulk", "periodic3d_bulk",
+         # the non-conservative energy form of App. B (gravity on: with g = 0
+         # it coincides with the other form)
+         "nc_rb2d_walls", "nc_rb2d_thetaoff_freeslip", "nc_rb3d_walls", "nc_rb3d_walls_bulk", "nc_rb2d_outflow_x"]
 
 
 def make_case(name):
+    if name.startswith("nc_"):
+        cfg, U = make_case(name[3:])
+        return dict(cfg, energy_form=1), U
+    if name == "rb2d_outflow_x":
+        # gravity needs walls along its axis; the lateral sides are outflow
+        cfg, U = make_case("rb2d_walls")
+        return dict(cfg, bc=[[2, 2], cfg["bc"][1]]), U
     if name == "rb2d_walls":
         cfg, prob, prm, seed = W.rb([10, 8], [2.0, 1.0], Ra=2e3, seed=3, amp=1e-3)
         return cfg, perturbed(cfg, prob, prm, seed)
@@ -117,14 +127,17 @@ def test_adjoint_vs_oracle_dense(A, name):
         assert abs(pg[1] - gk) <= 1e-10 * max(abs(gk), scale)
 
 
-def test_adjoint_vs_central_differences(A):
+@pytest.mark.parametrize("energy_form", [0, 1])
+def test_adjoint_vs_central_differences(A, energy_form):
     """3D RB 24x20x16 with walls: the adjoint against central differences of
     the GPU forward step at frozen dt, 10 seeded directions and the two
-    transport coefficients.  The step is piecewise smooth (upwind switch,
-    |u*|, min/max): h = 1e-8 of each field's scale and a 10 % velocity field
-    keep faces away from those switches while rounding stays ~1e-8."""
+    transport coefficients, in both energy forms.  The step is piecewise
+    smooth (upwind switch, |u*|, min/max): h = 1e-8 of each field's scale
+    and a 10 % velocity field keep faces away from those switches while
+    rounding stays ~1e-8."""
     import torch
     cfg, prob, prm, seed = W.rb([24, 20, 16], [1.0, 1.0, 1.0], Ra=1e5, seed=9, amp=1e-3)
+    cfg = dict(cfg, energy_form=energy_form)
     U = perturbed(cfg, prob, prm, seed, amp_u=1e-1)
     dt = O.dt(cfg, U)
     rng = np.random.default_rng(12)
