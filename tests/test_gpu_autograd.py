@@ -29,9 +29,10 @@ def T():
     return torch
 
 
-def make_problem(T, slots, nsteps=12, n=(16, 12, 10), Ra=2e4, dt_sched=None):
+def make_problem(T, slots, nsteps=12, n=(16, 12, 10), Ra=2e4, dt_sched=None, energy_form=0):
     from paper_1903_09043_amd.adjoint import RBProblem
     cfg, prob, prm, seed = W.rb(list(n), [1.0, 1.0, 1.0], Ra=Ra, seed=0, amp=0.0)
+    cfg = dict(cfg, energy_form=energy_form)
     rng = np.random.default_rng(5)
     u0 = 0.1 * rng.standard_normal((3,) + tuple(reversed(n)))
     return RBProblem(cfg, prob, prm, nsteps, slots, u0=u0, dt_sched=dt_sched), cfg
@@ -53,9 +54,11 @@ def test_checkpointed_gradient_equals_store_all(T):
     assert J0 == J1 and np.array_equal(g0, g1) and m0 == m1 and k0 == k1
 
 
-def test_gradient_vs_central_differences(T):
+@pytest.mark.parametrize("energy_form", [0, 1])
+def test_gradient_vs_central_differences(T, energy_form):
+    """Both energy forms (the relaxed total energy and App. B)."""
     from paper_1903_09043_amd.adjoint import rb_kinetic_energy, rb_kinetic_energy_ra_pr
-    pb, cfg = make_problem(T, 4)
+    pb, cfg = make_problem(T, 4, energy_form=energy_form)
     rng = np.random.default_rng(2)
     dT0 = (1e-2 * T.tensor(rng.standard_normal(pb.rho.shape))).cuda()
     dT = dT0.clone().requires_grad_()
@@ -70,7 +73,7 @@ def test_gradient_vs_central_differences(T):
     S.compute_dt()
     log = T.zeros(pb.nsteps, dtype=T.float64, device="cuda")
     S.step(pb.nsteps, dt_log=log)
-    pf, _ = make_problem(T, 4, dt_sched=log)
+    pf, _ = make_problem(T, 4, dt_sched=log, energy_form=energy_form)
 
     def Jf(x, m=cfg["mu"], k=cfg["kappa"]):
         with T.no_grad():
