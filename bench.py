@@ -140,7 +140,7 @@ def adjoint_leg(torch, A, W, nsteps=200, slots=16, reps=20, end_to_end=True):
     end (full gradient: forward, recomputation by the revolve plan and the
     adjoint sweep, over the forward run alone)."""
     from paper_1903_09043_amd.adjoint import RBProblem, rb_kinetic_energy
-    cfg, prob, prm, seed = W.config5()
+    cfg, prob, prm, seed = W.rb3d_ra1e5()
     pb = RBProblem(cfg, prob, prm, nsteps, slots)
     g = torch.Generator(device="cpu").manual_seed(1)
     dT = (1e-4 * (2 * torch.rand(pb.rho.shape, generator=g, dtype=torch.float64) - 1)).cuda()
@@ -192,9 +192,9 @@ def small_configs_leg(torch, A, W):
     steps (launch-bound) and the 2D Gresho vortex 1024^2 for 5000 steps with
     and without the low-Mach correction."""
     out = {}
-    for name, (cfg, prob, prm, seed), n in (("rb2d_64x32", W.config1(), 1000),
-                                           ("gresho_1024_theta_on", W.config3(low_mach=1), 5000),
-                                           ("gresho_1024_theta_off", W.config3(low_mach=0), 5000)):
+    for name, (cfg, prob, prm, seed), n in (("rb2d_64x32", W.rb2d_64x32(), 1000),
+                                           ("gresho_1024_theta_on", W.gresho_1024(low_mach=1), 5000),
+                                           ("gresho_1024_theta_off", W.gresho_1024(low_mach=0), 5000)):
         S = A.Solver(cfg).init(prob, prm, seed)
         S.step(20)
         ms = timed(torch, lambda: S.step(n))
@@ -209,7 +209,7 @@ def batch_leg(torch, A, W, nsteps=500, loop=True):
     for all instances and steps) over the loop of ars_step(500) per
     instance on the same stream; every instance's final state must be
     bitwise equal between the two."""
-    setups = W.config4()
+    setups = W.rb2d_batch()
     cfgs = [c for c, *_ in setups]
     B = A.Batch(cfgs)
     for k, (cfg, prob, prm, seed) in enumerate(setups):
@@ -287,7 +287,7 @@ def main():
     if args.only == "batch-kernel":
         print(json.dumps({"batch": batch_leg(torch, A, W, loop=False)}), flush=True)
         return
-    cfg, prob, prm, seed = W.config2(n=args.n)
+    cfg, prob, prm, seed = W.rb3d_ra1e6(n=args.n)
     ncell = args.n ** 3
     if args.mode == "copy":
         # plain copy of one state (5 FP64 fields): reads and writes 40 B per cell

@@ -59,22 +59,22 @@ def gresho(n=1024, Ma=1e-3, low_mach=1, cfl=0.4, K=1.1):
     return cfg, PROB_GRESHO, [Ma], 0
 
 
-def config1(low_mach=1):
+def rb2d_64x32(low_mach=1):
     """2D RB 64x32 on [0,2]x[0,1], Ra = 1e4, Pr = 1, 1000 steps."""
     return rb([64, 32], [2.0, 1.0], Ra=1e4, low_mach=low_mach)
 
 
-def config2(n=256):
+def rb3d_ra1e6(n=256):
     """3D RB 256^3 on the unit cube, Ra = 1e6, Pr = 1, 2000 steps, forward only."""
     return rb([n, n, n], [1.0, 1.0, 1.0], Ra=1e6)
 
 
-def config3(low_mach=1, n=1024):
+def gresho_1024(low_mach=1, n=1024):
     """2D Gresho vortex 1024^2, Ma = 1e-3, 5000 steps, theta on and off."""
     return gresho(n=n, Ma=1e-3, low_mach=low_mach)
 
 
-def config5(n=128):
+def rb3d_ra1e5(n=128):
     """3D RB 128^3, Ra = 1e5, Pr = 1: adjoint over 200 steps, 16 snapshots."""
     return rb([n, n, n], [1.0, 1.0, 1.0], Ra=1e5)
 
@@ -117,7 +117,7 @@ def splitmix64(state):
     return state, z ^ (z >> 31)
 
 
-def config4(n_inst=512, seed=1000):
+def rb2d_batch(n_inst=512, seed=1000):
     """Batched 2D RB: sizes uniform over {64x32, 128x64, 256x128} on
     [0,2]x[0,1], Ra log-uniform in [5e2, 5e3], Pr = 1, per-instance seeds
     SplitMix64(seed + k).  Returns a list of (cfg, problem, params, seed)."""

@@ -36,7 +36,7 @@ def test_strerror():
 
 
 CFGS = [
-    W.config1()[0],
+    W.rb2d_64x32()[0],
     W.gresho(n=64)[0],
     W.rb([12, 10, 8], [1.0, 1.0, 1.0], Ra=1e5)[0],
 ]
@@ -64,7 +64,7 @@ def test_create_rejects_1d():
 @pytest.mark.parametrize("which", ["rb2d", "rb3d", "gresho", "gresho_odd", "sod", "iso", "uniform", "rb2d_seed"])
 def test_host_init_bitwise_equals_oracle(which):
     if which == "rb2d":
-        cfg, prob, prm, seed = W.config1()
+        cfg, prob, prm, seed = W.rb2d_64x32()
     elif which == "rb2d_seed":
         cfg, prob, prm, seed = W.rb([30, 17], [2.0, 1.0], Ra=3e3, seed=987654321, amp=1e-3)
     elif which == "rb3d":
@@ -95,7 +95,7 @@ def test_workloads_transport_coefficients():
     assert abs(mu - 2.7386e-3) < 1e-7 and abs(k - 6.8465e-3) < 1e-7
     mu2, k2 = W.ra_pr_to_mu_kappa(4e4, 1.0)
     assert abs(mu2 * k2 * 4 - mu * k) < 1e-15
-    insts = W.config4()
+    insts = W.rb2d_batch()
     assert len(insts) == 512
     sizes = {tuple(c["n"]) for c, *_ in insts}
     assert sizes == {(64, 32), (128, 64), (256, 128)}
@@ -169,7 +169,7 @@ def test_spectrum_host_side():
         ref = len(O.spectrum(dict(base, n=n), np.ones((5, n[2], n[1], n[0])), 0))
         assert ref == shells
         assert L.ars_workspace_bytes_spectrum(ctx.h) == 12 * n[0] * n[1] * 8
-    ctx2 = A.Context(W.config1()[0])
+    ctx2 = A.Context(W.rb2d_64x32()[0])
     assert L.ars_spectrum_len(ctx2.h) == 33
     assert L.ars_workspace_bytes_spectrum(ctx2.h) == 8 * 64 * 8
     d = C.c_void_p(1)

@@ -118,14 +118,14 @@ def test_gradient_vs_central_differences(T, energy_form):
     agree(fd_ra, Ra.grad.item(), (1.0, 0.1), "Ra")
 
 
-def test_config5_gradient_vs_finite_differences(T):
+def test_rb3d_128_gradient_vs_finite_differences(T):
     """The adjoint workload at full size: 3D RB 128^3, Ra = 1e5, Pr = 1, 200
     steps from the base state heated by a seeded 1e-4 perturbation, 16
     revolve slots.  dJ/d(dT0) against central differences along 10 seeded
     unit-RMS directions, and dJ/dRa through the (Ra, Pr) map, all at the
     frozen time-step schedule of the forward run."""
     from paper_1903_09043_amd.adjoint import RBProblem, rb_kinetic_energy, rb_kinetic_energy_ra_pr
-    cfg, prob, prm, seed = W.config5()
+    cfg, prob, prm, seed = W.rb3d_ra1e5()
     pb = RBProblem(cfg, prob, prm, 200, 16)
     g0 = T.Generator(device="cpu").manual_seed(0)
     dT0 = (1e-4 * (2 * T.rand(pb.rho.shape, generator=g0, dtype=T.float64) - 1)).cuda()
@@ -134,7 +134,7 @@ def test_config5_gradient_vs_finite_differences(T):
     ka = T.tensor(cfg["kappa"], dtype=T.float64, requires_grad=True)
     J = rb_kinetic_energy(x, mu, ka, pb)
     J.backward()
-    say("config5 J", J.item(), "dJ/dmu", mu.grad.item(), "dJ/dkappa", ka.grad.item())
+    say("rb3d 128^3 J", J.item(), "dJ/dmu", mu.grad.item(), "dJ/dkappa", ka.grad.item())
     g = x.grad
     S = pb.solver(cfg["mu"], cfg["kappa"])
     S.U.copy_(pb.initial_state(dT0))

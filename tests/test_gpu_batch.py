@@ -155,7 +155,7 @@ def test_batch_instance_vs_oracle(A):
     """One batched instance (2D RB 64x32, Ra = 1e4, theta on) against the
     oracle directly, 300 steps, beside two other instances."""
     import torch
-    setups = [W.config1(), W.rb([128, 64], [2.0, 1.0], Ra=2e3, seed=9), W.rb([30, 20], [2.0, 1.0], Ra=800, seed=4)]
+    setups = [W.rb2d_64x32(), W.rb([128, 64], [2.0, 1.0], Ra=2e3, seed=9), W.rb([30, 20], [2.0, 1.0], Ra=800, seed=4)]
     B = init_batch(A, setups)
     B.step(300)
     torch.cuda.synchronize()
@@ -171,10 +171,10 @@ def test_batch_workload_sizes_500_steps(A):
     """The first 24 instances of the 512-instance batched workload (sizes
     from {64x32, 128x64, 256x128}, Ra log-uniform in [5e2, 5e3]), 500 steps,
     against the single-problem path."""
-    setups = W.config4()[:24]
+    setups = W.rb2d_batch()[:24]
     B = init_batch(A, setups)
     B.step(500)
-    check_against_single(A, B, setups, 500, "config4[:24]")
+    check_against_single(A, B, setups, 500, "rb2d_batch[:24]")
 
 
 def test_autotune_and_cache(A, tmp_path):

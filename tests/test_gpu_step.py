@@ -60,7 +60,7 @@ def gpu_run(A, cfg, U0, nsteps, zchunk=None):
 
 def test_init_and_dt_bitwise(A):
     import torch
-    for make in (W.config1, lambda: W.rb([20, 12, 10], [1.0, 1.0, 1.0], Ra=1e5, seed=3),
+    for make in (W.rb2d_64x32, lambda: W.rb([20, 12, 10], [1.0, 1.0, 1.0], Ra=1e5, seed=3),
                  lambda: W.gresho(n=64)):
         cfg, prob, prm, seed = make()
         say("init/dt", cfg["n"])
@@ -72,18 +72,18 @@ def test_init_and_dt_bitwise(A):
         assert S.dt.item() == O.dt(cfg, Uo)
 
 
-def test_config1_1000_steps(A):
+def test_rb2d_64x32_1000_steps(A):
     """2D RB 64x32, Ra = 1e4, theta on, 1000 steps: the workload of the
     parity requirement."""
-    cfg, prob, prm, seed = W.config1()
+    cfg, prob, prm, seed = W.rb2d_64x32()
     Uo0 = O.init(cfg, prob, prm, seed)
-    say("config1 gpu")
+    say("rb2d 64x32 gpu")
     U, log, t, rc, fc = gpu_run(A, cfg, Uo0, 1000)
     assert rc == 0
-    say("config1 oracle")
+    say("rb2d 64x32 oracle")
     r = O.run(cfg, Uo0, 1000)
     err = close(U, r["U"])
-    say("config1 max rel err", err, "bitwise", bitwise(U, r["U"]))
+    say("rb2d 64x32 max rel err", err, "bitwise", bitwise(U, r["U"]))
     assert err <= 1e-12
     np.testing.assert_allclose(log, r["dt_log"], rtol=1e-13)
     assert abs(t - r["t"]) <= 1e-12 * r["t"]
@@ -200,7 +200,7 @@ def test_result_independent_of_zchunk(A):
 def test_diagnostics_match_oracle(A):
     """Diagnostics of the oracle's state after 50 steps, on the GPU and in
     the oracle."""
-    cfg, prob, prm, seed = W.config1()
+    cfg, prob, prm, seed = W.rb2d_64x32()
     r = O.run(cfg, O.init(cfg, prob, prm, seed), 50)
     assert r["status"] == 0
     S = A.Solver(cfg).set_state(r["U"])
@@ -234,7 +234,7 @@ def test_full_size_256cubed_one_step(A):
     step (its CFL step chosen on the device) equals one oracle step on the
     whole grid."""
     import torch
-    cfg, prob, prm, seed = W.config2()
+    cfg, prob, prm, seed = W.rb3d_ra1e6()
     say("256^3 oracle init + 2 steps (threads=%d)" % O.num_threads())
     r = O.run(cfg, O.init(cfg, prob, prm, seed), 2)
     assert r["status"] == 0
@@ -257,7 +257,7 @@ def test_full_size_256cubed_10_steps_from_init(A):
     """3D RB 256^3 from the initial state: 10 GPU steps (CFL time steps
     chosen on the device) against 10 oracle steps on the whole grid."""
     import torch
-    cfg, prob, prm, seed = W.config2()
+    cfg, prob, prm, seed = W.rb3d_ra1e6()
     S = A.Solver(cfg).init(prob, prm, seed)
     log = torch.zeros(10, dtype=torch.float64, device="cuda")
     S.step(10, dt_log=log)
@@ -279,7 +279,7 @@ def test_gresho_1024_full_size(A, lm):
     length of the workload) keep the kinetic energy, more of it with the
     low-Mach correction than without (Sec. 4.2)."""
     import torch
-    cfg, prob, prm, seed = W.config3(low_mach=lm)
+    cfg, prob, prm, seed = W.gresho_1024(low_mach=lm)
     S = A.Solver(cfg).init(prob, prm, seed)
     ke0 = S.diagnostics()["e_kin"]
     S.step(10)
@@ -305,7 +305,7 @@ def test_checkpoint_resume(A, tmp_path):
     and of t, a load into a fresh solver and 500 more steps, bit for bit
     (dt of the resumed run comes from the loaded state)."""
     import torch
-    cfg, prob, prm, seed = W.config1()
+    cfg, prob, prm, seed = W.rb2d_64x32()
     S = A.Solver(cfg).init(prob, prm, seed)
     S.step(1000)
     torch.cuda.synchronize()

@@ -133,7 +133,7 @@ def test_rb_base_state_at_rest_with_dissipation():
     at rest to round-off for 1000 steps (Sec. 2.1.7: any discrete
     equilibrium is preserved; conduction of the linear profile is balanced
     to round-off because the profile is linear)."""
-    cfg, prob, prm, seed = W.config1()
+    cfg, prob, prm, seed = W.rb2d_64x32()
     prm = prm[:3] + [0.0]
     U = O.init(cfg, prob, prm, seed)
     r = O.run(cfg, U, 1000)
@@ -528,7 +528,7 @@ def test_nonconservative_rb_base_at_rest(dim):
     face, [Pi*]_i = S-bar_i and (uS)_i = 0, so the RB base (viscous,
     conducting, fixed-T walls) stays at rest to round-off."""
     if dim == 2:
-        cfg, prob, prm, seed = W.config1()
+        cfg, prob, prm, seed = W.rb2d_64x32()
     else:
         cfg, prob, prm, seed = W.rb([6, 5, 12], [1.0, 1.0, 1.0], Ra=1e5)
     cfg = dict(cfg, energy_form=1)
