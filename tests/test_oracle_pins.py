@@ -447,10 +447,12 @@ def test_validate_rejects_bad_configs():
 
 
 # ------------------------------------------------------ tangent linear -----
-def test_tlm_matches_central_differences():
+@pytest.mark.parametrize("energy_form", [0, 1])
+def test_tlm_matches_central_differences(energy_form):
     """The dual-number tangent-linear step agrees with central finite
-    differences of the plain step (frozen dt)."""
+    differences of the plain step (frozen dt), in both energy forms."""
     cfg, prob, prm, seed = W.rb([10, 8], [2.0, 1.0], Ra=2e3, amp=1e-3, seed=3)
+    cfg = dict(cfg, energy_form=energy_form)
     U = O.init(cfg, prob, prm, seed)
     rng = np.random.default_rng(8)
     U[1] = 1e-3 * rng.standard_normal(U[0].shape)
@@ -479,10 +481,12 @@ def test_tlm_matches_central_differences():
         assert np.max(np.abs(fd - tl)) <= 1e-6 * np.max(np.abs(tl)), which
 
 
-def test_dense_adjoint_dot_product():
+@pytest.mark.parametrize("energy_form", [0, 1])
+def test_dense_adjoint_dot_product(energy_form):
     """<J dU, lam> = <dU, J^T lam> with J^T lam from the brute-force reverse
-    product (exact identity up to summation order)."""
+    product (exact identity up to summation order), in both energy forms."""
     cfg, prob, prm, seed = W.rb([5, 4], [2.0, 1.0], Ra=2e3, amp=1e-3, seed=3)
+    cfg = dict(cfg, energy_form=energy_form)
     U = O.init(cfg, prob, prm, seed)
     dt = O.dt(cfg, U)
     rng = np.random.default_rng(1)
