@@ -180,3 +180,20 @@ def test_spectrum_host_side():
     assert L.ars_spectrum(ctx.h, d, 0, d, None, None) == A.EINVAL
     big = A.Context(dict(base, n=[2049, 4, 2]))
     assert L.ars_spectrum(big.h, d, 0, d, d, None) == A.EUNSUPPORTED
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    """Without the built HIP library the binding raises instead of falling
+    back to anything else, and a solver refuses to run without a GPU."""
+    import paper_1903_09043_amd as P
+    monkeypatch.setattr(P, "_lib", None)
+    monkeypatch.setattr(P, "LIB_PATH", str(tmp_path / "libars.so"))
+    with pytest.raises(ImportError):
+        P.lib()
+    with pytest.raises(ImportError):
+        P.validate(W.rb2d_64x32()[0])
+    monkeypatch.undo()
+    import torch
+    if not torch.cuda.is_available():
+        with pytest.raises(RuntimeError):
+            P.Solver(W.rb2d_64x32()[0])
