@@ -200,6 +200,19 @@ def small_configs_leg(torch, A, W):
         ms = timed(torch, lambda: S.step(n))
         cells = int(np.prod(cfg["n"]))
         out[name] = {"steps": n, "ms": round(ms, 2), "Mcell_per_s": round(cells * n / (ms * 1e-3) / 1e6, 1)}
+        if name == "rb2d_64x32":
+            # the same 1000 steps as ten replays of a captured 100-step graph
+            g = S.capture(100)
+            g.replay()
+            torch.cuda.synchronize()
+
+            def replay10():
+                for _ in range(n // 100):
+                    g.replay()
+            msg = timed(torch, replay10)
+            out[name + "_graph"] = {"steps": n, "ms": round(msg, 2),
+                                    "Mcell_per_s": round(cells * n / (msg * 1e-3) / 1e6, 1)}
+            del g
         del S
     return out
 

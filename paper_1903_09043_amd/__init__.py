@@ -300,6 +300,17 @@ class Solver:
                "ars_step")
         return self
 
+    def capture(self, n: int):
+        """Record n steps (one ars_step call: control preparation, n fused
+        launches, the copy back after an odd count, the dt finish) into a
+        graph on a capture stream.  Nothing runs while recording; every
+        graph.replay() then advances this solver's state, t and dt by n
+        steps exactly as step(n) would, with one launch from the host."""
+        g = self.torch.cuda.CUDAGraph()
+        with self.torch.cuda.graph(g):
+            self.step(n)
+        return g
+
     def step_sched(self, dt_sched):
         dt_sched = dt_sched.to(self.device, self.torch.float64).contiguous()
         _check(lib().ars_step_sched(self.ctx.h, _ptr(self.U), _ptr(self.tmp), _ptr(self.work), dt_sched.numel(),

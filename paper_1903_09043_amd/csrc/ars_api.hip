@@ -162,6 +162,10 @@ int ars_create(const ars_config* cfg, ars_ctx** out) {
     const long long tiles = (c->P.nx + 59) / 60;
     const long long want = 2048;
     long long nch = std::max(1ll, std::min((long long)c->P.nz / 4 + 1, want / std::max(1ll, tiles)));
+    // a problem with fewer (segment, plane) pairs than CUs leaves the chip
+    // idle whatever the split: one plane per workgroup gives the shortest
+    // march (its latency is the step time)
+    if (tiles * c->P.nz <= 256) nch = c->P.nz;
     zc = (int)((c->P.nz + nch - 1) / nch);
   }
   (void)cols;

@@ -410,3 +410,26 @@ def test_nonconservative_energy_vs_oracle(A, name):
     S.step_ref(torch.tensor(log, dtype=torch.float64))
     torch.cuda.synchronize()
     assert bitwise(S.numpy(), U)
+
+
+def test_step_graph_replay(A):
+    """Steps recorded in a graph and replayed equal eager steps bit for bit:
+    three replays of a 10-step graph (2D, even count) and of a 7-step graph
+    (3D, odd count: the copy back is a node of the graph), each replay
+    compared with an eager solver after eager work and synchronisation."""
+    import torch
+    for make, n in ((W.rb2d_64x32, 10), (lambda: W.rb([20, 12, 10], [1.0, 1.0, 1.0], Ra=1e5, seed=3), 7)):
+        cfg, prob, prm, seed = make()
+        G = A.Solver(cfg).init(prob, prm, seed)
+        E = A.Solver(cfg).init(prob, prm, seed)
+        torch.cuda.synchronize()
+        say("graph capture", cfg["n"], n)
+        g = G.capture(n)
+        for r in range(3):
+            g.replay()
+            torch.cuda.synchronize()
+            E.step(n)
+            torch.cuda.synchronize()
+            say("graph replay", cfg["n"], n, r)
+            assert bitwise(G.numpy(), E.numpy())
+            assert G.t.item() == E.t.item() and G.dt.item() == E.dt.item()
