@@ -143,7 +143,10 @@ size_t ars_workspace_bytes(const ars_ctx* ctx);
 int ars_workspace_init(ars_ctx* ctx, void* d_work, void* stream);
 
 /* Launch shape of the fused step: number of planes one workgroup marches
- * through along the vertical axis (results do not depend on it). */
+ * through along the vertical axis (results do not depend on it).  The
+ * default, set by ars_create from the grid: in 3D about 1536 (tile, chunk)
+ * shares; in 2D a share of about sqrt(segments x planes) / 13 planes (one
+ * plane for small grids, whose step time is the latency of one march). */
 int ars_set_zchunk(ars_ctx* ctx, int zchunk);
 int ars_get_zchunk(const ars_ctx* ctx);
 
