@@ -197,3 +197,15 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     if not torch.cuda.is_available():
         with pytest.raises(RuntimeError):
             P.Solver(W.rb2d_64x32()[0])
+
+
+def test_default_vertical_chunk():
+    """The default launch shape chosen at ars_create (results never depend
+    on it): in 2D a share of about sqrt(segments x planes) / 13 planes, one
+    plane for small grids; the 3D bench grid keeps its 37-plane chunks."""
+    def zc(cfg):
+        return A.Context(cfg).zchunk()
+    assert zc(W.rb2d_64x32()[0]) == 1
+    assert zc(W.rb([256, 128], [2.0, 1.0])[0]) == 2
+    assert zc(W.gresho_1024()[0]) == 10
+    assert zc(W.rb3d_ra1e6()[0]) == 37
