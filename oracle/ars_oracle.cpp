@@ -13,7 +13,8 @@
 //   O1 ghosts          -- Sec. 4.3 (hydrostatic extrapolation + reflexive
 //                         velocity), eq. (well_balanced_formula) solved for
 //                         the ghost density; Sec. 4.5.3 fixed-T walls.
-//   O2 primitives      -- ideal gas of Sec. 4, p = (gamma-1) rho e, c^2 = gamma p / rho.
+//   O2 primitives      -- ideal gas of Sec. 4, p = (gamma-1) rho e, T = p / rho
+//                         (R = 1, as p = rho T of Sec. 4.3), c^2 = gamma p / rho.
 //   O3 time step       -- CFL reduction ("time step kernel", Sec. 3.2); the
 //                         paper gives no formula, the reading is additive
 //                         hyperbolic + diffusive rate.
@@ -162,7 +163,6 @@ struct Grid {
 template <class S>
 struct Prim {
   S rho, r, u[3], p, c, rc, T;
-  S ic, irc;  // 1/c and 1/(rho c): the face solver divides by max(c) and by 2 K max(rho c)
 };
 
 // O2: conservative -> primitive for one cell.
@@ -183,11 +183,9 @@ Prim<S> cons_to_prim(const orc_config& c, const Grid& G, const S* U, long cell) 
   for (int k = 1; k < G.D; ++k) kin = kin + m[k] * q.u[k];
   kin = S(0.5) * kin;
   q.p = S(G.gm1) * (E - kin);
-  q.c = sqrt_((S(c.gamma) * q.p) * q.r);
+  q.T = q.p / q.rho;              // p = rho T (R = 1)
+  q.c = sqrt_(S(c.gamma) * q.T);  // c^2 = gamma p / rho = gamma T
   q.rc = q.rho * q.c;
-  q.T = q.p * q.r;
-  q.ic = S(1.0) / q.c;
-  q.irc = q.r * q.ic;
   return q;
 }
 
@@ -258,10 +256,8 @@ void build_padded(const orc_config& c, const Grid& G, const S* U, State<S>& st) 
           bool flip = c.wall_noslip ? true : (k == z);
           gq.u[k] = (k < G.D && flip) ? -in.u[k] : in.u[k];
         }
-        gq.c = sqrt_((S(c.gamma) * gq.p) * gq.r);
+        gq.c = sqrt_(S(c.gamma) * Tg);
         gq.rc = gq.rho * gq.c;
-        gq.ic = S(1.0) / gq.c;
-        gq.irc = gq.r * gq.ic;
         st.prim[dst] = gq;
         // conserved values of wall ghosts are never used (zero wall flux)
       }
@@ -272,10 +268,13 @@ struct Face {
   S a, S_, ustar, theta, pistar, P;
 };
 
-// O4: acoustic solver at the face between L and R = L + e_d.
-// a = K max(rho c); u* divides by 2a and Ma by max(c): both are written as
-// products with the smaller of the two cells' reciprocals,
-//   1/(2a) = (1/(2K)) min(1/(rho c)_L, 1/(rho c)_R),  1/max(c) = min(1/c_L, 1/c_R).
+// O4: acoustic solver at the face between L and R = L + e_d (Sec. 2.1.2):
+//   a  = K max(rho_L c_L, rho_R c_R)            (sub-characteristic condition)
+//   S  = -(rho_L + rho_R)/2 (Phi_R - Phi_L)     (interface gravity source)
+//   u* = (u_L + u_R)/2 - (Pi_R - Pi_L - S) / (2a)
+//   Ma = |u*| / max(c_L, c_R),  theta = min(Ma, 1)   (eq. low_mach_correction)
+//   Pi* = (Pi_L + Pi_R)/2 - (a theta / 2)(u_R - u_L)
+// with the quotients written as the paper writes them.
 template <class S>
 Face<S> acoustic_face(const orc_config& c, const Grid& G, const Prim<S>& L, const Prim<S>& R,
                       int d, double phiL, double phiR, bool wall) {
@@ -285,13 +284,12 @@ Face<S> acoustic_face(const orc_config& c, const Grid& G, const Prim<S>& L, cons
     f.S_ = (S(-0.5) * (L.rho + R.rho)) * S(phiR - phiL);
   else
     f.S_ = S(0.0);
-  const double hK = 0.5 / c.K;
   if (wall)
     f.ustar = S(0.0);
   else
-    f.ustar = S(0.5) * (L.u[d] + R.u[d]) - ((R.p - L.p) - f.S_) * (S(hK) * smin(L.irc, R.irc));
+    f.ustar = S(0.5) * (L.u[d] + R.u[d]) - ((R.p - L.p) - f.S_) / (S(2.0) * f.a);
   if (c.low_mach) {
-    S Ma = sabs(f.ustar) * smin(L.ic, R.ic);
+    S Ma = sabs(f.ustar) / smax(L.c, R.c);
     f.theta = smin(Ma, S(1.0));
   } else {
     f.theta = S(1.0);
@@ -395,11 +393,11 @@ int step_impl(const orc_config& c, const S* U, S* Uout, double dt, S mu, S kappa
         } else {
           calE = st.cons[(1 + D) * NP + p] + rho * S(st.phi[q[z]]);
         }
-        S iL = S(1.0) / Lc;
+        // L~ b~ = b - A^b  (the acoustic update of Sec. 2.1.2)
         A.L[p] = Lc;
-        A.bt[0 * NP + p] = rho * iL;
-        for (int k = 0; k < D; ++k) A.bt[(1 + k) * NP + p] = (st.cons[(1 + k) * NP + p] - Am[k]) * iL;
-        A.bt[(1 + D) * NP + p] = (calE - AE) * iL;
+        A.bt[0 * NP + p] = rho / Lc;
+        for (int k = 0; k < D; ++k) A.bt[(1 + k) * NP + p] = (st.cons[(1 + k) * NP + p] - Am[k]) / Lc;
+        A.bt[(1 + D) * NP + p] = (calE - AE) / Lc;
       }
 
   // O6 + O7: total face flux G for faces between padded q and q+1,
@@ -763,11 +761,9 @@ void orc_face(const orc_config* c, int d, double rhoL, double uL, double pL, dou
   Grid G(*c);
   Prim<double> L{}, R{};
   L.rho = rhoL; L.r = 1.0 / rhoL; L.u[d] = uL; L.p = pL;
-  L.c = std::sqrt((c->gamma * pL) * L.r); L.rc = rhoL * L.c; L.T = pL * L.r;
-  L.ic = 1.0 / L.c; L.irc = L.r * L.ic;
+  L.T = pL / rhoL; L.c = std::sqrt(c->gamma * L.T); L.rc = rhoL * L.c;
   R.rho = rhoR; R.r = 1.0 / rhoR; R.u[d] = uR; R.p = pR;
-  R.c = std::sqrt((c->gamma * pR) * R.r); R.rc = rhoR * R.c; R.T = pR * R.r;
-  R.ic = 1.0 / R.c; R.irc = R.r * R.ic;
+  R.T = pR / rhoR; R.c = std::sqrt(c->gamma * R.T); R.rc = rhoR * R.c;
   Face<double> f = acoustic_face(*c, G, L, R, d, phiL, phiR, wall != 0);
   out[0] = f.a; out[1] = f.S_; out[2] = f.ustar; out[3] = f.theta; out[4] = f.pistar; out[5] = f.P;
 }
