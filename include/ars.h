@@ -161,6 +161,29 @@ int ars_init_state(ars_ctx* ctx, int problem, const double* params, int n_params
 int ars_init_state_host(const ars_ctx* ctx, int problem, const double* params, int n_params, uint64_t seed,
                         double* h_state);
 
+/* Rayleigh-Benard initial state with a caller temperature perturbation
+ * (Sec. 4.5 set-up; the base is the discrete hydrostatic equilibrium of eq.
+ * well_balanced_formula with the linear temperature T_k of level k, as for
+ * ARS_PROB_RB):  rho = rho_k,  m = rho u0,
+ *   E = rho (T_k + dT) / (gamma - 1) + |m|^2 / (2 rho)
+ * params: T_bottom, T_top, rho of the bottom cell (<= 0: T_bottom), as for
+ * ARS_PROB_RB (a fourth value is ignored).  d_dT: device field of
+ * ars_state_len()/(dim+2) doubles in the layout of one state variable.
+ * d_u0 (nullable): device initial velocity, dim fields in the momentum
+ * layout; NULL is rest, and then the state equals ars_init_state with the
+ * SplitMix64 perturbation replaced by dT.  Builds the base on the host,
+ * copies it to d_state and adds dT on the device (synchronous on
+ * `stream`).  EINVAL for a configuration without walls on the vertical
+ * axis or a NULL pointer. */
+int ars_init_rb_dT(ars_ctx* ctx, const double* params, int n_params, const double* d_dT, const double* d_u0,
+                   double* d_state, void* stream);
+/* Transpose of the map dT -> U^0 of ars_init_rb_dT at the state it built:
+ *   d_g_dT = (dU^0/d dT)^T d_lam = d_lam[E] rho / (gamma - 1)  (overwritten)
+ * d_state0: that initial state (its density); d_lam: adjoint of U^0 in the
+ * state layout.  Asynchronous. */
+int ars_init_rb_dT_adjoint(ars_ctx* ctx, const double* d_state0, const double* d_lam, double* d_g_dT,
+                           void* stream);
+
 /* dt = cfl / max_i lambda_i of d_state (time-step kernel, Sec. 3.2),
  * written to the device double *d_dt.  Also prepares the workspace for
  * ars_step.  Asynchronous. */

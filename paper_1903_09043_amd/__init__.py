@@ -74,6 +74,8 @@ SIGNATURES = [
     ("ars_get_zchunk", C.c_int, [_VP]),
     ("ars_init_state", C.c_int, [_VP, C.c_int, _DP, C.c_int, C.c_uint64, _VP, _VP]),
     ("ars_init_state_host", C.c_int, [_VP, C.c_int, _DP, C.c_int, C.c_uint64, _DP]),
+    ("ars_init_rb_dT", C.c_int, [_VP, _DP, C.c_int, _VP, _VP, _VP, _VP]),
+    ("ars_init_rb_dT_adjoint", C.c_int, [_VP, _VP, _VP, _VP, _VP]),
     ("ars_compute_dt", C.c_int, [_VP, _VP, _VP, _VP, _VP]),
     ("ars_step", C.c_int, [_VP, _VP, _VP, _VP, C.c_int, _VP, _VP, _VP, _VP]),
     ("ars_step_sched", C.c_int, [_VP, _VP, _VP, _VP, C.c_int, _VP, _VP, _VP]),
@@ -283,6 +285,30 @@ class Solver:
         self.t.zero_()
         self.compute_dt()
         return self
+
+    def init_rb_dT(self, params, dT, u0=None):
+        """Rayleigh-Benard base (params as for PROB_RB) with the device
+        temperature perturbation field dT (and optional initial velocity u0,
+        shape (dim, ...)); t = 0 and dt from the new state."""
+        p = np.asarray(list(params)[:3] + [0.0], dtype=np.float64)
+        n = self.ctx.state_len // (self.cfg["dim"] + 2)
+        _check(lib().ars_init_rb_dT(self.ctx.h, p.ctypes.data_as(_DP), min(len(params), 3), self._arg(dT, n, "dT"),
+                                    self._arg(u0, self.cfg["dim"] * n, "u0"), _ptr(self.U), self.stream),
+               "ars_init_rb_dT")
+        self.t.zero_()
+        self.compute_dt()
+        return self
+
+    def init_rb_dT_adjoint(self, U0, lam, out=None):
+        """(dU0/d dT)^T lam at the state U0 built by init_rb_dT."""
+        t = self.torch
+        n = self.ctx.state_len // (self.cfg["dim"] + 2)
+        if out is None:
+            out = t.empty(U0.shape[1:], dtype=t.float64, device=self.device)
+        L = self.ctx.state_len
+        _check(lib().ars_init_rb_dT_adjoint(self.ctx.h, self._arg(U0, L, "U0"), self._arg(lam, L, "lam"),
+                                            self._arg(out, n, "out"), self.stream), "ars_init_rb_dT_adjoint")
+        return out
 
     def set_state(self, U):
         self.U.copy_(self.torch.as_tensor(U, dtype=self.torch.float64).to(self.device))

@@ -42,20 +42,19 @@ class RBProblem:
         self.nsteps = int(nsteps)
         self.slots = max(1, min(int(slots), self.nsteps))
         self.device = torch.device(device)
-        base = Solver(self.cfg, device=device).init(prob, list(params[:3]) + [0.0], seed)
-        U = base.U.clone()
-        D = self.cfg["dim"]
-        self.gm1 = self.cfg.get("gamma", 5.0 / 3.0) - 1.0
-        self.rho = U[0].clone()
-        # base temperature p / rho of the hydrostatic state (no flow)
-        self.T = U[D + 1] * self.gm1 / self.rho
+        self.params = list(params[:3])
+        self._base = Solver(self.cfg, device=device)
+        self.u0 = None
         if u0 is not None:
-            u0 = torch.as_tensor(u0, dtype=torch.float64, device=self.device)
-            for k in range(D):
-                U[1 + k] = self.rho * u0[k]
-        self.U_base = U
+            self.u0 = torch.as_tensor(u0, dtype=torch.float64, device=self.device).contiguous()
+        self.shape = tuple(self._base.U.shape[1:])
         self.dt_sched = dt_sched
         self._solvers = {}
+
+    @property
+    def rho(self):
+        """Density field of the base state (any perturbation keeps it)."""
+        return self.initial_state(torch.zeros(self.shape, dtype=torch.float64, device=self.device))[0]
 
     def solver(self, mu, kappa):
         key = (float(mu), float(kappa))
@@ -64,29 +63,26 @@ class RBProblem:
             self._solvers[key] = Solver(dict(self.cfg, mu=key[0], kappa=key[1]), device=self.device)
         return self._solvers[key]
 
+    def build(self, S, dT0):
+        """U^0 into S.U (ars_init_rb_dT: base density and flow, p = rho (T + dT0))."""
+        S.init_rb_dT(self.params, dT0.detach().to(self.device, torch.float64).contiguous(), self.u0)
+        return S.U
+
     def initial_state(self, dT0):
-        """U^0: base density and flow, p = rho (T + dT0)."""
-        D = self.cfg["dim"]
-        U = self.U_base.clone()
-        kin = torch.zeros_like(self.rho)
-        for k in range(D):
-            kin = kin + U[1 + k] * U[1 + k]
-        U[D + 1] = (self.rho * (self.T + dT0)) / self.gm1 + 0.5 * kin / self.rho
-        return U
+        """A copy of U^0 for the perturbation dT0."""
+        return self.build(self._base, dT0).clone()
 
 
 class _RBObjective(torch.autograd.Function):
     @staticmethod
     def forward(ctx, dT0, mu, kappa, problem):
         S = problem.solver(mu.item(), kappa.item())
-        U0 = problem.initial_state(dT0.detach().to(problem.device, torch.float64))
-        S.U.copy_(U0)
+        U0 = problem.build(S, dT0).clone()
         n = problem.nsteps
         if problem.dt_sched is not None:
             log = problem.dt_sched.to(problem.device, torch.float64).contiguous()
             S.step_sched(log)
         else:
-            S.compute_dt()
             log = torch.zeros(n, dtype=torch.float64, device=problem.device)
             S.step(n, dt_log=log)
         grad = torch.empty_like(S.U)
@@ -122,8 +118,7 @@ class _RBObjective(torch.autograd.Function):
             elif op == OP_ADJOINT:
                 S.step_adjoint(S.U, lam, log[step:step + 1], lam_n=lam_next, param_grad=pg)
                 lam, lam_next = lam_next, lam
-        D = problem.cfg["dim"]
-        g_dT = lam[D + 1] * problem.rho / problem.gm1
+        g_dT = S.init_rb_dT_adjoint(U0, lam)
         return g_dT, pg[0].reshape(()), pg[1].reshape(()), None
 
 

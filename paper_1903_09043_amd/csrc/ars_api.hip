@@ -94,6 +94,45 @@ ars::Control* ctl_of(void* w) { return (ars::Control*)w; }
 
 }  // namespace
 
+// U^0 of a Rayleigh-Benard base with a temperature perturbation field: the
+// density of d_state (the uploaded base) is kept, the energy is rebuilt from
+// the level's linear temperature (the formula of the host initial state).
+template <int DIM>
+static __global__ void k_rb_dT(ars::Params P, double Tb, double Tt, double Lz, const double* __restrict__ dT,
+                        const double* __restrict__ u0, double* __restrict__ U) {
+  const long long N = P.ncell;
+  const long long plane = (long long)P.nx * P.ny;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (long long)gridDim.x * blockDim.x) {
+    const int k = (int)(i / plane);
+    const double zk = ((double)k + 0.5) * P.dx[2];
+    const double T = Tb + (Tt - Tb) * (zk / Lz);
+    const double rho = U[i];
+    double E = (rho * (T + dT[i])) / P.gm1;
+    if (u0) {
+      double mm = 0.0;
+#pragma unroll
+      for (int a = 0; a < DIM; ++a) {
+        const double m = rho * u0[a * N + i];
+        U[(1 + a) * N + i] = m;
+        mm = mm + m * m;
+      }
+      E = E + (0.5 * mm) / rho;
+    }
+    U[(DIM + 1) * N + i] = E;
+  }
+}
+
+static __global__ void k_rb_dT_adjoint(long long N, int DIMv, double gm1, const double* __restrict__ U0,
+                                const double* __restrict__ lam, double* __restrict__ g) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (long long)gridDim.x * blockDim.x)
+    g[i] = (lam[(DIMv + 1) * N + i] * U0[i]) / gm1;
+}
+
+static unsigned flat_blocks(long long n) {
+  const long long b = (n + 255) / 256;
+  return (unsigned)std::max(1ll, std::min(b, 8192ll));
+}
+
 ars::Params ars::params_of(const ars_config* c) { return derive(c); }
 
 extern "C" {
@@ -343,6 +382,35 @@ int ars_init_state(ars_ctx* ctx, int problem, const double* prm, int nprm, uint6
   if (hipMemcpyAsync(d_state, h.data(), ctx->len * sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess)
     return ARS_EDEVICE;
   return check(hipStreamSynchronize(s));
+}
+
+int ars_init_rb_dT(ars_ctx* ctx, const double* prm, int nprm, const double* d_dT, const double* d_u0,
+                   double* d_state, void* stream) {
+  if (!ctx || !d_dT || !d_state || nprm < 0 || (nprm > 0 && !prm)) return ARS_EINVAL;
+  const ars_config& c = ctx->cfg;
+  const int z = c.dim - 1;
+  if (c.bc[z][0] != ARS_BC_WALL || c.bc[z][1] != ARS_BC_WALL) return ARS_EINVAL;
+  double base[4] = {1.0, 0.5, -1.0, 0.0};
+  for (int i = 0; i < nprm && i < 3; ++i) base[i] = prm[i];
+  int rc = ars_init_state(ctx, ARS_PROB_RB, base, 4, 0, d_state, stream);
+  if (rc != ARS_OK) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  const unsigned nb = flat_blocks(ctx->P.ncell);
+  if (c.dim == 3)
+    hipLaunchKernelGGL(k_rb_dT<3>, dim3(nb), dim3(256), 0, s, ctx->P, base[0], base[1], c.L[z], d_dT, d_u0, d_state);
+  else
+    hipLaunchKernelGGL(k_rb_dT<2>, dim3(nb), dim3(256), 0, s, ctx->P, base[0], base[1], c.L[z], d_dT, d_u0, d_state);
+  if (hipGetLastError() != hipSuccess) return ARS_EDEVICE;
+  return check(hipStreamSynchronize(s));
+}
+
+int ars_init_rb_dT_adjoint(ars_ctx* ctx, const double* d_state0, const double* d_lam, double* d_g_dT,
+                           void* stream) {
+  if (!ctx || !d_state0 || !d_lam || !d_g_dT) return ARS_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_rb_dT_adjoint, dim3(flat_blocks(ctx->P.ncell)), dim3(256), 0, s, ctx->P.ncell,
+                     ctx->cfg.dim, ctx->P.gm1, d_state0, d_lam, d_g_dT);
+  return check(hipGetLastError());
 }
 
 // ---------------------------------------------------------------- stepping

@@ -1,9 +1,11 @@
 """Batched persistent launch (ars_batch_*) on an MI355X.
 
 Every instance of a batch must equal the single-problem path (ars_step on
-that instance alone, itself bitwise equal to the oracle) bit for bit: same
-states, same accumulated time, same next dt.  One instance is also checked
-against the oracle directly.  Also: independence of the tiling (row
+that instance alone, the same kernel code) bit for bit: same states, same
+accumulated time, same next dt.  One instance is also checked against the
+oracle directly, to the 1e-12 scale-aware tolerance of tests/parity.py
+(the oracle evaluates the paper's quotients, the kernels reciprocal
+products).  Also: independence of the tiling (row
 segments per workgroup, vertical chunks), continuation (a + b steps equal
 a then b), graph capture and replay, and the largest instance size of the
 batched workload.
@@ -15,6 +17,7 @@ import pytest
 
 import oracle as O
 from paper_1903_09043_amd import workloads as W
+from tests import parity as P
 
 pytestmark = pytest.mark.gpu
 
@@ -163,8 +166,13 @@ def test_batch_instance_vs_oracle(A):
     Uo = O.init(cfg, prob, prm, seed)
     r = O.run(cfg, Uo, 300)
     assert r["status"] == 0
-    assert np.array_equal(B.view(0).cpu().numpy(), r["U"])
-    assert B.read()[0][0] == r["t"]
+    U = B.view(0).cpu().numpy()
+    o = r["U"]
+    err = P.rel_err(cfg, U, o)
+    say("batch instance vs oracle, 300 steps: parity %.3e (each variable on its own max: %.3e)"
+        % (err, P.strict_err(U, o)), "bitwise", np.array_equal(U, o))
+    assert err <= 1e-12
+    assert abs(B.read()[0][0] - r["t"]) <= 1e-13 * r["t"]
 
 
 def test_batch_workload_sizes_500_steps(A):
