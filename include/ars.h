@@ -49,7 +49,8 @@ typedef enum {
   ARS_ENOMEM = -2,        /* host allocation failed */
   ARS_EDEVICE = -3,       /* HIP runtime / launch error */
   ARS_ENONPHYS = -4,      /* latched numerical fault (see ars_diag.fault_cell) */
-  ARS_EUNSUPPORTED = -5   /* valid configuration this build does not run */
+  ARS_EUNSUPPORTED = -5,  /* valid configuration this build does not run */
+  ARS_ESCRATCH = -6       /* state larger than the library's static scratch (ars_step_noalloc) */
 } ars_status;
 
 enum { ARS_BC_PERIODIC = 0, ARS_BC_WALL = 1, ARS_BC_OUTFLOW = 2 };
@@ -199,6 +200,24 @@ int ars_compute_dt(ars_ctx* ctx, const double* d_state, void* d_work, double* d_
  * Asynchronous; numerical faults are latched. */
 int ars_step(ars_ctx* ctx, double* d_state, double* d_tmp, void* d_work, int n_steps, double* d_t, double* d_dt,
              double* d_dt_log, void* stream);
+
+/* For callers that cannot allocate device memory (code under graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): ars_step
+ * without d_tmp and d_work.  Its scratch -- the 256-byte control block
+ * (CFL rate slots, fault latch) and the ping-pong state -- is a static
+ * device array of the library, one per GPU, held until the process ends:
+ * 256 + 8 * ARS_NOALLOC_MAX_STATE bytes (about 1 MiB).  The call allocates
+ * nothing.  Returns ARS_ESCRATCH, launching nothing, when
+ * ars_state_len(ctx) > ARS_NOALLOC_MAX_STATE (e.g. 2D grids up to 256 x 128
+ * fit; larger problems use ars_step).  Results, *d_t, *d_dt and d_dt_log are
+ * those of ars_step bit for bit; a numerical fault during the call leaves
+ * *d_dt = NaN (no fault cell: ars_step reports it).  Every call on one GPU
+ * shares that GPU's scratch and resets it at its start: calls that overlap
+ * on one GPU (other streams, other threads) race and must be serialised by
+ * the caller.  Asynchronous. */
+#define ARS_NOALLOC_MAX_STATE 131072
+int ars_step_noalloc(ars_ctx* ctx, double* d_state, int n_steps, double* d_t, double* d_dt, double* d_dt_log,
+                     void* stream);
 
 /* Same with a prescribed per-step dt schedule d_dt_sched[n_steps] (device);
  * used with a frozen schedule by the adjoint and finite-difference checks.

@@ -16,7 +16,8 @@ from . import workloads  # noqa: F401  (problem set-ups)
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libars.so")
 
-OK, EINVAL, ENOMEM, EDEVICE, ENONPHYS, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+OK, EINVAL, ENOMEM, EDEVICE, ENONPHYS, EUNSUPPORTED, ESCRATCH = 0, -1, -2, -3, -4, -5, -6
+NOALLOC_MAX_STATE = 131072  # ARS_NOALLOC_MAX_STATE of include/ars.h
 BC_PERIODIC, BC_WALL, BC_OUTFLOW = 0, 1, 2
 
 
@@ -78,6 +79,7 @@ SIGNATURES = [
     ("ars_init_rb_dT_adjoint", C.c_int, [_VP, _VP, _VP, _VP, _VP]),
     ("ars_compute_dt", C.c_int, [_VP, _VP, _VP, _VP, _VP]),
     ("ars_step", C.c_int, [_VP, _VP, _VP, _VP, C.c_int, _VP, _VP, _VP, _VP]),
+    ("ars_step_noalloc", C.c_int, [_VP, _VP, C.c_int, _VP, _VP, _VP, _VP]),
     ("ars_step_sched", C.c_int, [_VP, _VP, _VP, _VP, C.c_int, _VP, _VP, _VP]),
     ("ars_workspace_bytes_ref", C.c_size_t, [_VP]),
     ("ars_step_ref", C.c_int, [_VP, _VP, _VP, _VP, _VP, C.c_int, _VP, _VP]),

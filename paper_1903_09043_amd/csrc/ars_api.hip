@@ -145,6 +145,7 @@ const char* ars_strerror(int s) {
     case ARS_EDEVICE: return "HIP runtime or launch error";
     case ARS_ENONPHYS: return "non-physical state (rho, p or L not positive, or non-finite)";
     case ARS_EUNSUPPORTED: return "configuration not supported by this build";
+    case ARS_ESCRATCH: return "state larger than the allocation-free scratch (ARS_NOALLOC_MAX_STATE doubles)";
     default: return "unknown status";
   }
 }
