@@ -76,8 +76,23 @@ def valu_view(ms_per_launch, n):
             "issue_bound_frac": round(v["balanced_issue_bound_ms"] / ms_per_launch, 3)}
 
 
-def cpu_baseline(cfg, prob, prm, seed, budget_s=12.0):
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown CPU"
+
+
+def cpu_worker(budget_s):
+    """Oracle steps of the 256^3 workload in this process (OpenMP threads as
+    OMP_NUM_THREADS sets them); prints one JSON line."""
     import oracle as O
+    from paper_1903_09043_amd import workloads as W
+    cfg, prob, prm, seed = W.rb3d_ra1e6()
     U = O.init(cfg, prob, prm, seed)
     ncell = 1
     for a in range(cfg["dim"]):
@@ -91,19 +106,33 @@ def cpu_baseline(cfg, prob, prm, seed, budget_s=12.0):
         el = time.perf_counter() - t0
         if el >= budget_s or steps >= 50:
             break
-    del U
-    model = "unknown CPU"
-    try:
-        with open("/proc/cpuinfo") as f:
-            for line in f:
-                if line.startswith("model name"):
-                    model = line.split(":", 1)[1].strip()
-                    break
-    except OSError:
-        pass
-    return dict(value=ncell * steps / el / 1e6, unit="Mcell-updates/s", cores=O.num_threads(), kind="oracle",
-                sample=f"{steps} oracle step(s) of the same 256^3 workload ({ncell} cells each), "
-                       f"{el:.1f} s on {O.num_threads()} host thread(s) of {os.cpu_count()} ({model})")
+    print(json.dumps(dict(steps=steps, seconds=el, ncell=ncell, threads=O.num_threads())), flush=True)
+
+
+def cpu_baseline(budget_s=12.0):
+    """The oracle on the host cores, serial and with every core: each run in
+    a child process (OpenMP fixes its thread count at start-up)."""
+    import subprocess
+    runs = {}
+    for tag, env_threads in (("serial", "1"), ("threaded", None)):
+        env = dict(os.environ)
+        if env_threads:
+            env["OMP_NUM_THREADS"] = env_threads
+        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-worker", str(budget_s)], env=env,
+                           capture_output=True, text=True, check=True)
+        runs[tag] = json.loads(r.stdout.strip().splitlines()[-1])
+    model = cpu_model()
+
+    def fig(d):
+        return dict(value=d["ncell"] * d["steps"] / d["seconds"] / 1e6, cores=d["threads"],
+                    sample=f"{d['steps']} oracle step(s) of the same 256^3 workload ({d['ncell']} cells each), "
+                           f"{d['seconds']:.1f} s on {d['threads']} host thread(s) of {os.cpu_count()} ({model})")
+
+    thr, ser = fig(runs["threaded"]), fig(runs["serial"])
+    out = dict(value=thr["value"], unit="Mcell-updates/s", cores=thr["cores"], kind="oracle", sample=thr["sample"],
+               serial=dict(value=ser["value"], unit="Mcell-updates/s", cores=1, sample=ser["sample"]),
+               cpu_model=model, host_cpus=os.cpu_count())
+    return out
 
 
 def timed(torch, fn, stream=None):
@@ -279,7 +308,11 @@ def main():
     ap.add_argument("--zchunk", type=int, default=0)
     ap.add_argument("--mode", choices=["step", "copy"], default="step",
                     help="copy: device-to-device copies of one state (calibrates the HBM byte counters)")
+    ap.add_argument("--cpu-worker", type=float, default=None, help=argparse.SUPPRESS)
     args = ap.parse_args()
+    if args.cpu_worker is not None:
+        cpu_worker(args.cpu_worker)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
@@ -371,7 +404,7 @@ def main():
         out["batch"] = batch_leg(torch, A, W)
         torch.cuda.empty_cache()
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(cfg, prob, prm, seed)
+        out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
 
 

@@ -1,9 +1,10 @@
 """Build libars.so (the HIP library behind include/ars.h) for gfx950.
 
 hipcc cross-compiles without a GPU.  Flags:
-  -ffp-contract=off      no FMA contraction: every kernel evaluates exactly
-                         the expression trees written in the source, so all
-                         GPU paths agree bit for bit;
+  -ffp-contract=on       a * b + c within one source expression becomes one
+                         fused multiply-add; contraction never crosses
+                         statements, so the kernels that share an expression
+                         (fused, reference, batched) still agree bit for bit;
   -packed-fp32-ops off   no packed-FP32 instructions are generated;
   --offload-arch=gfx950  MI355X only.
 """
@@ -20,7 +21,7 @@ SOURCES = ["ars_api.hip", "ars_fused.hip", "ars_ref.hip", "ars_reduce.hip", "ars
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
-    "-ffp-contract=off", "-fno-fast-math",
+    "-ffp-contract=on", "-fno-fast-math",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-munsafe-fp-atomics",
     "-Wno-unused-variable", "-Wno-unused-parameter",

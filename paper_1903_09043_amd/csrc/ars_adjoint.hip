@@ -252,7 +252,7 @@ __device__ __forceinline__ void adj_cell_values(const Params& P, const RefGrid& 
                                                 double lamz, const double* btb) {
   constexpr int NV = DIM + 2;
   const long long n = G.npad;
-  const double iL = 1.0 / W[R_L * n + i];
+  const double iL = rcp_nr(W[R_L * n + i]);
   double consb[NV], Ab[NV];
   double Lb = 0.0;
   for (int v = 0; v < NV; ++v) {

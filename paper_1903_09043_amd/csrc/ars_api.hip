@@ -194,7 +194,8 @@ int ars_create(const ars_config* cfg, ars_ctx** out) {
   const long long cols = (long long)c->P.nx * c->P.ny;
   int zc;
   if (cfg->dim == 3) {
-    const long long tiles = ((c->P.nx + 31) / 32) * (long long)((c->P.ny + 9) / 10);  // 32 x 10 outputs per tile
+    constexpr int TX = ARS_T3X - 4, TY = ARS_T3Y - 4;  // outputs per tile
+    const long long tiles = ((c->P.nx + TX - 1) / TX) * (long long)((c->P.ny + TY - 1) / TY);
     const long long want = 1536;
     long long nch = std::max(1ll, std::min((long long)c->P.nz, want / std::max(1ll, tiles)));
     zc = (int)((c->P.nz + nch - 1) / nch);

@@ -2,9 +2,9 @@
 // step (arXiv 1903.09043, Sec. 2) for gfx950, shared by the fused kernels,
 // the phase-by-phase reference kernels, the batched kernel and the adjoint.
 //
-// Every function fixes one expression tree (operation order, no FMA
-// contraction: the library is built with -ffp-contract=off) so that all GPU
-// paths produce the same bits.
+// Every function fixes one expression tree (operation order; the library is
+// built with -ffp-contract=on, which fuses a multiply and an add only inside
+// one expression) so that all GPU paths produce the same bits.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -41,6 +41,41 @@ struct Control {
   unsigned long long pad1[25];
 };
 
+#ifndef ARS_FASTMATH
+#define ARS_FASTMATH 1
+#endif
+
+// Reciprocal and reciprocal square root to about one ulp: the hardware
+// estimates (v_rcp_f64 / v_rsq_f64, good to about 2^-23) refined by two
+// Newton-Raphson steps each (quadratic convergence), a third of the
+// instructions of the correctly rounded division and square root the
+// compiler expands.  Every GPU path calls these same functions, so all of
+// them round alike.
+__device__ __forceinline__ double rcp_nr(double x) {
+#if ARS_FASTMATH
+  double r = __builtin_amdgcn_rcp(x);
+  double e = __builtin_fma(-x, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-x, r, 1.0);
+  return __builtin_fma(r, e, r);
+#else
+  return 1.0 / x;
+#endif
+}
+__device__ __forceinline__ double rsq_nr(double x) {
+#if ARS_FASTMATH
+  double y = __builtin_amdgcn_rsq(x);
+  double t = x * y;
+  double e = __builtin_fma(-t, y, 1.0);  // 1 - x y^2
+  y = __builtin_fma(0.5 * y, e, y);
+  t = x * y;
+  e = __builtin_fma(-t, y, 1.0);
+  return __builtin_fma(0.5 * y, e, y);
+#else
+  return 1.0 / sqrt(x);
+#endif
+}
+
 __device__ __forceinline__ double dmax2(double a, double b) { return a >= b ? a : b; }
 __device__ __forceinline__ double dmin2(double a, double b) { return a <= b ? a : b; }
 
@@ -63,7 +98,7 @@ template <int DIM>
 __device__ __forceinline__ Prim<DIM> cons_to_prim(const Params& P, const double* b) {
   Prim<DIM> q;
   q.rho = b[0];
-  q.r = 1.0 / q.rho;
+  q.r = rcp_nr(q.rho);
 #pragma unroll
   for (int k = 0; k < DIM; ++k) q.u[k] = b[1 + k] * q.r;
   double kin = b[1] * q.u[0];
@@ -71,10 +106,11 @@ __device__ __forceinline__ Prim<DIM> cons_to_prim(const Params& P, const double*
   for (int k = 1; k < DIM; ++k) kin = kin + b[1 + k] * q.u[k];
   kin = 0.5 * kin;
   q.p = P.gm1 * (b[DIM + 1] - kin);
-  q.c = sqrt((P.gamma * q.p) * q.r);
+  const double c2 = (P.gamma * q.p) * q.r;  // c^2 = gamma p / rho
+  q.ic = rsq_nr(c2);
+  q.c = c2 * q.ic;
   q.rc = q.rho * q.c;
   q.T = q.p * q.r;
-  q.ic = 1.0 / q.c;
   q.irc = q.r * q.ic;
   return q;
 }
@@ -90,7 +126,7 @@ __device__ __forceinline__ Prim<DIM> wall_ghost(const Params& P, const Prim<DIM>
   const double Tg = (P.thermal[side] == TH_FIXED) ? P.Tw2[side] - Ti : Ti;
   const double hd = 0.5 * delta;
   g.rho = (in.rho * (Ti - hd)) / (Tg + hd);
-  g.r = 1.0 / g.rho;
+  g.r = rcp_nr(g.rho);
   g.p = g.rho * Tg;
   g.T = Tg;
 #pragma unroll
@@ -98,9 +134,10 @@ __device__ __forceinline__ Prim<DIM> wall_ghost(const Params& P, const Prim<DIM>
     const bool flip = P.noslip ? true : (k == DIM - 1);
     g.u[k] = flip ? -in.u[k] : in.u[k];
   }
-  g.c = sqrt((P.gamma * g.p) * g.r);
+  const double c2 = (P.gamma * g.p) * g.r;
+  g.ic = rsq_nr(c2);
+  g.c = c2 * g.ic;
   g.rc = g.rho * g.c;
-  g.ic = 1.0 / g.c;
   g.irc = g.r * g.ic;
   return g;
 }

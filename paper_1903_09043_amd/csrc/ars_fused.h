@@ -258,7 +258,7 @@ __device__ __forceinline__ void march_tile(const Params& P, const double* __rest
       } else {
         calE = U1[NV - 1] + U1[0] * phi1;
       }
-      const double iL = 1.0 / Lc;
+      const double iL = rcp_nr(Lc);
       bt1[0] = U1[0] * iL;
       bt1[1] = (U1[1] - Amx) * iL;
       if (DIM == 3) {

@@ -162,8 +162,8 @@ hipError_t launch_step_fused(const Params& P, const double* Uin, double* Uout, S
   if (P.dim == 2)
     return P.nc ? launch_variant<2, true, 64, 1>(P, Uin, Uout, io, ts, s)
                 : launch_variant<2, false, 64, 1>(P, Uin, Uout, io, ts, s);
-  return P.nc ? launch_variant<3, true, 36, 14>(P, Uin, Uout, io, ts, s)
-              : launch_variant<3, false, 36, 14>(P, Uin, Uout, io, ts, s);
+  return P.nc ? launch_variant<3, true, ARS_T3X, ARS_T3Y>(P, Uin, Uout, io, ts, s)
+              : launch_variant<3, false, ARS_T3X, ARS_T3Y>(P, Uin, Uout, io, ts, s);
 }
 
 }  // namespace ars

@@ -7,6 +7,14 @@
 #include "../../include/ars.h"
 #include "ars_dev.h"
 
+// Positions (outputs + 4) of the 3D fused step's tile.
+#ifndef ARS_T3X
+#define ARS_T3X 36
+#endif
+#ifndef ARS_T3Y
+#define ARS_T3Y 14
+#endif
+
 namespace ars {
 
 // Per-launch inputs/outputs of one fused step.

@@ -169,7 +169,7 @@ __global__ void k_ref_face_cell(Params P, RefGrid G, const double* __restrict__ 
   } else {
     calE = E0 + rho * phi_at(P, qz - 2);
   }
-  const double iL = 1.0 / Lc;
+  const double iL = rcp_nr(Lc);
   W[R_L * n + i] = Lc;
   W[R_SB * n + i] = sb;
   W[R_BT * n + i] = rho * iL;
