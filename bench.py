@@ -52,6 +52,22 @@ def load_counters():
     return d
 
 
+def batch_counters():
+    """The committed counter summary of the batched kernel, if taken on the
+    current kernel source (else None)."""
+    p = os.path.join(ROOT, "profiles", "batch_rb2d_512_counters.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        d = json.load(open(p))
+    except Exception:
+        return None
+    h = hashlib.sha256()
+    for f in ("ars_batch.hip", "ars_fused.h", "ars_dev.h"):
+        h.update(open(os.path.join(ROOT, "paper_1903_09043_amd", "csrc", f), "rb").read())
+    return d if d.get("kernel_hash") == h.hexdigest()[:16] else None
+
+
 def load_traffic(n_cells):
     """HBM bytes per launch of the fused step (FETCH_SIZE and WRITE_SIZE,
     scaled by a copy of known size) for the 256^3 workload."""
@@ -246,6 +262,19 @@ def small_configs_leg(torch, A, W):
     return out
 
 
+def batch_roofline(cell_updates, ms):
+    """HBM view of the batched kernel: 64 algorithmic bytes per 2D cell
+    update over the launch time.  The 512 states (235 MB, twice for the
+    ping-pong) partly fit in the 256 MB MALL, so this is not an HBM-bound
+    claim; traffic from the committed counters when they match the source."""
+    achieved = cell_updates * 64 / (ms * 1e-3) / 1e9
+    c = batch_counters()
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "cache_resident": "partly (235 MB x 2 vs 256 MB MALL)",
+            "traffic": (c["read_bytes"] + c["write_bytes"]) if c else None,
+            "valu_busy_frac": c["valu_busy_frac"] if c else None}
+
+
 def batch_leg(torch, A, W, nsteps=500, loop=True):
     """Speedup of the batched persistent launch (graph-captured, one launch
     for all instances and steps) over the loop of ars_step(500) per
@@ -290,6 +319,7 @@ def batch_leg(torch, A, W, nsteps=500, loop=True):
             "batched_Mcell_per_s": round(cells * nsteps / batch_ms / 1e3, 1),
             "loop_Mcell_per_s": round(cells * nsteps / loop_ms / 1e3, 1),
             "bitwise_equal": bool(same), "faults": int((fc >= 0).sum()),
+            "roofline": batch_roofline(cells * nsteps, batch_ms),
             "tiling": {"rows": rows, "zc_policy": tune["zc_policy"], "tuner_candidates": tune["n_candidates"]}}
 
 
