@@ -151,6 +151,16 @@ int ars_workspace_init(ars_ctx* ctx, void* d_work, void* stream);
 int ars_set_zchunk(ars_ctx* ctx, int zchunk);
 int ars_get_zchunk(const ars_ctx* ctx);
 
+/* Tile of the 3D fused step: output cells per workgroup in x and y (plus a
+ * 2-cell halo on each side), each a compiled kernel; results do not depend
+ * on it.  ARS_TILE3_32x10 (36 x 14 positions, the default) or
+ * ARS_TILE3_16x20 (20 x 24).  Choosing a tile resets the vertical share
+ * to that tile's default.  2D problems have one tile (EUNSUPPORTED for the
+ * other). */
+enum { ARS_TILE3_32x10 = 0, ARS_TILE3_16x20 = 1 };
+int ars_set_tile3(ars_ctx* ctx, int tile);
+int ars_get_tile3(const ars_ctx* ctx);
+
 /* Build an initial state (Sec. 4 problems; hydrostatic bases from the
  * discrete equilibrium eq. well_balanced_formula, Sec. 4.3/4.5) on the
  * host and copy it to d_state (synchronous on `stream`).  RB perturbation:
@@ -357,8 +367,9 @@ int ars_batch_read(const ars_batch* b, const void* d_table, double* h_t, double*
  * 32).  Results never depend on either, only time does.
  *
  * ars_autotune times the fused step (trial_steps steps after one untimed
- * step, per candidate) for candidate (zchunk, wg_per_cu) pairs on a copy of
- * d_state, keeps the fastest in ctx and returns it in *out (may be NULL).
+ * step, per candidate) for candidate (tile, zchunk, wg_per_cu) triples (both
+ * tiles of ars_set_tile3 in 3D) on a copy of d_state, keeps the fastest in
+ * ctx and returns it in *out (may be NULL).
  * d_state is not modified; the workspace's rate slots and fault latch are
  * reset (as by ars_workspace_init).  It allocates and frees a temporary
  * device copy of two states: a set-up call, never to be captured.
@@ -370,7 +381,7 @@ int ars_batch_read(const ars_batch* b, const void* d_table, double* h_t, double*
  * restored to its contents at the call; it allocates a temporary copy.
  *
  * cache_path (may be NULL): text file of tuned shapes, one line per key
- * "<key> <a> <b> <ms_per_step>"; a key found there is applied without
+ * "<key> <a> <b> <ms_per_step> [<tile>]"; a key found there is applied without
  * timing (from_cache = 1), otherwise the result is appended.  Keys name
  * the device (architecture, compute units) and the problem (dimension,
  * grid, boundary kinds, theta and dissipation switches; for a batch a hash
@@ -380,6 +391,7 @@ typedef struct ars_tune_result {
   int32_t rows, zc_policy;    /* batch */
   int32_t from_cache, n_candidates;
   double ms_per_step;         /* of the chosen shape */
+  int32_t tile3, pad_;        /* fused step, 3D: ARS_TILE3_* */
 } ars_tune_result;
 int ars_set_tiling(ars_ctx* ctx, int zchunk, int wg_per_cu);
 int ars_get_tiling(const ars_ctx* ctx, int* zchunk, int* wg_per_cu);

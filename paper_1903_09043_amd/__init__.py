@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libars.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ENONPHYS, EUNSUPPORTED, ESCRATCH = 0, -1, -2, -3, -4, -5, -6
 NOALLOC_MAX_STATE = 131072  # ARS_NOALLOC_MAX_STATE of include/ars.h
+TILE3_32x10, TILE3_16x20 = 0, 1
 BC_PERIODIC, BC_WALL, BC_OUTFLOW = 0, 1, 2
 
 
@@ -47,7 +48,8 @@ class ArsConfig(C.Structure):
 
 class ArsTuneResult(C.Structure):
     _fields_ = [("zchunk", C.c_int32), ("wg_per_cu", C.c_int32), ("rows", C.c_int32), ("zc_policy", C.c_int32),
-                ("from_cache", C.c_int32), ("n_candidates", C.c_int32), ("ms_per_step", C.c_double)]
+                ("from_cache", C.c_int32), ("n_candidates", C.c_int32), ("ms_per_step", C.c_double),
+                ("tile3", C.c_int32), ("pad_", C.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -108,6 +110,8 @@ SIGNATURES = [
     ("ars_batch_replay", C.c_int, [_VP, _VP]),
     ("ars_batch_read", C.c_int, [_VP, _VP, _DP, _DP, C.POINTER(C.c_int64), _VP]),
     ("ars_set_tiling", C.c_int, [_VP, C.c_int, C.c_int]),
+    ("ars_set_tile3", C.c_int, [_VP, C.c_int]),
+    ("ars_get_tile3", C.c_int, [_VP]),
     ("ars_get_tiling", C.c_int, [_VP, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     ("ars_autotune", C.c_int, [_VP, _VP, _VP, C.c_int, C.c_char_p, _VP, C.POINTER(ArsTuneResult)]),
     ("ars_batch_autotune", C.c_int, [_VP, _VP, _VP, _VP, C.c_int, C.c_char_p, _VP, C.POINTER(ArsTuneResult)]),
@@ -224,6 +228,14 @@ class Context:
 
     def set_zchunk(self, z: int):
         _check(lib().ars_set_zchunk(self.h, int(z)), "ars_set_zchunk")
+
+    def set_tile3(self, tile: int):
+        """3D tile of the fused step: TILE3_32x10 (default) or TILE3_16x20."""
+        _check(lib().ars_set_tile3(self.h, int(tile)), "ars_set_tile3")
+
+    @property
+    def tile3(self) -> int:
+        return lib().ars_get_tile3(self.h)
 
     def set_tiling(self, zchunk: int, wg_per_cu: int = 0):
         _check(lib().ars_set_tiling(self.h, int(zchunk), int(wg_per_cu)), "ars_set_tiling")

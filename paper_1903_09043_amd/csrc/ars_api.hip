@@ -135,6 +135,29 @@ static unsigned flat_blocks(long long n) {
 
 ars::Params ars::params_of(const ars_config* c) { return derive(c); }
 
+int ars::default_zchunk(const Params& P, int tile3) {
+  int zc;
+  if (P.dim == 3) {
+    // enough (tile, chunk) shares to fill 256 CUs several times over
+    const int TX = TILE3_EX[tile3] - 4, TY = TILE3_EY[tile3] - 4;  // outputs per tile
+    const long long tiles = ((P.nx + TX - 1) / TX) * (long long)((P.ny + TY - 1) / TY);
+    const long long want = 1536;
+    const long long nch = std::max(1ll, std::min((long long)P.nz, want / std::max(1ll, tiles)));
+    zc = (int)((P.nz + nch - 1) / nch);
+  } else {
+    // 2D: (segment, plane) pairs per workgroup share ~ sqrt(pairs) / 13,
+    // fitted to measured step times from 64 x 32 to 2048^2 (within a few
+    // percent of the best share everywhere): small grids march one plane
+    // per workgroup, since their step time is the latency of one march,
+    // large ones longer shares that amortise the four halo planes
+    const long long tiles = (P.nx + 59) / 60;
+    const double pairs = (double)tiles * (double)P.nz;
+    zc = (int)std::llround(std::sqrt(pairs) / 13.0);
+    zc = std::max(1, std::min(zc, P.nz));
+  }
+  return std::max(1, zc);
+}
+
 extern "C" {
 
 const char* ars_strerror(int s) {
@@ -190,28 +213,8 @@ int ars_create(const ars_config* cfg, ars_ctx** out) {
   if (!c) return ARS_ENOMEM;
   c->cfg = *cfg;
   c->P = derive(cfg);
-  // vertical chunk: enough workgroups to fill 256 CUs several times over
-  const long long cols = (long long)c->P.nx * c->P.ny;
-  int zc;
-  if (cfg->dim == 3) {
-    constexpr int TX = ARS_T3X - 4, TY = ARS_T3Y - 4;  // outputs per tile
-    const long long tiles = ((c->P.nx + TX - 1) / TX) * (long long)((c->P.ny + TY - 1) / TY);
-    const long long want = 1536;
-    long long nch = std::max(1ll, std::min((long long)c->P.nz, want / std::max(1ll, tiles)));
-    zc = (int)((c->P.nz + nch - 1) / nch);
-  } else {
-    // 2D: (segment, plane) pairs per workgroup share ~ sqrt(pairs) / 13,
-    // fitted to measured step times from 64 x 32 to 2048^2 (within a few
-    // percent of the best share everywhere): small grids march one plane
-    // per workgroup, since their step time is the latency of one march,
-    // large ones longer shares that amortise the four halo planes
-    const long long tiles = (c->P.nx + 59) / 60;
-    const double pairs = (double)tiles * (double)c->P.nz;
-    zc = (int)std::llround(std::sqrt(pairs) / 13.0);
-    zc = std::max(1, std::min(zc, c->P.nz));
-  }
-  (void)cols;
-  c->ts.zchunk = std::max(1, zc);
+  c->ts.tile3 = 0;
+  c->ts.zchunk = ars::default_zchunk(c->P, 0);
   c->ts.num_cu = 0;
   c->ts.wg_per_cu = 0;
   c->len = (size_t)(cfg->dim + 2) * (size_t)c->P.ncell;
@@ -251,6 +254,18 @@ int ars_get_tiling(const ars_ctx* c, int* zchunk, int* wg_per_cu) {
   if (wg_per_cu) *wg_per_cu = c->ts.wg_per_cu;
   return ARS_OK;
 }
+
+int ars_set_tile3(ars_ctx* c, int tile) {
+  if (!c || (tile != ARS_TILE3_32x10 && tile != ARS_TILE3_16x20)) return ARS_EINVAL;
+  if (c->cfg.dim != 3) return tile == ARS_TILE3_32x10 ? ARS_OK : ARS_EUNSUPPORTED;
+  if (c->ts.tile3 != tile) {
+    c->ts.tile3 = tile;
+    c->ts.zchunk = ars::default_zchunk(c->P, tile);
+  }
+  return ARS_OK;
+}
+
+int ars_get_tile3(const ars_ctx* c) { return c ? c->ts.tile3 : -1; }
 
 int ars_workspace_init(ars_ctx* c, void* d_work, void* stream) {
   if (!c || !d_work) return ARS_EINVAL;

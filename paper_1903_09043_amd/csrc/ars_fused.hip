@@ -162,8 +162,11 @@ hipError_t launch_step_fused(const Params& P, const double* Uin, double* Uout, S
   if (P.dim == 2)
     return P.nc ? launch_variant<2, true, 64, 1>(P, Uin, Uout, io, ts, s)
                 : launch_variant<2, false, 64, 1>(P, Uin, Uout, io, ts, s);
-  return P.nc ? launch_variant<3, true, ARS_T3X, ARS_T3Y>(P, Uin, Uout, io, ts, s)
-              : launch_variant<3, false, ARS_T3X, ARS_T3Y>(P, Uin, Uout, io, ts, s);
+  if (ts.tile3 == 1)
+    return P.nc ? launch_variant<3, true, TILE3_EX[1], TILE3_EY[1]>(P, Uin, Uout, io, ts, s)
+                : launch_variant<3, false, TILE3_EX[1], TILE3_EY[1]>(P, Uin, Uout, io, ts, s);
+  return P.nc ? launch_variant<3, true, TILE3_EX[0], TILE3_EY[0]>(P, Uin, Uout, io, ts, s)
+              : launch_variant<3, false, TILE3_EX[0], TILE3_EY[0]>(P, Uin, Uout, io, ts, s);
 }
 
 }  // namespace ars

@@ -7,14 +7,6 @@
 #include "../../include/ars.h"
 #include "ars_dev.h"
 
-// Positions (outputs + 4) of the 3D fused step's tile.
-#ifndef ARS_T3X
-#define ARS_T3X 36
-#endif
-#ifndef ARS_T3Y
-#define ARS_T3Y 14
-#endif
-
 namespace ars {
 
 // Per-launch inputs/outputs of one fused step.
@@ -29,7 +21,13 @@ struct StepIO {
   int zchunk, ntx, nty;
 };
 
+// Tiles of the 3D fused step (positions = outputs + the 2-cell halo on
+// each side): ARS_TILE3_32x10 and ARS_TILE3_16x20 of include/ars.h.
+constexpr int TILE3_EX[2] = {36, 20};
+constexpr int TILE3_EY[2] = {14, 24};
+
 struct TileShape {
+  int tile3;      // 3D tile (index into TILE3_EX / TILE3_EY)
   int zchunk;     // minimum share of planes per workgroup
   int num_cu;     // compute units of the device (queried at first launch)
   int wg_per_cu;  // resident workgroups per CU of the chosen kernel
@@ -52,6 +50,8 @@ hipError_t launch_step_adjoint(const Params& P, const double* Un, const double* 
 
 // Derived kernel parameters of a validated configuration (ars_api.hip).
 Params params_of(const ars_config* c);
+// Default vertical share per workgroup of the fused step for a tile.
+int default_zchunk(const Params& P, int tile3);
 
 // Batched problems (ars_batch.hip): x segments of one instance and the
 // cost-model vertical chunk count for `rows` segments per workgroup.

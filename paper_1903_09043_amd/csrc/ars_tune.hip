@@ -35,7 +35,7 @@ std::string device_tag() {
   return arch + ":cu" + std::to_string(prop.multiProcessorCount);
 }
 
-bool cache_lookup(const char* path, const std::string& key, int* a, int* b, double* ms) {
+bool cache_lookup(const char* path, const std::string& key, int* a, int* b, double* ms, int* c = nullptr) {
   if (!path || !path[0]) return false;
   FILE* f = std::fopen(path, "r");
   if (!f) return false;
@@ -43,12 +43,14 @@ bool cache_lookup(const char* path, const std::string& key, int* a, int* b, doub
   bool found = false;
   while (std::fgets(line, sizeof line, f)) {
     char k[768];
-    int x = 0, y = 0;
+    int x = 0, y = 0, z = 0;
     double m = 0.0;
-    if (std::sscanf(line, "%767s %d %d %lf", k, &x, &y, &m) == 4 && key == k) {
+    const int got = std::sscanf(line, "%767s %d %d %lf %d", k, &x, &y, &m, &z);
+    if (got >= 4 && key == k) {
       *a = x;
       *b = y;
       *ms = m;
+      if (c) *c = got == 5 ? z : 0;
       found = true;
     }
   }
@@ -56,11 +58,14 @@ bool cache_lookup(const char* path, const std::string& key, int* a, int* b, doub
   return found;
 }
 
-void cache_store(const char* path, const std::string& key, int a, int b, double ms) {
+void cache_store(const char* path, const std::string& key, int a, int b, double ms, int c = -1) {
   if (!path || !path[0]) return;
   FILE* f = std::fopen(path, "a");
   if (!f) return;
-  std::fprintf(f, "%s %d %d %.6f\n", key.c_str(), a, b, ms);
+  if (c >= 0)
+    std::fprintf(f, "%s %d %d %.6f %d\n", key.c_str(), a, b, ms, c);
+  else
+    std::fprintf(f, "%s %d %d %.6f\n", key.c_str(), a, b, ms);
   std::fclose(f);
 }
 
@@ -108,11 +113,13 @@ int ars_autotune(ars_ctx* ctx, const double* d_state, void* d_work, int trial_st
                     std::to_string(P.bcy[0]) + std::to_string(P.bcz[0]) + ":lm" + std::to_string(P.low_mach) +
                     ":diss" + std::to_string(P.diss);
   ars_tune_result r{};
-  int za = 0, wb = 0;
+  int za = 0, wb = 0, tc = 0;
   double ms = 0.0;
-  if (cache_lookup(cache_path, key, &za, &wb, &ms) && za >= 1 && wb >= 0) {
+  if (cache_lookup(cache_path, key, &za, &wb, &ms, &tc) && za >= 1 && wb >= 0 && (tc == 0 || (tc == 1 && P.dim == 3))) {
+    ctx->ts.tile3 = tc;
     ctx->ts.zchunk = za;
     ctx->ts.wg_per_cu = wb;
+    r.tile3 = tc;
     r.zchunk = za;
     r.wg_per_cu = wb;
     r.ms_per_step = ms;
@@ -120,13 +127,11 @@ int ars_autotune(ars_ctx* ctx, const double* d_state, void* d_work, int trial_st
     if (out) *out = r;
     return ARS_OK;
   }
-  // candidates: vertical share per workgroup around the built-in choice,
-  // and workgroups per CU (0 = as many as are resident at once, else that
-  // many per CU, queued beyond residency)
-  std::vector<int> zs;
-  const int z0 = ctx->ts.zchunk;
-  for (int z : {z0, 1, 2, 4, 8, 16, 32, 64, std::max(1, z0 / 2), z0 * 2})
-    if (z >= 1 && z <= P.nz && std::find(zs.begin(), zs.end(), z) == zs.end()) zs.push_back(z);
+  // candidates: the 3D tiles; for each, vertical shares per workgroup
+  // around that tile's default; workgroups per CU (0 = as many as are
+  // resident at once, else that many per CU, queued beyond residency)
+  std::vector<int> tiles = {ctx->ts.tile3};
+  if (P.dim == 3) tiles = {0, 1};
   std::vector<int> ws = {0, 2, 4};
   if (P.dim == 2) ws = {0, 4, 8, 16};
   double* buf = nullptr;
@@ -141,23 +146,31 @@ int ars_autotune(ars_ctx* ctx, const double* d_state, void* d_work, int trial_st
   double best = -1.0;
   ars::TileShape bestts = keep;
   int ncand = 0;
-  for (int z : zs) {
-    for (int w : ws) {
-      ctx->ts.zchunk = z;
-      ctx->ts.wg_per_cu = w;
-      // every candidate starts from the caller's state
-      if (hipMemcpyAsync(A, d_state, bytes, hipMemcpyDeviceToDevice, s) != hipSuccess) rc = ARS_EDEVICE;
-      if (rc == ARS_OK) rc = ars_compute_dt(ctx, A, d_work, dd + 1, s);
-      double m = 0.0;
-      if (rc == ARS_OK)
-        rc = time_ms([&](int n) { return ars_step(ctx, A, B, d_work, n, dd, dd + 1, nullptr, s); }, trial_steps, s,
-                     &m);
-      if (rc != ARS_OK) break;
-      ++ncand;
-      if (best < 0.0 || m < best) {
-        best = m;
-        bestts = ctx->ts;
+  for (int tl : tiles) {
+    std::vector<int> zs;
+    const int z0 = tl == keep.tile3 ? keep.zchunk : ars::default_zchunk(P, tl);
+    for (int z : {z0, 1, 2, 4, 8, 16, 32, 64, std::max(1, z0 / 2), z0 * 2})
+      if (z >= 1 && z <= P.nz && std::find(zs.begin(), zs.end(), z) == zs.end()) zs.push_back(z);
+    for (int z : zs) {
+      for (int w : ws) {
+        ctx->ts.tile3 = tl;
+        ctx->ts.zchunk = z;
+        ctx->ts.wg_per_cu = w;
+        // every candidate starts from the caller's state
+        if (hipMemcpyAsync(A, d_state, bytes, hipMemcpyDeviceToDevice, s) != hipSuccess) rc = ARS_EDEVICE;
+        if (rc == ARS_OK) rc = ars_compute_dt(ctx, A, d_work, dd + 1, s);
+        double m = 0.0;
+        if (rc == ARS_OK)
+          rc = time_ms([&](int n) { return ars_step(ctx, A, B, d_work, n, dd, dd + 1, nullptr, s); }, trial_steps,
+                       s, &m);
+        if (rc != ARS_OK) break;
+        ++ncand;
+        if (best < 0.0 || m < best) {
+          best = m;
+          bestts = ctx->ts;
+        }
       }
+      if (rc != ARS_OK) break;
     }
     if (rc != ARS_OK) break;
   }
@@ -174,7 +187,8 @@ int ars_autotune(ars_ctx* ctx, const double* d_state, void* d_work, int trial_st
     return rc;
   }
   ctx->ts = bestts;
-  cache_store(cache_path, key, bestts.zchunk, bestts.wg_per_cu, best);
+  cache_store(cache_path, key, bestts.zchunk, bestts.wg_per_cu, best, bestts.tile3);
+  r.tile3 = bestts.tile3;
   r.zchunk = bestts.zchunk;
   r.wg_per_cu = bestts.wg_per_cu;
   r.ms_per_step = best;

@@ -207,13 +207,18 @@ def test_autotune_and_cache(A, tmp_path):
     say("step tune", r3)
     assert r3["from_cache"] == 0 and r3["n_candidates"] >= 2
     assert torch.equal(S.U, U0)
-    assert S.ctx.tiling() == (r3["zchunk"], r3["wg_per_cu"])
+    assert S.ctx.tiling() == (r3["zchunk"], r3["wg_per_cu"]) and S.ctx.tile3 == r3["tile3"]
     S.compute_dt()
     S.step(5)
     ref = A.Solver(cfg).init(prob, prm, seed).step(5)
     torch.cuda.synchronize()
     assert torch.equal(S.U, ref.U) and S.t.item() == ref.t.item()
     assert S.fault()[0] == 0
+    # the tuned run against the oracle directly
+    r = O.run(cfg, O.init(cfg, prob, prm, seed), 5)
+    err = P.rel_err(cfg, S.numpy(), r["U"])
+    say("tuned step vs oracle", err)
+    assert err <= 1e-12
     S2 = A.Solver(cfg)
     S2.U.copy_(U0)
     assert S2.autotune(trial_steps=2, cache_path=cache)["from_cache"] == 1

@@ -193,15 +193,43 @@ def test_fused_equals_reference_path(A):
         assert bitwise(S1.numpy(), S2.numpy())
 
 
-def test_result_independent_of_zchunk(A):
+def test_result_independent_of_zchunk_and_tile(A):
+    """Vertical shares and both 3D tiles give the same bits."""
     cfg, prob, prm, seed = W.rb([40, 24, 30], [1.0, 1.0, 1.0], Ra=1e5, seed=9, amp=1e-2)
     outs = []
-    for zc in (30, 7, 1):
+    for tile, zc in ((A.TILE3_32x10, 30), (A.TILE3_32x10, 7), (A.TILE3_32x10, 1), (A.TILE3_16x20, 30),
+                     (A.TILE3_16x20, 4)):
         S = A.Solver(cfg).init(prob, prm, seed)
+        S.ctx.set_tile3(tile)
         S.ctx.set_zchunk(zc)
         S.step(6)
         outs.append(S.numpy())
-    assert bitwise(outs[0], outs[1]) and bitwise(outs[0], outs[2])
+    for o in outs[1:]:
+        assert bitwise(outs[0], o)
+
+
+@pytest.mark.parametrize("name", ["rb3d_ragged", "rb3d_thetaoff"])
+def test_tile_16x20_vs_oracle(A, name):
+    """The second 3D tile (16 x 20 outputs) against the oracle on ragged
+    grids with a flow added."""
+    make, nsteps, zc = CASES[name]
+    cfg, prob, prm, seed = make()
+    Uo0 = O.init(cfg, prob, prm, seed)
+    rng = np.random.default_rng(7)
+    for k in range(3):
+        Uo0[1 + k] = 1e-2 * rng.standard_normal(Uo0[0].shape) * Uo0[0]
+    Uo0[-1] += 0.5 * sum(Uo0[1 + k] ** 2 for k in range(3)) / Uo0[0]
+    import torch
+    S = A.Solver(cfg)
+    S.ctx.set_tile3(A.TILE3_16x20)
+    S.set_state(Uo0)
+    S.step(nsteps)
+    torch.cuda.synchronize()
+    assert S.fault()[0] == 0
+    r = O.run(cfg, Uo0, nsteps)
+    err = close(cfg, S.numpy(), r["U"])
+    say(name, "tile 16x20 max rel err", err)
+    assert err <= 1e-12
 
 
 def test_diagnostics_match_oracle(A):
