@@ -78,6 +78,9 @@ def lib():
         L.orc_splitmix64.argtypes = [C.c_uint64, C.c_long, C.POINTER(C.c_uint64)]
         L.orc_splitmix64.restype = None
         L.orc_num_threads.restype = C.c_int
+        L.orc_imex_system.argtypes = [cp, dp, C.c_double, C.c_int64, i64p, i64p, dp, dp, i64p]
+        L.orc_imex_residual.argtypes = [cp, dp, C.c_double, dp, dp]
+        L.orc_step_imex_x.argtypes = [cp, dp, dp, C.c_double, dp, i64p]
         _lib = L
     return _lib
 
@@ -262,6 +265,68 @@ def spectrum(cfg: dict, U, kz: int) -> np.ndarray:
     nshell = int(shell.max()) + 1
     E = np.bincount(shell.ravel(), weights=P.ravel(), minlength=nshell)[:nshell]
     return E / (2.0 * N * N)
+
+
+def imex_system(cfg: dict, U, dt_: float):
+    """Sparse matrix L (scipy CSR) and right-hand side b of the implicit
+    acoustic system L x = b of one IMEX step from U with time step dt
+    (ars_oracle.cpp, IMEX section); x = [Pi | u_0 | ... | u_{D-1}]."""
+    import scipy.sparse as sp
+    c = make_config(cfg)
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    D = cfg["dim"]
+    n = (D + 1) * ncell(cfg)
+    cap = n * (8 * D + 4)
+    while True:
+        rows = np.zeros(cap, dtype=np.int64)
+        cols = np.zeros(cap, dtype=np.int64)
+        vals = np.zeros(cap)
+        rhs = np.zeros(n)
+        nnz = C.c_int64(0)
+        rc = lib().orc_imex_system(C.byref(c), _dp(U), float(dt_), cap, rows.ctypes.data_as(C.POINTER(C.c_int64)),
+                                   cols.ctypes.data_as(C.POINTER(C.c_int64)), _dp(vals), _dp(rhs), C.byref(nnz))
+        if rc == OK:
+            break
+        if nnz.value <= cap:
+            raise ValueError("orc_imex_system failed")
+        cap = nnz.value
+    k = nnz.value
+    return sp.csr_matrix((vals[:k], (rows[:k], cols[:k])), shape=(n, n)), rhs
+
+
+def imex_residual(cfg: dict, U, dt_: float, x) -> np.ndarray:
+    c = make_config(cfg)
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    r = np.zeros_like(x)
+    assert lib().orc_imex_residual(C.byref(c), _dp(U), float(dt_), _dp(x), _dp(r)) == OK
+    return r
+
+
+def step_imex(cfg: dict, U, dt_: float):
+    """One IMEX step: the implicit system solved by a direct sparse solver
+    (the solution is that of the plain definition, a linear solve), then
+    the step with its interface values.  Returns (U_new, status, x)."""
+    import scipy.sparse.linalg as spl
+    Lm, b = imex_system(cfg, U, dt_)
+    x = spl.spsolve(Lm.tocsc(), b)
+    c = make_config(cfg)
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    out = np.zeros_like(U)
+    fc = C.c_int64(-1)
+    rc = lib().orc_step_imex_x(C.byref(c), _dp(U), _dp(np.ascontiguousarray(x)), float(dt_), _dp(out), C.byref(fc))
+    return out, rc, x
+
+
+def run_imex(cfg: dict, U, nsteps: int, dt_):
+    """nsteps IMEX steps with a fixed time step (or a list of them)."""
+    U = np.array(U, dtype=np.float64)
+    sched = list(dt_) if hasattr(dt_, "__len__") else [float(dt_)] * nsteps
+    for s in range(nsteps):
+        U, rc, _ = step_imex(cfg, U, sched[s])
+        if rc != OK:
+            return {"U": U, "status": rc, "steps": s + 1}
+    return {"U": U, "status": OK, "steps": nsteps}
 
 
 def splitmix64(seed: int, n: int) -> np.ndarray:

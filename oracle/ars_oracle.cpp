@@ -33,6 +33,13 @@
 //                         scheme of App. B (energy without the potential,
 //                         source (uS)_i, no relaxation step).
 //   O9 validity        -- L > 0, rho > 0, p > 0, finite.
+//   IMEX               -- implicit acoustic step (the further work of the
+//                         Conclusion): Sec. 2.1.2's acoustic step with its
+//                         interface values at the end of the step, a linear
+//                         system solved by a direct sparse solver in
+//                         oracle/__init__.py; then O5-O9.  See the IMEX
+//                         section for the reading and its one unpinned
+//                         coefficient.
 //
 // Multi-dimensional form: unsplit (every face from U^n with one dt, L sums
 // all directions), which is how the constant-potential limit (the all-regime
@@ -58,6 +65,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 #include <algorithm>
 #include <limits>
@@ -319,8 +327,12 @@ inline bool is_wall_face(const orc_config& c, const Grid& G, int d, int q) {
 }
 
 template <class S>
+void imex_override(const orc_config& c, const Grid& G, const State<S>& st, StepArrays<S>& A, double dt,
+                   const double* x);
+
+template <class S>
 int step_impl(const orc_config& c, const S* U, S* Uout, double dt, S mu, S kappa,
-              int64_t* fault_cell) {
+              int64_t* fault_cell, const double* imex_x = nullptr) {
   Grid G(c);
   const int D = G.D, z = G.zax, nv = D + 2;
   const long NP = G.npad;
@@ -352,6 +364,10 @@ int step_impl(const orc_config& c, const S* U, S* Uout, double dt, S mu, S kappa
           A.face[d][p] = acoustic_face(c, G, st.prim[p], st.prim[pr], d, phiL, phiR, w);
         }
   }
+
+  // Implicit acoustic step: the interface values u*, Pi* (and Pi* u*) of
+  // every face come from the solution x of the implicit system instead.
+  if (imex_x) imex_override(c, G, st, A, dt, imex_x);
 
   // O5: acoustic cell values for padded cells [1, P-1) along every axis.
   A.L.assign(NP, S(1.0));
@@ -516,6 +532,173 @@ int step_impl(const orc_config& c, const S* U, S* Uout, double dt, S mu, S kappa
   return ORC_OK;
 }
 
+
+// ---------------------------------------------------------------- IMEX --
+// Implicit acoustic step.  The paper names it as further work (Conclusion:
+// solve the acoustic part implicitly to lift the acoustic CFL condition and
+// keep the well-balanced gravity source) and prints no scheme; this is the
+// reading taken here.  Sec. 2.1.2's acoustic step is solved with its
+// interface values at the END of the step (backward Euler on the linear
+// relaxation system at frozen a), everything else as in the explicit step.
+// Unknowns per interior cell i: Pi_i and the normal velocities u_{d,i},
+// x = [Pi | u_0 | ... | u_{D-1}], each block in interior cell order.  Frozen
+// at t^n from O1-O4: a_j, S_j, theta_j of every face, rho_i, tau_i = 1/rho_i,
+// p_i, c_i, and the hydrostatic offset p_g - p_i of every wall ghost.  With
+// lambda_d = dt / dx_d:
+//   u*_j  = (u_L + u_R)/2 - (Pi_R - Pi_L - S_j) / (2 a_j)       (0 at walls)
+//   Pi*_j = (Pi_L + Pi_R)/2 - (a_j theta_j / 2)(u_R - u_L)
+//   u_{d,i} = u^n_{d,i} - lambda_d tau_i ([Pi*]_{d,i} - S-bar_{d,i})
+//   Pi_i    = p_i - rho_i c_i^2 sum_d lambda_d [u*]_{d,i}
+// The last line is the Lagrangian pressure update linearised through the
+// equation of state (dp = -rho c^2 dtau / tau, c^2 = gamma p / rho), the
+// implicit counterpart of the relaxation Pi~ = p_EOS of Sec. 2.1.2.
+// Parity unpinned for that coefficient: any positive one gives a
+// consistent, well-balanced and stable step, so no property of the paper
+// or of the mathematics tells rho c^2 apart (the rest of the system is
+// pinned: tests/test_oracle_imex.py).  Ghost
+// cells take the boundary rules of O1 applied to the unknowns: periodic
+// images, outflow copies, and at walls Pi_g = Pi_i + (p_g - p_i)^n with the
+// velocity of O1 (normal component reversed).  The implicit (u*, Pi*)
+// replace the explicit ones in O5-O8.
+
+// Padded extension of x (with_const: the wall ghosts' hydrostatic offset).
+void imex_extend(const orc_config& c, const Grid& G, const State<double>& st, const double* x, bool with_const,
+                 std::vector<double>& Pp, std::vector<double> up[3]) {
+  const int D = G.D, z = G.zax;
+  const long N = G.ncell;
+  Pp.assign(G.npad, 0.0);
+  for (int d = 0; d < D; ++d) up[d].assign(G.npad, 0.0);
+  for (int q2 = 0; q2 < G.P[2]; ++q2)
+    for (int q1 = 0; q1 < G.P[1]; ++q1)
+      for (int q0 = 0; q0 < G.P[0]; ++q0) {
+        int q[3] = {q0, q1, q2};
+        int rq[3] = {q0, q1, q2};
+        for (int a = 0; a < D; ++a)
+          if (a != z) rq[a] = resolve_axis(c, G, a, q[a]);
+        const long dst = G.pad(q0, q1, q2);
+        const int qz = q[z], nz = G.n[z];
+        bool wall_ghost = false;
+        int side = (qz < 2) ? 0 : 1;
+        if (qz < 2 || qz >= nz + 2) {
+          if (c.bc[z][side] == BC_WALL) {
+            wall_ghost = true;
+            rq[z] = (side == 0) ? 2 : nz + 1;
+          } else {
+            rq[z] = resolve_axis(c, G, z, qz);
+          }
+        }
+        const long cell = G.cell(rq[0] - 2, D > 1 ? rq[1] - 2 : 0, D > 2 ? rq[2] - 2 : 0);
+        double Pi = x[cell];
+        if (wall_ghost && with_const) {
+          const long pi_ = G.pad(rq[0], rq[1], rq[2]);
+          Pi = Pi + (st.prim[dst].p - st.prim[pi_].p);
+        }
+        Pp[dst] = Pi;
+        for (int d = 0; d < D; ++d) {
+          double u = x[(1 + d) * N + cell];
+          if (wall_ghost && (c.wall_noslip || d == z)) u = -u;
+          up[d][dst] = u;
+        }
+      }
+}
+
+// Implicit interface values of every padded face from the extension.
+void imex_faces(const orc_config& c, const Grid& G, const StepArrays<double>& A, const std::vector<double>& Pp,
+                const std::vector<double> up[3], bool with_const, std::vector<double> us[3],
+                std::vector<double> pis[3]) {
+  const int D = G.D;
+  long stride[3] = {1, (long)G.P[0], (long)G.P[0] * G.P[1]};
+  for (int d = 0; d < D; ++d) {
+    us[d].assign(G.npad, 0.0);
+    pis[d].assign(G.npad, 0.0);
+    for (int q2 = 0; q2 < G.P[2]; ++q2)
+      for (int q1 = 0; q1 < G.P[1]; ++q1)
+        for (int q0 = 0; q0 < G.P[0]; ++q0) {
+          int q[3] = {q0, q1, q2};
+          if (q[d] + 1 >= G.P[d]) continue;
+          const long p = G.pad(q0, q1, q2), pr = p + stride[d];
+          const Face<double>& f = A.face[d][p];
+          const double uL = up[d][p], uR = up[d][pr], PL = Pp[p], PR = Pp[pr];
+          const double Sj = with_const ? f.S_ : 0.0;
+          us[d][p] = A.wall[d][p] ? 0.0 : 0.5 * (uL + uR) - ((PR - PL) - Sj) / (2.0 * f.a);
+          pis[d][p] = 0.5 * (PL + PR) - ((0.5 * f.a) * f.theta) * (uR - uL);
+        }
+  }
+}
+
+// Frozen data of the implicit system at t^n (O1, O2, O4).
+struct ImexFrozen {
+  Grid G;
+  State<double> st;
+  StepArrays<double> A;
+  explicit ImexFrozen(const orc_config& c, const double* U) : G(c) {
+    build_padded(c, G, U, st);
+    long stride[3] = {1, (long)G.P[0], (long)G.P[0] * G.P[1]};
+    for (int d = 0; d < G.D; ++d) {
+      A.face[d].assign(G.npad, Face<double>());
+      A.wall[d].assign(G.npad, 0);
+      for (int q2 = 0; q2 < G.P[2]; ++q2)
+        for (int q1 = 0; q1 < G.P[1]; ++q1)
+          for (int q0 = 0; q0 < G.P[0]; ++q0) {
+            int q[3] = {q0, q1, q2};
+            if (q[d] + 1 >= G.P[d]) continue;
+            long p = G.pad(q0, q1, q2);
+            double phiL = st.phi[q[G.zax]], phiR = st.phi[q[G.zax] + (d == G.zax ? 1 : 0)];
+            bool w = is_wall_face(c, G, d, q[d]);
+            A.wall[d][p] = w;
+            A.face[d][p] = acoustic_face(c, G, st.prim[p], st.prim[p + stride[d]], d, phiL, phiR, w);
+          }
+    }
+  }
+};
+
+// Residual F(x) of the implicit system (with_const = false: its linear
+// part), one row per unknown in the order of x.
+void imex_residual(const orc_config& c, const ImexFrozen& F, double dt, const double* x, bool with_const,
+                   double* r) {
+  const Grid& G = F.G;
+  const int D = G.D, z = G.zax;
+  const long N = G.ncell;
+  long stride[3] = {1, (long)G.P[0], (long)G.P[0] * G.P[1]};
+  std::vector<double> Pp, up[3], us[3], pis[3];
+  imex_extend(c, G, F.st, x, with_const, Pp, up);
+  imex_faces(c, G, F.A, Pp, up, with_const, us, pis);
+  for (int k = 0; k < G.n[2]; ++k)
+    for (int j = 0; j < G.n[1]; ++j)
+      for (int i = 0; i < G.n[0]; ++i) {
+        const long cell = G.cell(i, j, k);
+        const long p = G.pad(i + 2, D > 1 ? j + 2 : 0, D > 2 ? k + 2 : 0);
+        const Prim<double>& q = F.st.prim[p];
+        double div = 0.0;
+        for (int d = 0; d < D; ++d) div = div + (dt / G.dx[d]) * (us[d][p] - us[d][p - stride[d]]);
+        const double rc2 = q.rho * (q.c * q.c);
+        r[cell] = (x[cell] - (with_const ? q.p : 0.0)) + rc2 * div;
+        for (int d = 0; d < D; ++d) {
+          double dpi = pis[d][p] - pis[d][p - stride[d]];
+          if (d == z && with_const) dpi = dpi - 0.5 * (F.A.face[d][p].S_ + F.A.face[d][p - stride[d]].S_);
+          const double un = with_const ? q.u[d] : 0.0;
+          r[(1 + d) * N + cell] = (x[(1 + d) * N + cell] - un) + ((dt / G.dx[d]) * q.r) * dpi;
+        }
+      }
+}
+
+template <class S>
+void imex_override(const orc_config& c, const Grid& G, const State<S>& st, StepArrays<S>& A, double dt,
+                   const double* x) {
+  if constexpr (std::is_same<S, double>::value) {
+    std::vector<double> Pp, up[3], us[3], pis[3];
+    imex_extend(c, G, st, x, true, Pp, up);
+    imex_faces(c, G, A, Pp, up, true, us, pis);
+    for (int d = 0; d < G.D; ++d)
+      for (long p = 0; p < G.npad; ++p) {
+        A.face[d][p].ustar = us[d][p];
+        A.face[d][p].pistar = pis[d][p];
+        A.face[d][p].P = pis[d][p] * us[d][p];
+      }
+  }
+  (void)dt;
+}
+
 // O3: the largest local rate lambda_i over interior cells.
 double max_rate(const orc_config& c, const double* U) {
   Grid G(c);
@@ -587,6 +770,54 @@ int orc_step_dt(const orc_config* c, const double* U, double* Uout, double dt, i
 // n steps in place; dt of each step from O3 on its own input state unless
 // dt_sched is given.  dt_log (optional) receives the dt used by each step;
 // *t is advanced.  Returns the first failing status.
+// Implicit acoustic step: the sparse matrix of the linear part of the
+// system (probed column by column: exact coefficients) and its right-hand
+// side -F(0); solve L x = rhs, then orc_step_imex_x.  cap: room for cap
+// nonzeros; EINVAL if too small (*nnz then holds the count needed) or for
+// the App. B energy form.
+int orc_imex_system(const orc_config* c, const double* U, double dt, int64_t cap, int64_t* rows, int64_t* cols,
+                    double* vals, double* rhs, int64_t* nnz) {
+  if (orc_validate(c) != ORC_OK || c->energy_form != 0) return ORC_EINVAL;
+  ImexFrozen F(*c, U);
+  const long N = F.G.ncell;
+  const long n = (long)(F.G.D + 1) * N;
+  std::vector<double> e(n, 0.0), col(n);
+  imex_residual(*c, F, dt, e.data(), true, rhs);
+  for (long i = 0; i < n; ++i) rhs[i] = -rhs[i];
+  int64_t k = 0;
+  for (long j = 0; j < n; ++j) {
+    e[j] = 1.0;
+    imex_residual(*c, F, dt, e.data(), false, col.data());
+    e[j] = 0.0;
+    for (long i = 0; i < n; ++i)
+      if (col[i] != 0.0) {
+        if (k < cap) {
+          rows[k] = i;
+          cols[k] = j;
+          vals[k] = col[i];
+        }
+        ++k;
+      }
+  }
+  *nnz = k;
+  return k <= cap ? ORC_OK : ORC_EINVAL;
+}
+
+// F(x) of the implicit system (test of a solution).
+int orc_imex_residual(const orc_config* c, const double* U, double dt, const double* x, double* r) {
+  if (orc_validate(c) != ORC_OK || c->energy_form != 0) return ORC_EINVAL;
+  ImexFrozen F(*c, U);
+  imex_residual(*c, F, dt, x, true, r);
+  return ORC_OK;
+}
+
+// One step with the interface values of the solution x of the implicit
+// system.
+int orc_step_imex_x(const orc_config* c, const double* U, const double* x, double dt, double* Uout,
+                    int64_t* fault_cell) {
+  if (orc_validate(c) != ORC_OK || c->energy_form != 0) return ORC_EINVAL;
+  return step_impl<double>(*c, U, Uout, dt, c->mu, c->kappa, fault_cell, x);
+}
 int orc_run(const orc_config* c, double* U, int nsteps, const double* dt_sched, double* dt_log, double* t,
             int64_t* fault_cell, int64_t* fault_step) {
   Grid G(*c);

@@ -1,0 +1,195 @@
+"""Pins of the oracle's implicit acoustic (IMEX) step.
+
+The paper names the implicit treatment of the acoustic part as further work
+(Conclusion) and prints no scheme; the reading (oracle/ars_oracle.cpp, IMEX
+section) solves Sec. 2.1.2's acoustic step with its interface values taken
+at the end of the step.  What pins it, independently of its own formulas:
+
+* consistency: as dt -> 0 the IMEX step differs from the explicit step of
+  eq. (all_regime_scheme) by O(dt^2) (both are first order in time);
+* well-balancing at any dt: a discrete hydrostatic equilibrium (eq.
+  well_balanced_formula) stays at rest for time steps far above the
+  acoustic CFL limit -- the property the Conclusion asks the implicit
+  scheme to keep;
+* conservation of mass, momentum and total energy (flux form);
+* linear stability: a small acoustic wave never grows, up to an acoustic
+  CFL number of 1000 (the point of the implicit step);
+* the wave travels at the physical sound speed c: its phase after half a
+  period converges to pi under refinement at a fixed acoustic CFL number
+  (a system relaxing at the numerical impedance a = K rho c would converge
+  to K pi);
+* low Mach: the Gresho vortex (Sec. 4.2) at Mach 1e-3 with steps 440 times
+  the acoustic limit keeps most of its kinetic energy with the low-Mach
+  correction and loses half of it without (eq. low_mach_correction).
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1903_09043_amd import workloads as W
+
+
+def _flow(cfg, U, amp=1e-2, seed=7):
+    rng = np.random.default_rng(seed)
+    D = cfg["dim"]
+    U = U.copy()
+    for k in range(D):
+        U[1 + k] = amp * rng.standard_normal(U[0].shape) * U[0]
+    U[-1] += 0.5 * sum(U[1 + k] ** 2 for k in range(D)) / U[0]
+    return U
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_imex_consistent_with_explicit_step(dim):
+    """|IMEX - explicit| shrinks as dt^2: the ratio over the last halving is
+    close to 4 (it would be 2 for an O(dt) inconsistency)."""
+    if dim == 2:
+        cfg, prob, prm, seed = W.rb([16, 8], [2.0, 1.0], Ra=1e4, seed=1, amp=1e-2)
+    else:
+        cfg, prob, prm, seed = W.rb([6, 5, 7], [1.0, 1.0, 1.0], Ra=1e5, seed=2, amp=1e-2)
+    U = _flow(cfg, O.init(cfg, prob, prm, seed))
+    dt = O.dt(cfg, U)
+    errs = []
+    for f in (0.5, 0.25, 0.125):
+        Ui, rc, _ = O.step_imex(cfg, U, dt * f)
+        Ue, rce, _ = O.step_dt(cfg, U, dt * f)
+        assert rc == 0 and rce == 0
+        errs.append(np.max(np.abs(Ui - Ue)))
+    assert errs[0] > 0.0
+    assert 3.5 < errs[1] / errs[2] < 4.5, errs
+    assert 3.0 < errs[0] / errs[1] < 4.5, errs
+
+
+@pytest.mark.parametrize("lm", [1, 0])
+@pytest.mark.parametrize("mult", [10, 100])
+def test_imex_well_balanced_rb_base(lm, mult):
+    """Inviscid RB base (linear T, fixed-T walls, hydrostatic by eq.
+    well_balanced_formula) at rest after 5 IMEX steps of 10 and 100 times
+    the explicit CFL step."""
+    cfg, prob, prm, seed = W.rb([12, 16], [2.0, 1.0], Ra=1e4, seed=1, amp=0.0, low_mach=lm)
+    cfg = dict(cfg, mu=0.0, kappa=0.0)
+    U = O.init(cfg, prob, prm, seed)
+    dt = O.dt(cfg, U) * mult
+    r = O.run_imex(cfg, U, 5, dt)
+    assert r["status"] == 0
+    assert np.max(np.abs(r["U"][1:3] / r["U"][0])) < 1e-12
+    assert np.max(np.abs(r["U"][0] - U[0])) < 1e-12
+
+
+def test_imex_well_balanced_isothermal_column():
+    """Sec. 4.3 isothermal column (walls at both ends) at 50 times the
+    explicit step, 10 steps: velocities at the round-off level of Table 1."""
+    for lm in (0, 1):
+        cfg = dict(dim=2, n=[4, 64], L=[1.0, 3.0], gamma=5.0 / 3.0, g=1.0, mu=0.0, kappa=0.0, K=1.1, cfl=0.4,
+                   low_mach=lm, dt_mode=0, bc=[[0, 0], [1, 1]], wall_noslip=1, thermal=[0, 0], T_wall=[1.0, 1.0])
+        U = O.init(cfg, W.PROB_ISOTHERMAL)
+        r = O.run_imex(cfg, U, 10, O.dt(cfg, U) * 50)
+        assert r["status"] == 0
+        assert np.max(np.abs(r["U"][1:3] / r["U"][0])) < 1e-13
+
+
+def test_imex_equilibrium_solves_the_system():
+    """At a discrete equilibrium the acoustic unknowns (Pi, u) = (p, 0) are
+    the solution: the residual of the implicit system vanishes there up to
+    the rounding of p_{i+1} - p_i - S (a few ulps of p, times dt / dx)."""
+    cfg, prob, prm, seed = W.rb([8, 12], [2.0, 1.0], Ra=1e4, seed=1, amp=0.0)
+    U = O.init(cfg, prob, prm, seed)
+    N = U[0].size
+    rho = U[0].ravel()
+    p = (cfg["gamma"] - 1.0) * U[-1].ravel()
+    x = np.concatenate([p, np.zeros(2 * N)])
+    for mult in (1.0, 1e3):
+        r = O.imex_residual(cfg, U, O.dt(cfg, U) * mult, x)
+        assert np.max(np.abs(r[:N])) <= 1e-15 * mult * np.max(p)
+        assert np.max(np.abs(r[N:])) <= 1e-15 * mult
+    assert rho.min() > 0
+
+
+@pytest.mark.parametrize("visc", [0.0, 2e-3])
+def test_imex_conservation_periodic(visc):
+    """Periodic box, no gravity: mass, momentum and total energy conserved
+    to round-off over 5 steps of 10 times the explicit step."""
+    cfg = dict(dim=2, n=[12, 10], L=[1.0, 0.8], gamma=5.0 / 3.0, g=0.0, mu=visc, kappa=1.5 * visc, K=1.1, cfl=0.4,
+               low_mach=1, dt_mode=0, bc=[[0, 0], [0, 0]], wall_noslip=1, thermal=[0, 0], T_wall=[1.0, 1.0])
+    from tests import inputs as I
+    U = I.smooth_random(cfg, seed=3)
+    dt = O.dt(cfg, U) * (10 if visc == 0.0 else 1)
+    r = O.run_imex(cfg, U, 5, dt)
+    assert r["status"] == 0
+    for v in range(4):
+        s0, s1 = U[v].sum(), r["U"][v].sum()
+        assert abs(s1 - s0) <= 1e-13 * max(np.abs(U[v]).sum(), 1.0), v
+
+
+def _sound_wave(n, eps=1e-6):
+    cfg = dict(dim=2, n=[n, 1], L=[1.0, 1.0], gamma=1.4, g=0.0, mu=0.0, kappa=0.0, K=1.1, cfl=0.4, low_mach=0,
+               dt_mode=0, bc=[[0, 0], [0, 0]], wall_noslip=1, thermal=[0, 0], T_wall=[1.0, 1.0])
+    x = (np.arange(n) + 0.5) / n
+    c = np.sqrt(1.4)
+    u = eps * np.sin(2 * np.pi * x)
+    p = 1.0 + c * u
+    rho = 1.0 + u / c
+    U = np.zeros((4, 1, n))
+    U[0, 0], U[1, 0], U[3, 0] = rho, rho * u, p / 0.4 + 0.5 * rho * u * u
+    return cfg, U, x, c
+
+
+def _mode(U, x, eps):
+    u = U[1, 0] / U[0, 0]
+    a = 2 * np.mean(u * np.sin(2 * np.pi * x))
+    b = 2 * np.mean(u * np.cos(2 * np.pi * x))
+    return np.hypot(a, b) / eps, np.arctan2(-b, a)
+
+
+@pytest.mark.parametrize("nu", [10.0, 100.0, 1000.0])
+def test_imex_linear_wave_never_grows(nu):
+    """Acoustic CFL number nu = K c dt / dx far above 1: the amplitude of a
+    small sound wave decreases at every step (until it reaches the
+    round-off floor of the 1e-6 wave, 1e-6 of it)."""
+    cfg, U, x, c = _sound_wave(32)
+    dt = nu * (1.0 / 32) / (1.1 * c)
+    amp_prev = 1.0
+    for s in range(12):
+        U, rc, _ = O.step_imex(cfg, U, dt)
+        assert rc == 0
+        amp, _ = _mode(U, x, 1e-6)
+        if amp_prev > 1e-6:
+            assert amp < amp_prev
+        amp_prev = amp
+    assert amp_prev < 1e-3
+
+
+def test_imex_wave_travels_at_sound_speed():
+    """Half a period of a right-moving sound wave at acoustic CFL number 2:
+    the phase converges to pi (speed c) as the grid is refined."""
+    errs = []
+    for n in (32, 64, 128):
+        cfg, U, x, c = _sound_wave(n)
+        dt = 2.0 * (1.0 / n) / (1.1 * c)
+        T = 0.5 / c
+        ns = int(round(T / dt))
+        r = O.run_imex(cfg, U, ns, T / ns)
+        assert r["status"] == 0
+        _, ph = _mode(r["U"], x, 1e-6)
+        errs.append(abs(ph - np.pi))
+    assert errs[0] > errs[1] > errs[2]
+    assert errs[2] < 0.03
+
+
+def test_imex_gresho_low_mach():
+    """Gresho vortex, Mach 1e-3, 32^2, time step of the transport CFL 0.4
+    (440 times the acoustic limit), 8 steps: the low-Mach correction keeps
+    the kinetic energy (> 85 %), without it half is lost (< 60 %); mass and
+    total energy are conserved to round-off."""
+    out = {}
+    for lm in (1, 0):
+        cfg, prob, prm, seed = W.gresho(n=32, Ma=1e-3, low_mach=lm)
+        U = O.init(cfg, prob, prm, seed)
+        d0 = O.diag(cfg, U)
+        r = O.run_imex(cfg, U, 8, 0.4 / 32)
+        assert r["status"] == 0
+        d = O.diag(cfg, r["U"])
+        out[lm] = d["e_kin"] / d0["e_kin"]
+        assert abs(d["mass"] - d0["mass"]) <= 1e-14 * d0["mass"]
+        assert abs(d["e_total"] - d0["e_total"]) <= 1e-14 * d0["e_total"]
+    assert out[1] > 0.85 and out[0] < 0.6
