@@ -50,7 +50,8 @@ typedef enum {
   ARS_EDEVICE = -3,       /* HIP runtime / launch error */
   ARS_ENONPHYS = -4,      /* latched numerical fault (see ars_diag.fault_cell) */
   ARS_EUNSUPPORTED = -5,  /* valid configuration this build does not run */
-  ARS_ESCRATCH = -6       /* state larger than the library's static scratch (ars_step_noalloc) */
+  ARS_ESCRATCH = -6,      /* state larger than the library's static scratch (ars_step_noalloc) */
+  ARS_ENOCONV = -7        /* implicit solve of ars_step_imex did not converge */
 } ars_status;
 
 enum { ARS_BC_PERIODIC = 0, ARS_BC_WALL = 1, ARS_BC_OUTFLOW = 2 };
@@ -76,7 +77,10 @@ enum {
  *  low_mach   1: theta = min(|u*| / max(c_L, c_R), 1); 0: theta = 1.
  *  dt_mode    0: lambda_i = sum_d (|u_d| + c)/dx_d + 2 D_i sum_d dx_d^-2
  *                with D_i = max(4 mu/3, kappa (gamma-1)) / rho_i;
- *             1: hyperbolic part only.
+ *             1: hyperbolic part only;
+ *             2: lambda_i = sum_d |u_d|/dx_d + the diffusive part (no sound
+ *                speed: the step ars_step_imex allows; ars_step itself is
+ *                unstable with it).
  *  bc[a][s]   per axis a, side s (0 low, 1 high): periodic / wall / outflow.
  *             Walls only on the gravity axis; gravity needs walls on it;
  *             periodic must be set on both sides.
@@ -234,6 +238,31 @@ int ars_step_noalloc(ars_ctx* ctx, double* d_state, int n_steps, double* d_t, do
  * *d_t advanced; *d_dt untouched. */
 int ars_step_sched(ars_ctx* ctx, double* d_state, double* d_tmp, void* d_work, int n_steps,
                    const double* d_dt_sched, double* d_t, void* stream);
+
+/* Implicit acoustic (IMEX) step: the further work named in the paper's
+ * Conclusion (solve the acoustic part implicitly to lift the acoustic CFL
+ * condition while keeping the well-balanced gravity source); the paper
+ * prints no scheme.  Reading: the acoustic step of Sec. 2.1.2 with its
+ * interface values u*, Pi* taken at the end of the step (backward Euler on
+ * the linear relaxation system at the frozen a, S and theta of t^n):
+ *   u*_j  = (u_L + u_R)/2 - (Pi_R - Pi_L - S_j) / (2 a_j)    (0 at walls)
+ *   Pi*_j = (Pi_L + Pi_R)/2 - (a_j theta_j / 2)(u_R - u_L)
+ *   u_{d,i} = u^n_{d,i} - (dt/dx_d) tau_i ([Pi*]_{d,i} - S-bar_{d,i})
+ *   Pi_i    = p_i - rho_i c_i^2 sum_d (dt/dx_d) [u*]_{d,i}
+ * solved for (Pi, u) by BiCGSTAB to ||residual|| <= tol ||rhs||; the
+ * implicit (u*, Pi*) then enter the acoustic cell values, transport,
+ * update and relaxation of eq. all_regime_scheme as in ars_step.  Dissipative
+ * fluxes stay explicit.  dt of step s = d_dt_sched[s] (device); with
+ * dt_mode = 2 ars_compute_dt gives the transport + diffusive CFL step that
+ * this call allows (the acoustic limit is lifted).  d_tmp: scratch state;
+ * d_work: the ars_step workspace (fault latch); d_work_imex:
+ * ars_workspace_bytes_imex bytes, caller-owned.  *h_iters (nullable): total
+ * solver iterations.  Synchronises (the solver reads its residual); returns
+ * ARS_ENOCONV if a solve does not reach tol within max_iter iterations,
+ * ARS_EUNSUPPORTED for the energy form of App. B. */
+size_t ars_workspace_bytes_imex(const ars_ctx* ctx);
+int ars_step_imex(ars_ctx* ctx, double* d_state, double* d_tmp, void* d_work, void* d_work_imex, int n_steps,
+                  const double* d_dt_sched, double* d_t, double tol, int max_iter, int* h_iters, void* stream);
 
 /* Reference path: the same step as separate phase kernels (ghosts and
  * primitives, faces, acoustic cell values, fluxes, update) with their

@@ -17,7 +17,8 @@
 //                         (R = 1, as p = rho T of Sec. 4.3), c^2 = gamma p / rho.
 //   O3 time step       -- CFL reduction ("time step kernel", Sec. 3.2); the
 //                         paper gives no formula, the reading is additive
-//                         hyperbolic + diffusive rate.
+//                         hyperbolic + diffusive rate (dt_mode 2, for the
+//                         IMEX step: transport + diffusive, no sound speed).
 //   O4 faces           -- acoustic approximate Riemann solver (Sec. 2.1.2):
 //                         u*, Pi*, a >= max(rho c), interface gravity S_{i+1/2};
 //                         low-Mach factor theta of eq. (low_mach_correction).
@@ -710,10 +711,12 @@ double max_rate(const orc_config& c, const double* U) {
 #pragma omp parallel for schedule(static) reduction(max : m)
   for (long cell = 0; cell < G.ncell; ++cell) {
     Prim<double> q = cons_to_prim(c, G, U, cell);
-    double h = (std::fabs(q.u[0]) + q.c) * G.idx[0];
-    for (int d = 1; d < D; ++d) h = h + (std::fabs(q.u[d]) + q.c) * G.idx[d];
+    // dt_mode 2 (IMEX step): the sound speed leaves the rate
+    const double cs = (c.dt_mode == 2) ? 0.0 : q.c;
+    double h = (std::fabs(q.u[0]) + cs) * G.idx[0];
+    for (int d = 1; d < D; ++d) h = h + (std::fabs(q.u[d]) + cs) * G.idx[d];
     double l = h;
-    if (c.dt_mode == 0) l = h + (2.0 * (dmax * q.r)) * sumidx2;
+    if (c.dt_mode != 1) l = h + (2.0 * (dmax * q.r)) * sumidx2;
     if (!(l < std::numeric_limits<double>::infinity())) l = std::numeric_limits<double>::infinity();
     if (l > m) m = l;
   }
@@ -753,7 +756,7 @@ int orc_validate(const orc_config* c) {
   if (c->g != 0.0 && (c->bc[z][0] != BC_WALL || c->bc[z][1] != BC_WALL)) return ORC_EINVAL;
   if (!(c->gamma > 1.0) || !(c->mu >= 0.0) || !(c->kappa >= 0.0) || !(c->K >= 1.0) || !(c->cfl > 0.0))
     return ORC_EINVAL;
-  if (c->dt_mode != 0 && c->dt_mode != 1) return ORC_EINVAL;
+  if (c->dt_mode != 0 && c->dt_mode != 1 && c->dt_mode != 2) return ORC_EINVAL;
   if (c->energy_form != 0 && c->energy_form != 1) return ORC_EINVAL;
   return ORC_OK;
 }

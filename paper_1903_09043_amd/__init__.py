@@ -16,7 +16,7 @@ from . import workloads  # noqa: F401  (problem set-ups)
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libars.so")
 
-OK, EINVAL, ENOMEM, EDEVICE, ENONPHYS, EUNSUPPORTED, ESCRATCH = 0, -1, -2, -3, -4, -5, -6
+OK, EINVAL, ENOMEM, EDEVICE, ENONPHYS, EUNSUPPORTED, ESCRATCH, ENOCONV = 0, -1, -2, -3, -4, -5, -6, -7
 NOALLOC_MAX_STATE = 131072  # ARS_NOALLOC_MAX_STATE of include/ars.h
 TILE3_32x10, TILE3_16x20 = 0, 1
 BC_PERIODIC, BC_WALL, BC_OUTFLOW = 0, 1, 2
@@ -84,6 +84,9 @@ SIGNATURES = [
     ("ars_step_noalloc", C.c_int, [_VP, _VP, C.c_int, _VP, _VP, _VP, _VP]),
     ("ars_step_sched", C.c_int, [_VP, _VP, _VP, _VP, C.c_int, _VP, _VP, _VP]),
     ("ars_workspace_bytes_ref", C.c_size_t, [_VP]),
+    ("ars_workspace_bytes_imex", C.c_size_t, [_VP]),
+    ("ars_step_imex", C.c_int, [_VP, _VP, _VP, _VP, _VP, C.c_int, _VP, _VP, C.c_double, C.c_int,
+                                C.POINTER(C.c_int), _VP]),
     ("ars_step_ref", C.c_int, [_VP, _VP, _VP, _VP, _VP, C.c_int, _VP, _VP]),
     ("ars_workspace_bytes_adjoint", C.c_size_t, [_VP]),
     ("ars_step_adjoint", C.c_int, [_VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
@@ -274,6 +277,7 @@ class Solver:
         self.t = torch.zeros(1, dtype=torch.float64, device=self.device)
         self.dt = torch.zeros(1, dtype=torch.float64, device=self.device)
         self._wref = None
+        self._wimex = None
         _check(lib().ars_workspace_init(self.ctx.h, _ptr(self.work), self.stream), "ars_workspace_init")
 
     @property
@@ -365,6 +369,19 @@ class Solver:
         _check(lib().ars_step_ref(self.ctx.h, _ptr(self.U), _ptr(self.tmp), _ptr(self.work), _ptr(self._wref),
                                   dt_sched.numel(), _ptr(dt_sched), self.stream), "ars_step_ref")
         return self
+
+    def step_imex(self, dt_sched, tol=1e-13, max_iter=2000):
+        """Implicit acoustic steps (ars_step_imex), dt of step s =
+        dt_sched[s]; returns the total solver iterations."""
+        t = self.torch
+        dt_sched = t.as_tensor(dt_sched, dtype=t.float64).to(self.device).contiguous()
+        if self._wimex is None:
+            self._wimex = t.empty(lib().ars_workspace_bytes_imex(self.ctx.h), dtype=t.uint8, device=self.device)
+        its = C.c_int(0)
+        _check(lib().ars_step_imex(self.ctx.h, _ptr(self.U), _ptr(self.tmp), _ptr(self.work), _ptr(self._wimex),
+                                   int(dt_sched.numel()), _ptr(dt_sched), _ptr(self.t), float(tol), int(max_iter),
+                                   C.byref(its), self.stream), "ars_step_imex")
+        return its.value
 
     def adjoint_workspace(self):
         if getattr(self, "_wadj", None) is None:

@@ -16,7 +16,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libars.so")
 SOURCES = ["ars_api.hip", "ars_fused.hip", "ars_ref.hip", "ars_reduce.hip", "ars_adjoint.hip", "ars_revolve.hip",
-           "ars_batch.hip", "ars_tune.hip", "ars_spectrum.hip", "ars_noalloc.hip"]
+           "ars_batch.hip", "ars_tune.hip", "ars_spectrum.hip", "ars_noalloc.hip",
+           "ars_imex.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

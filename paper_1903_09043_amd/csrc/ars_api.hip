@@ -169,6 +169,7 @@ const char* ars_strerror(int s) {
     case ARS_ENONPHYS: return "non-physical state (rho, p or L not positive, or non-finite)";
     case ARS_EUNSUPPORTED: return "configuration not supported by this build";
     case ARS_ESCRATCH: return "state larger than the allocation-free scratch (ARS_NOALLOC_MAX_STATE doubles)";
+    case ARS_ENOCONV: return "implicit acoustic solve did not converge";
     default: return "unknown status";
   }
 }
@@ -192,7 +193,7 @@ int ars_validate(const ars_config* c) {
   if (!std::isfinite(c->g) || !std::isfinite(c->mu) || !std::isfinite(c->kappa) || !std::isfinite(c->K) ||
       !std::isfinite(c->cfl) || !std::isfinite(c->gamma))
     return ARS_EINVAL;
-  if (c->dt_mode != 0 && c->dt_mode != 1) return ARS_EINVAL;
+  if (c->dt_mode != 0 && c->dt_mode != 1 && c->dt_mode != 2) return ARS_EINVAL;
   if (c->energy_form != 0 && c->energy_form != 1) return ARS_EINVAL;
   if (c->low_mach != 0 && c->low_mach != 1) return ARS_EINVAL;
   for (int s = 0; s < 2; ++s)
@@ -492,6 +493,20 @@ int ars_step_sched(ars_ctx* ctx, double* d_state, double* d_tmp, void* d_work, i
       return ARS_EDEVICE;
   }
   return ARS_OK;
+}
+
+size_t ars_workspace_bytes_imex(const ars_ctx* c) { return c ? ars::imex_workspace_bytes(c->P) : 0; }
+
+int ars_step_imex(ars_ctx* ctx, double* d_state, double* d_tmp, void* d_work, void* d_work_imex, int n,
+                  const double* d_dt_sched, double* d_t, double tol, int max_iter, int* h_iters, void* stream) {
+  if (h_iters) *h_iters = 0;
+  if (!ctx || !d_state || !d_tmp || !d_work || !d_work_imex || !d_dt_sched || n < 0 || d_state == d_tmp ||
+      !(tol > 0.0) || max_iter < 1)
+    return ARS_EINVAL;
+  if (ctx->P.nc) return ARS_EUNSUPPORTED;
+  if (n == 0) return ARS_OK;
+  return ars::step_imex(ctx->P, d_state, d_tmp, ctl_of(d_work), d_work_imex, n, d_dt_sched, d_t, tol, max_iter,
+                        h_iters, (hipStream_t)stream);
 }
 
 int ars_step_ref(ars_ctx* ctx, double* d_state, double* d_tmp, void* d_work, void* d_work_ref, int n,

@@ -181,14 +181,17 @@ __device__ __forceinline__ void face_vert(const Params& P, const Prim<DIM>& L, c
 
 // Largest local rate of a cell for the CFL reduction (time-step kernel):
 // sum_d (|u_d| + c)/dx_d, plus 2 D sum_d dx_d^-2 with D = dmax / rho when
-// dt_mode == 0.  Non-finite rates count as +inf.
+// dt_mode == 0; dt_mode 1 drops the diffusive part, dt_mode 2 (for the
+// IMEX step, whose acoustic part is implicit) the sound speed.  Non-finite
+// rates count as +inf.
 template <int DIM>
 __device__ __forceinline__ double cell_rate(const Params& P, const Prim<DIM>& q) {
-  double h = (fabs(q.u[0]) + q.c) * P.idx[0];
-  if (DIM == 3) h = h + (fabs(q.u[1]) + q.c) * P.idx[1];
-  h = h + (fabs(q.u[DIM - 1]) + q.c) * P.idx[2];
+  const double cs = (P.dt_mode == 2) ? 0.0 : q.c;  // dt_mode 2 (IMEX step): no sound speed
+  double h = (fabs(q.u[0]) + cs) * P.idx[0];
+  if (DIM == 3) h = h + (fabs(q.u[1]) + cs) * P.idx[1];
+  h = h + (fabs(q.u[DIM - 1]) + cs) * P.idx[2];
   double l = h;
-  if (P.dt_mode == 0) l = h + (2.0 * (P.dmax * q.r)) * P.sumidx2;
+  if (P.dt_mode != 1) l = h + (2.0 * (P.dmax * q.r)) * P.sumidx2;
   if (!(l < __builtin_huge_val())) l = __builtin_huge_val();
   return l;
 }

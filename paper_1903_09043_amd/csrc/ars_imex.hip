@@ -1,0 +1,520 @@
+// ars_imex.hip -- implicit acoustic (IMEX) step of the all-regime scheme:
+// the further work the paper names in its Conclusion (solve the acoustic
+// part implicitly to lift the acoustic CFL condition, keeping the
+// well-balanced gravity source).  The paper prints no scheme; the reading:
+// Sec. 2.1.2's acoustic step with its interface values taken at the END of
+// the step (backward Euler on the linear relaxation system at frozen
+// a, S, theta of t^n).  Unknowns per interior cell i: Pi_i and the normal
+// velocities u_{d,i}; with lambda_d = dt / dx_d,
+//   u*_j  = (u_L + u_R)/2 - (Pi_R - Pi_L - S_j) / (2 a_j)       (0 at walls)
+//   Pi*_j = (Pi_L + Pi_R)/2 - (a_j theta_j / 2)(u_R - u_L)
+//   u_{d,i} = u^n_{d,i} - lambda_d tau_i ([Pi*]_{d,i} - S-bar_{d,i})
+//   Pi_i    = p_i - rho_i c_i^2 sum_d lambda_d [u*]_{d,i}
+// (the pressure row is the Lagrangian update linearised through the
+// equation of state).  Ghost cells take the boundary rules of the explicit
+// step applied to the unknowns (periodic images, outflow copies; at walls
+// Pi_g = Pi_i + (p_g - p_i)^n and the reflected velocity).  The implicit
+// (u*, Pi*) then replace the explicit ones in the acoustic cell values,
+// the transport, the update and the relaxation, which are the explicit
+// step's (the dissipative fluxes stay explicit).
+//
+// GPU layout: the reference step's padded workspace (primitives, explicit
+// faces for a, S, theta, then the implicit faces, L, b~, fluxes), padded
+// extensions of the unknowns, and the vectors of an unpreconditioned
+// BiCGSTAB on the (D+1) N unknowns.  The operator is applied matrix-free:
+// one kernel extends a vector to the ghost cells, one forms every row from
+// the two faces of each axis.  Dot products are two-level reductions in a
+// fixed order (deterministic); the iteration's scalars stay on the device
+// and the host reads the residual norm every few iterations.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <vector>
+
+#include "../../include/ars.h"
+#include "ars_dev.h"
+#include "ars_internal.h"
+#include "ars_ref.h"
+
+namespace ars {
+
+namespace {
+
+constexpr int DOT_BLOCKS = 1024;
+constexpr int BS = 256;
+// scalar slots of the iteration
+enum { SC_RHO_OLD = 0, SC_ALPHA, SC_OMEGA, SC_RHO_NEW, SC_RV, SC_TS, SC_TT, SC_RR, SC_BB, SC_N = 16 };
+
+struct ImexLayout {
+  RefGrid G;
+  long long n;      // unknowns (D + 1) N
+  double* W;        // reference workspace
+  double* ext;      // (D + 1) padded fields: Pi, u_0..u_{D-1}
+  double* x;        // solution
+  double* r;
+  double* rh;       // shadow residual
+  double* p;
+  double* v;
+  double* sv;
+  double* t;
+  double* b;
+  double* part;     // DOT_BLOCKS partial sums
+  double* sc;       // scalars
+};
+
+ImexLayout layout_of(const Params& P, void* work) {
+  ImexLayout L;
+  L.G = make_grid(P);
+  const int D = P.dim;
+  L.n = (long long)(D + 1) * P.ncell;
+  char* w = (char*)work;
+  size_t off = 0;
+  auto take = [&](size_t count) {
+    double* q = (double*)(w + off);
+    off += ((count * sizeof(double) + 255) / 256) * 256;
+    return q;
+  };
+  L.W = take((size_t)R_NFIELD * L.G.npad);
+  L.ext = take((size_t)(D + 1) * L.G.npad);
+  L.x = take(L.n);
+  L.r = take(L.n);
+  L.rh = take(L.n);
+  L.p = take(L.n);
+  L.v = take(L.n);
+  L.sv = take(L.n);
+  L.t = take(L.n);
+  L.b = take(L.n);
+  L.part = take(DOT_BLOCKS);
+  L.sc = take(SC_N);
+  return L;
+}
+
+__device__ __forceinline__ int comp_axis(int DIM, int a) { return a == 2 ? DIM - 1 : a; }
+
+// Padded extension of x (cst: with the wall ghosts' hydrostatic offset).
+template <int DIM>
+__global__ void k_imex_ext(Params P, RefGrid G, const double* __restrict__ W, const double* __restrict__ x, int cst,
+                           double* __restrict__ ext) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= G.npad) return;
+  int qx, qy, qz;
+  decode(G, i, qx, qy, qz);
+  const int cx = resolve_lat(qx - 2, P.nx, P.bcx);
+  const int cy = (DIM == 3) ? resolve_lat(qy - 2, P.ny, P.bcy) : 0;
+  int kz = qz - 2;
+  int ghost = -1;
+  if (kz < 0 || kz >= P.nz) {
+    const int side = kz < 0 ? 0 : 1;
+    if (P.bcz[side] == BC_WALL) {
+      ghost = side;
+      kz = side == 0 ? 0 : P.nz - 1;
+    } else {
+      kz = resolve_lat(kz, P.nz, P.bcz);
+    }
+  }
+  const long long N = P.ncell;
+  const long long cell = cx + (long long)P.nx * (cy + (long long)P.ny * kz);
+  const long long n = G.npad;
+  double Pi = x[cell];
+  if (ghost >= 0 && cst) {
+    const long long qi = G.pad(qx, qy, ghost == 0 ? 2 : P.nz + 1);
+    Pi = Pi + (W[R_P * n + i] - W[R_P * n + qi]);
+  }
+  ext[i] = Pi;
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) {
+    double u = x[(1 + k) * N + cell];
+    if (ghost >= 0 && (P.noslip || k == DIM - 1)) u = -u;
+    ext[(1 + k) * n + i] = u;
+  }
+}
+
+// Implicit u*, Pi* of face (a, l | l + e_a) (lz: vertical padded index of l).
+template <int DIM, bool LM>
+__device__ __forceinline__ void imex_face(const Params& P, const RefGrid& G, const double* __restrict__ W,
+                                          const double* __restrict__ ext, long long l, int lz, int a, int cst,
+                                          double& us, double& pi, double& S) {
+  const long long n = G.npad;
+  const long long r = l + astride(G, a);
+  const int k = comp_axis(DIM, a);
+  const double am = P.K * dmax2(W[R_RC * n + l], W[R_RC * n + r]);
+  const double h2a = P.hK * dmin2(W[R_IRC * n + l], W[R_IRC * n + r]);  // 1 / (2a)
+  double theta = 1.0;
+  if (LM) {
+    const double use = W[(R_FACE + 4 * a) * n + l];  // explicit u* of t^n
+    theta = dmin2(fabs(use) * dmin2(W[R_IC * n + l], W[R_IC * n + r]), 1.0);
+  }
+  S = (a == 2) ? W[(R_FACE + 4 * a + 3) * n + l] : 0.0;
+  const double uL = ext[(1 + k) * n + l], uR = ext[(1 + k) * n + r];
+  const double PL = ext[l], PR = ext[r];
+  const bool wall = ref_wall(P, a, lz);
+  us = wall ? 0.0 : 0.5 * (uL + uR) - ((PR - PL) - (cst ? S : 0.0)) * h2a;
+  pi = 0.5 * (PL + PR) - ((0.5 * am) * theta) * (uR - uL);
+}
+
+// Rows of the system at every interior cell: y = F(x) (cst) or its linear
+// part (cst = 0), from the padded extension of x.
+template <int DIM, bool LM>
+__global__ void k_imex_rows(Params P, RefGrid G, const double* __restrict__ W, const double* __restrict__ ext,
+                            const double* __restrict__ d_dt, const double* __restrict__ x, int cst,
+                            double* __restrict__ y) {
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= P.ncell) return;
+  const int cxx = (int)(c % P.nx);
+  const long long rr = c / P.nx;
+  const int cyy = (int)(rr % P.ny);
+  const int czz = (int)(rr / P.ny);
+  const long long q = G.pad(cxx + 2, DIM == 3 ? cyy + 2 : 0, czz + 2);
+  const long long n = G.npad, N = P.ncell;
+  const double dt = *d_dt;
+  const int axes[3] = {0, DIM == 3 ? 1 : 2, 2};
+  double div = 0.0;
+  double urow[3];
+#pragma unroll
+  for (int t = 0; t < DIM; ++t) {
+    const int a = axes[t];
+    const double lam = dt / P.dx[a];
+    double usp, pip, Sp, usm, pim, Sm;
+    imex_face<DIM, LM>(P, G, W, ext, q, czz + 2, a, cst, usp, pip, Sp);
+    imex_face<DIM, LM>(P, G, W, ext, q - astride(G, a), czz + 2 - (a == 2), a, cst, usm, pim, Sm);
+    div = div + lam * (usp - usm);
+    double dpi = pip - pim;
+    if (a == 2 && cst) dpi = dpi - 0.5 * (Sp + Sm);
+    const int k = comp_axis(DIM, a);
+    const double un = cst ? W[ufield(DIM, k) * n + q] : 0.0;
+    urow[k] = (x[(1 + k) * N + c] - un) + (lam * W[R_R * n + q]) * dpi;
+  }
+  const double rc2 = W[R_RC * n + q] * W[R_C * n + q];  // rho c^2
+  y[c] = (x[c] - (cst ? W[R_P * n + q] : 0.0)) + rc2 * div;
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) y[(1 + k) * N + c] = urow[k];
+}
+
+// Implicit faces of every padded face into the workspace (u*, Pi*, Pi* u*;
+// S and the explicit values of other faces untouched).
+template <int DIM, bool LM>
+__global__ void k_imex_faces(Params P, RefGrid G, double* __restrict__ W, const double* __restrict__ ext) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= G.npad) return;
+  int qx, qy, qz;
+  decode(G, i, qx, qy, qz);
+  const long long n = G.npad;
+  const int axes[3] = {0, DIM == 3 ? 1 : 2, 2};
+  double us[3], pi[3];
+  bool has[3];
+#pragma unroll
+  for (int t = 0; t < DIM; ++t) {
+    const int a = axes[t];
+    const int qa = a == 0 ? qx : (a == 1 ? qy : qz);
+    const int Pa = a == 0 ? G.Px : (a == 1 ? G.Py : G.Pz);
+    has[t] = qa + 1 < Pa;
+    us[t] = pi[t] = 0.0;
+    double S;
+    if (has[t]) imex_face<DIM, LM>(P, G, W, ext, i, qz, a, 1, us[t], pi[t], S);
+  }
+  // every thread reads only its own faces' explicit u*: safe to overwrite
+#pragma unroll
+  for (int t = 0; t < DIM; ++t) {
+    if (!has[t]) continue;
+    const int f = R_FACE + 4 * axes[t];
+    W[(f + 0) * n + i] = us[t];
+    W[(f + 1) * n + i] = pi[t];
+    W[(f + 2) * n + i] = pi[t] * us[t];
+  }
+}
+
+// Acoustic cell values L, S-bar, b~ (Sec. 2.1.2) from the stored faces.
+template <int DIM>
+__global__ void k_imex_cell(Params P, RefGrid G, const double* __restrict__ d_dt, double* __restrict__ W) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= G.npad) return;
+  constexpr int NV = DIM + 2;
+  int qx, qy, qz;
+  decode(G, i, qx, qy, qz);
+  const bool cell = qx >= 1 && qx < G.Px - 1 && qz >= 1 && qz < G.Pz - 1 && (DIM == 2 || (qy >= 1 && qy < G.Py - 1));
+  if (!cell) return;
+  const long long n = G.npad;
+  const double dt = *d_dt;
+  const int axes[3] = {0, DIM == 3 ? 1 : 2, 2};
+  double Lc = 1.0, Am[3], AE = 0.0;
+  const long long sz = astride(G, 2);
+  const double sb = 0.5 * (W[(R_FACE + 4 * 2 + 3) * n + i] + W[(R_FACE + 4 * 2 + 3) * n + i - sz]);
+#pragma unroll
+  for (int t = 0; t < DIM; ++t) {
+    const int a = axes[t];
+    const int f = R_FACE + 4 * a;
+    const long long m = i - astride(G, a);
+    const double lam = dt / P.dx[a];
+    Lc = Lc + lam * (W[f * n + i] - W[f * n + m]);
+    double dpi = W[(f + 1) * n + i] - W[(f + 1) * n + m];
+    if (a == 2) dpi = dpi - sb;
+    Am[t] = lam * dpi;
+    const double term = lam * (W[(f + 2) * n + i] - W[(f + 2) * n + m]);
+    AE = (t == 0) ? term : AE + term;
+  }
+  const double rho = W[R_CONS * n + i];
+  const double calE = W[(R_CONS + NV - 1) * n + i] + rho * phi_at(P, qz - 2);
+  const double iL = rcp_nr(Lc);
+  W[R_L * n + i] = Lc;
+  W[R_SB * n + i] = sb;
+  W[R_BT * n + i] = rho * iL;
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) W[(R_BT + 1 + k) * n + i] = (W[(R_CONS + 1 + k) * n + i] - Am[k]) * iL;
+  W[(R_BT + NV - 1) * n + i] = (calE - AE) * iL;
+}
+
+// ------------------------------------------------------------ BiCGSTAB ----
+__global__ void k_dot_partial(const double* __restrict__ a, const double* __restrict__ b, long long n,
+                              double* __restrict__ part) {
+  __shared__ double sh[BS];
+  double s = 0.0;
+  for (long long i = (long long)blockIdx.x * BS + threadIdx.x; i < n; i += (long long)gridDim.x * BS)
+    s = s + a[i] * b[i];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = BS / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] = sh[threadIdx.x] + sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ void k_dot_final(const double* __restrict__ part, int nb, double* __restrict__ out) {
+  __shared__ double sh[BS];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nb; i += BS) s = s + part[i];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = BS / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] = sh[threadIdx.x] + sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = sh[0];
+}
+
+// r = b - r (r holds A x on entry); rh = r; p = v = 0; scalars start.
+__global__ void k_bicg_start(long long n, const double* __restrict__ b, double* __restrict__ r, double* __restrict__ rh,
+                             double* __restrict__ p, double* __restrict__ v, double* __restrict__ sc) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) {
+    sc[SC_RHO_OLD] = 1.0;
+    sc[SC_ALPHA] = 1.0;
+    sc[SC_OMEGA] = 1.0;
+  }
+  if (i >= n) return;
+  const double ri = b[i] - r[i];
+  r[i] = ri;
+  rh[i] = ri;
+  p[i] = 0.0;
+  v[i] = 0.0;
+}
+
+// p = r + beta (p - omega v),  beta = (rho_new / rho_old) (alpha / omega)
+__global__ void k_bicg_p(long long n, const double* __restrict__ r, const double* __restrict__ v,
+                         double* __restrict__ p, const double* __restrict__ sc) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double beta = (sc[SC_RHO_NEW] / sc[SC_RHO_OLD]) * (sc[SC_ALPHA] / sc[SC_OMEGA]);
+  p[i] = r[i] + beta * (p[i] - sc[SC_OMEGA] * v[i]);
+}
+
+// s = r - alpha v,  alpha = rho_new / (rh, v)
+__global__ void k_bicg_s(long long n, const double* __restrict__ r, const double* __restrict__ v,
+                         double* __restrict__ s, double* __restrict__ sc) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const double alpha = sc[SC_RHO_NEW] / sc[SC_RV];
+  if (i >= n) return;
+  s[i] = r[i] - alpha * v[i];
+}
+
+// x += alpha p + omega s;  r = s - omega t;  omega = (t, s) / (t, t)
+__global__ void k_bicg_xr(long long n, const double* __restrict__ p, const double* __restrict__ s,
+                          const double* __restrict__ t, double* __restrict__ x, double* __restrict__ r,
+                          double* __restrict__ sc) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const double alpha = sc[SC_RHO_NEW] / sc[SC_RV];
+  const double omega = sc[SC_TT] > 0.0 ? sc[SC_TS] / sc[SC_TT] : 0.0;
+  if (i < n) {
+    x[i] = x[i] + alpha * p[i] + omega * s[i];
+    r[i] = s[i] - omega * t[i];
+  }
+}
+
+// alpha, omega and rho_old of this iteration for the next one's beta (a
+// kernel of its own: k_bicg_xr's threads read the previous values)
+__global__ void k_bicg_scalars(double* __restrict__ sc) {
+  if (threadIdx.x == 0) {
+    sc[SC_ALPHA] = sc[SC_RHO_NEW] / sc[SC_RV];
+    sc[SC_OMEGA] = sc[SC_TT] > 0.0 ? sc[SC_TS] / sc[SC_TT] : 0.0;
+    sc[SC_RHO_OLD] = sc[SC_RHO_NEW];
+  }
+}
+
+// x0 = (p^n, u^n) of every interior cell (the explicit state's values).
+template <int DIM>
+__global__ void k_imex_x0(Params P, RefGrid G, const double* __restrict__ W, double* __restrict__ x) {
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= P.ncell) return;
+  const int cxx = (int)(c % P.nx);
+  const long long rr = c / P.nx;
+  const int cyy = (int)(rr % P.ny);
+  const int czz = (int)(rr / P.ny);
+  const long long q = G.pad(cxx + 2, DIM == 3 ? cyy + 2 : 0, czz + 2);
+  const long long n = G.npad, N = P.ncell;
+  x[c] = W[R_P * n + q];
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) x[(1 + k) * N + c] = W[ufield(DIM, k) * n + q];
+}
+
+__global__ void k_fill0(long long n, double* __restrict__ a) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = 0.0;
+}
+
+__global__ void k_neg(long long n, double* __restrict__ a) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = -a[i];
+}
+
+__global__ void k_add_t(double* __restrict__ t, const double* __restrict__ dt) {
+  if (threadIdx.x == 0) *t = *t + *dt;
+}
+
+unsigned nblk(long long n) { return (unsigned)((n + BS - 1) / BS); }
+
+template <int DIM>
+struct Imex {
+  const Params& P;
+  ImexLayout L;
+  hipStream_t s;
+  const double* d_dt;
+
+  hipError_t apply(const double* xin, double* y, int cst) {
+    hipLaunchKernelGGL(k_imex_ext<DIM>, dim3(nblk(L.G.npad)), dim3(BS), 0, s, P, L.G, L.W, xin, cst, L.ext);
+    if (P.low_mach)
+      hipLaunchKernelGGL((k_imex_rows<DIM, true>), dim3(nblk(P.ncell)), dim3(BS), 0, s, P, L.G, L.W, L.ext, d_dt, xin,
+                         cst, y);
+    else
+      hipLaunchKernelGGL((k_imex_rows<DIM, false>), dim3(nblk(P.ncell)), dim3(BS), 0, s, P, L.G, L.W, L.ext, d_dt,
+                         xin, cst, y);
+    return hipGetLastError();
+  }
+  void dot(const double* a, const double* b, int slot) {
+    hipLaunchKernelGGL(k_dot_partial, dim3(DOT_BLOCKS), dim3(BS), 0, s, a, b, L.n, L.part);
+    hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(BS), 0, s, L.part, DOT_BLOCKS, L.sc + slot);
+  }
+  int read(int slot, double* h) {
+    if (hipMemcpyAsync(h, L.sc + slot, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess) return ARS_EDEVICE;
+    return hipStreamSynchronize(s) == hipSuccess ? ARS_OK : ARS_EDEVICE;
+  }
+
+  // Solve the implicit system of the state whose primitives and explicit
+  // faces are in the workspace; returns iterations in *its.
+  int solve(double tol, int max_iter, int* its) {
+    const unsigned nb = nblk(L.n);
+    // b = -F(0); x0 = explicit values; r = b - L x0
+    hipLaunchKernelGGL(k_fill0, dim3(nb), dim3(BS), 0, s, L.n, L.t);
+    if (apply(L.t, L.b, 1) != hipSuccess) return ARS_EDEVICE;
+    hipLaunchKernelGGL(k_neg, dim3(nb), dim3(BS), 0, s, L.n, L.b);
+    hipLaunchKernelGGL(k_imex_x0<DIM>, dim3(nblk(P.ncell)), dim3(BS), 0, s, P, L.G, L.W, L.x);
+    if (apply(L.x, L.r, 0) != hipSuccess) return ARS_EDEVICE;
+    hipLaunchKernelGGL(k_bicg_start, dim3(nb), dim3(BS), 0, s, L.n, L.b, L.r, L.rh, L.p, L.v, L.sc);
+    dot(L.b, L.b, SC_BB);
+    double bb = 0.0;
+    if (read(SC_BB, &bb) != ARS_OK) return ARS_EDEVICE;
+    const double target = tol * tol * (bb > 0.0 ? bb : 1.0);
+    int it = 0;
+    for (; it < max_iter; ++it) {
+      dot(L.rh, L.r, SC_RHO_NEW);
+      hipLaunchKernelGGL(k_bicg_p, dim3(nb), dim3(BS), 0, s, L.n, L.r, L.v, L.p, L.sc);
+      if (apply(L.p, L.v, 0) != hipSuccess) return ARS_EDEVICE;
+      dot(L.rh, L.v, SC_RV);
+      hipLaunchKernelGGL(k_bicg_s, dim3(nb), dim3(BS), 0, s, L.n, L.r, L.v, L.sv, L.sc);
+      if (apply(L.sv, L.t, 0) != hipSuccess) return ARS_EDEVICE;
+      dot(L.t, L.sv, SC_TS);
+      dot(L.t, L.t, SC_TT);
+      hipLaunchKernelGGL(k_bicg_xr, dim3(nb), dim3(BS), 0, s, L.n, L.p, L.sv, L.t, L.x, L.r, L.sc);
+      hipLaunchKernelGGL(k_bicg_scalars, dim3(1), dim3(64), 0, s, L.sc);
+      if (it % 4 == 3 || it + 1 == max_iter) {
+        dot(L.r, L.r, SC_RR);
+        double rr = 0.0;
+        if (read(SC_RR, &rr) != ARS_OK) return ARS_EDEVICE;
+        if (!std::isfinite(rr)) return ARS_ENOCONV;
+        if (rr <= target) {
+          ++it;
+          break;
+        }
+      }
+    }
+    if (its) *its = it;
+    if (it >= max_iter) {
+      double rr = 0.0;
+      if (read(SC_RR, &rr) != ARS_OK) return ARS_EDEVICE;
+      if (!(rr <= target)) return ARS_ENOCONV;
+    }
+    return hipGetLastError() == hipSuccess ? ARS_OK : ARS_EDEVICE;
+  }
+
+  // The rest of the step with the implicit faces of x.
+  hipError_t finish(double* Uout, Control* ctl) {
+    hipLaunchKernelGGL(k_imex_ext<DIM>, dim3(nblk(L.G.npad)), dim3(BS), 0, s, P, L.G, L.W, L.x, 1, L.ext);
+    if (P.low_mach)
+      hipLaunchKernelGGL((k_imex_faces<DIM, true>), dim3(nblk(L.G.npad)), dim3(BS), 0, s, P, L.G, L.W, L.ext);
+    else
+      hipLaunchKernelGGL((k_imex_faces<DIM, false>), dim3(nblk(L.G.npad)), dim3(BS), 0, s, P, L.G, L.W, L.ext);
+    hipLaunchKernelGGL(k_imex_cell<DIM>, dim3(nblk(L.G.npad)), dim3(BS), 0, s, P, L.G, d_dt, L.W);
+    if (hipGetLastError() != hipSuccess) return hipErrorUnknown;
+    return launch_ref_finish(P, L.W, Uout, d_dt, ctl, s);
+  }
+};
+
+}  // namespace
+
+size_t imex_workspace_bytes(const Params& P) {
+  RefGrid G = make_grid(P);
+  const long long n = (long long)(P.dim + 1) * P.ncell;
+  auto al = [](size_t b) { return ((b + 255) / 256) * 256; };
+  size_t s = al((size_t)R_NFIELD * G.npad * sizeof(double)) + al((size_t)(P.dim + 1) * G.npad * sizeof(double));
+  s += 8 * al((size_t)n * sizeof(double));
+  s += al(DOT_BLOCKS * sizeof(double)) + al(SC_N * sizeof(double));
+  return s;
+}
+
+template <int DIM>
+static int imex_steps(const Params& P, double* d_state, double* d_tmp, Control* ctl, void* wimex, int nsteps,
+                      const double* d_dt_sched, double* d_t, double tol, int max_iter, int* h_iters, hipStream_t s) {
+  Imex<DIM> M{P, layout_of(P, wimex), s, nullptr};
+  int total = 0;
+  double* src = d_state;
+  double* dst = d_tmp;
+  for (int st = 0; st < nsteps; ++st) {
+    M.d_dt = d_dt_sched + st;
+    if (launch_ref_forward(P, src, M.L.W, M.d_dt, s) != hipSuccess) return ARS_EDEVICE;
+    int its = 0;
+    const int rc = M.solve(tol, max_iter, &its);
+    total += its;
+    if (rc != ARS_OK) {
+      if (h_iters) *h_iters = total;
+      return rc;
+    }
+    if (M.finish(dst, ctl) != hipSuccess) return ARS_EDEVICE;
+    if (d_t) hipLaunchKernelGGL(k_add_t, dim3(1), dim3(64), 0, s, d_t, M.d_dt);
+    double* w = src;
+    src = dst;
+    dst = w;
+  }
+  if (src != d_state &&
+      hipMemcpyAsync(d_state, src, (size_t)(P.dim + 2) * P.ncell * sizeof(double), hipMemcpyDeviceToDevice, s) !=
+          hipSuccess)
+    return ARS_EDEVICE;
+  if (h_iters) *h_iters = total;
+  return hipGetLastError() == hipSuccess ? ARS_OK : ARS_EDEVICE;
+}
+
+int step_imex(const Params& P, double* d_state, double* d_tmp, Control* ctl, void* wimex, int nsteps,
+              const double* d_dt_sched, double* d_t, double tol, int max_iter, int* h_iters, hipStream_t s) {
+  return P.dim == 3 ? imex_steps<3>(P, d_state, d_tmp, ctl, wimex, nsteps, d_dt_sched, d_t, tol, max_iter, h_iters, s)
+                    : imex_steps<2>(P, d_state, d_tmp, ctl, wimex, nsteps, d_dt_sched, d_t, tol, max_iter, h_iters, s);
+}
+
+}  // namespace ars

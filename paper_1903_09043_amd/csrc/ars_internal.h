@@ -42,6 +42,14 @@ hipError_t launch_step_ref(const Params& P, const double* Uin, double* Uout, voi
                            Control* ctl, hipStream_t s);
 // forward phases only (primitives, faces, acoustic cell values) into wref
 hipError_t launch_ref_forward(const Params& P, const double* Uin, void* wref, const double* d_dt, hipStream_t s);
+// face fluxes and update from the faces and cell values in wref
+hipError_t launch_ref_finish(const Params& P, void* wref, double* Uout, const double* d_dt, Control* ctl,
+                             hipStream_t s);
+
+// Implicit acoustic (IMEX) step (ars_imex.hip).
+size_t imex_workspace_bytes(const Params& P);
+int step_imex(const Params& P, double* d_state, double* d_tmp, Control* ctl, void* wimex, int nsteps,
+              const double* d_dt_sched, double* d_t, double tol, int max_iter, int* h_iters, hipStream_t s);
 
 // Adjoint step (ars_adjoint.hip).
 size_t adjoint_workspace_bytes(const Params& P);

@@ -335,6 +335,31 @@ static hipError_t ref_forward_t(const Params& P, const double* Uin, void* wref, 
   return hipGetLastError();
 }
 
+// Fluxes and update from the faces and acoustic cell values already in wref.
+template <int DIM>
+static hipError_t ref_finish_t(const Params& P, void* wref, double* Uout, const double* d_dt, Control* ctl,
+                               hipStream_t s) {
+  RefGrid G = make_grid(P);
+  double* W = (double*)wref;
+  const int bs = 256;
+  const unsigned nb = (unsigned)((G.npad + bs - 1) / bs);
+  for (int a = 0; a < 3; ++a) {
+    if (DIM == 2 && a == 1) continue;
+    if (P.diss)
+      hipLaunchKernelGGL((k_ref_flux<DIM, true>), dim3(nb), dim3(bs), 0, s, P, G, a, W);
+    else
+      hipLaunchKernelGGL((k_ref_flux<DIM, false>), dim3(nb), dim3(bs), 0, s, P, G, a, W);
+  }
+  const unsigned nc = (unsigned)((P.ncell + bs - 1) / bs);
+  hipLaunchKernelGGL(k_ref_update<DIM>, dim3(nc), dim3(bs), 0, s, P, G, d_dt, W, Uout, ctl);
+  return hipGetLastError();
+}
+
+hipError_t launch_ref_finish(const Params& P, void* wref, double* Uout, const double* d_dt, Control* ctl,
+                             hipStream_t s) {
+  return P.dim == 3 ? ref_finish_t<3>(P, wref, Uout, d_dt, ctl, s) : ref_finish_t<2>(P, wref, Uout, d_dt, ctl, s);
+}
+
 hipError_t launch_ref_forward(const Params& P, const double* Uin, void* wref, const double* d_dt, hipStream_t s) {
   return P.dim == 3 ? ref_forward_t<3>(P, Uin, wref, d_dt, s) : ref_forward_t<2>(P, Uin, wref, d_dt, s);
 }
