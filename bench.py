@@ -179,6 +179,42 @@ def spectrum_leg(torch, S, n, reps=20):
                      "frac": round(flops / (ms * 1e-3) / 1e12 / FP64_MFMA_PEAK_TFS, 4)}}
 
 
+def imex_leg(torch, A, W, n=1024, Ma=1e-3, expl_steps=5000, tol=1e-10):
+    """Implicit acoustic (IMEX) steps against the explicit step on the low-
+    Mach workload (Gresho vortex n^2, Mach 1e-3, theta on): the explicit
+    step runs its 5000 CFL steps, the IMEX step reaches the same time with
+    the transport + diffusive CFL step (dt_mode 2, CFL 0.4: about 440 times
+    the acoustic one)."""
+    cfg, prob, prm, seed = W.gresho(n=n, Ma=Ma, low_mach=1)
+    E = A.Solver(cfg).init(prob, prm, seed)
+    d0 = E.diagnostics()
+    expl_ms = timed(torch, lambda: E.step(expl_steps))
+    t_end = E.t.item()
+    de = E.diagnostics()
+    S2 = A.Solver(dict(cfg, dt_mode=2)).init(prob, prm, seed)
+    dt_cfl = S2.dt.item()
+    nst = max(1, int(np.ceil(t_end / dt_cfl)))
+    sched = torch.full((nst,), t_end / nst, dtype=torch.float64, device="cuda")
+    S = A.Solver(cfg).init(prob, prm, seed)
+    its = {}
+
+    def run_imex():
+        its["n"] = S.step_imex(sched, tol=tol, max_iter=20000)
+    imex_ms = timed(torch, run_imex)
+    d = S.diagnostics()
+    iters = its["n"]
+    return {"workload": f"2D Gresho vortex {n}^2, Mach {Ma:g}, theta on, to t = {t_end:.6g}",
+            "explicit_steps": expl_steps, "explicit_ms": round(expl_ms, 2),
+            "imex_steps": nst, "imex_dt": t_end / nst, "acoustic_cfl": round(1.1 * (1.0 / Ma) * (t_end / nst) * n, 1),
+            "solver_iterations": iters, "iterations_per_step": round(iters / nst, 1),
+            "imex_ms": round(imex_ms, 2), "ms_per_iteration": round(imex_ms / max(iters, 1), 4),
+            "speedup_vs_explicit": round(expl_ms / imex_ms, 3),
+            "ke_ratio_imex": d["e_kin"] / d0["e_kin"], "ke_ratio_explicit": de["e_kin"] / d0["e_kin"],
+            "mass_drift_imex": (d["mass"] - d0["mass"]) / d0["mass"],
+            "energy_drift_imex": (d["e_total"] - d0["e_total"]) / d0["e_total"],
+            "unknowns": 3 * n * n}
+
+
 def adjoint_leg(torch, A, W, nsteps=200, slots=16, reps=20, end_to_end=True):
     """Adjoint/forward ratio on the 3D RB 128^3 workload: per step (one
     adjoint step vs one fused step, both warm, median of `reps`) and end to
@@ -332,8 +368,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-imex", action="store_true")
     ap.add_argument("--no-small", action="store_true", help="skip the cache-resident configs")
-    ap.add_argument("--only", choices=["adjoint", "adjoint-step", "batch", "batch-kernel"], default=None,
+    ap.add_argument("--only", choices=["adjoint", "adjoint-step", "batch", "batch-kernel", "imex"], default=None,
                     help="run one side leg alone (profiling); prints its JSON object")
     ap.add_argument("--zchunk", type=int, default=0)
     ap.add_argument("--mode", choices=["step", "copy"], default="step",
@@ -359,6 +396,9 @@ def main():
         return
     if args.only == "batch":
         print(json.dumps({"batch": batch_leg(torch, A, W)}), flush=True)
+        return
+    if args.only == "imex":
+        print(json.dumps({"imex": imex_leg(torch, A, W)}), flush=True)
         return
     if args.only == "batch-kernel":
         print(json.dumps({"batch": batch_leg(torch, A, W, loop=False)}), flush=True)
@@ -432,6 +472,8 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_batch:
         out["batch"] = batch_leg(torch, A, W)
+    if not args.no_imex:
+        out["imex"] = imex_leg(torch, A, W)
         torch.cuda.empty_cache()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()

@@ -246,10 +246,14 @@ int ars_step_sched(ars_ctx* ctx, double* d_state, double* d_tmp, void* d_work, i
  * interface values u*, Pi* taken at the end of the step (backward Euler on
  * the linear relaxation system at the frozen a, S and theta of t^n):
  *   u*_j  = (u_L + u_R)/2 - (Pi_R - Pi_L - S_j) / (2 a_j)    (0 at walls)
- *   Pi*_j = (Pi_L + Pi_R)/2 - (a_j theta_j / 2)(u_R - u_L)
+ *   Pi*_j = (Pi_L + Pi_R)/2 - (a_j theta_j / 2)(u^n_R - u^n_L)
  *   u_{d,i} = u^n_{d,i} - (dt/dx_d) tau_i ([Pi*]_{d,i} - S-bar_{d,i})
  *   Pi_i    = p_i - rho_i c_i^2 sum_d (dt/dx_d) [u*]_{d,i}
- * solved for (Pi, u) by BiCGSTAB to ||residual|| <= tol ||rhs||; the
+ * u is eliminated (its rows are explicit in Pi) and the system for Pi,
+ * rows scaled by 1 / (rho c^2), is solved by BiCGSTAB to a relative
+ * residual tol.  The acoustic dissipation of Pi* acts on u^n: with the
+ * low-Mach correction (theta ~ Ma) steps far above the acoustic limit are
+ * stable, without it (theta = 1) only steps near it.  The
  * implicit (u*, Pi*) then enter the acoustic cell values, transport,
  * update and relaxation of eq. all_regime_scheme as in ars_step.  Dissipative
  * fluxes stay explicit.  dt of step s = d_dt_sched[s] (device); with

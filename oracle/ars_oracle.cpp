@@ -547,9 +547,15 @@ int step_impl(const orc_config& c, const S* U, S* Uout, double dt, S mu, S kappa
 // p_i, c_i, and the hydrostatic offset p_g - p_i of every wall ghost.  With
 // lambda_d = dt / dx_d:
 //   u*_j  = (u_L + u_R)/2 - (Pi_R - Pi_L - S_j) / (2 a_j)       (0 at walls)
-//   Pi*_j = (Pi_L + Pi_R)/2 - (a_j theta_j / 2)(u_R - u_L)
+//   Pi*_j = (Pi_L + Pi_R)/2 - (a_j theta_j / 2)(u^n_R - u^n_L)
 //   u_{d,i} = u^n_{d,i} - lambda_d tau_i ([Pi*]_{d,i} - S-bar_{d,i})
 //   Pi_i    = p_i - rho_i c_i^2 sum_d lambda_d [u*]_{d,i}
+// The acoustic dissipation of Pi* acts on the velocities of t^n (it is a
+// diffusion of u with coefficient a theta / 2: with the low-Mach correction
+// theta ~ |u*| / c its stability limit is a transport one, without it an
+// acoustic one), so the velocity rows have the identity in u and u can be
+// eliminated: the system for Pi alone is symmetric after scaling its rows
+// by 1 / (rho c^2) (with periodic and wall boundaries).
 // The last line is the Lagrangian pressure update linearised through the
 // equation of state (dp = -rho c^2 dtau / tau, c^2 = gamma p / rho), the
 // implicit counterpart of the relaxation Pi~ = p_EOS of Sec. 2.1.2.
@@ -604,9 +610,9 @@ void imex_extend(const orc_config& c, const Grid& G, const State<double>& st, co
 }
 
 // Implicit interface values of every padded face from the extension.
-void imex_faces(const orc_config& c, const Grid& G, const StepArrays<double>& A, const std::vector<double>& Pp,
-                const std::vector<double> up[3], bool with_const, std::vector<double> us[3],
-                std::vector<double> pis[3]) {
+void imex_faces(const orc_config& c, const Grid& G, const State<double>& st, const StepArrays<double>& A,
+                const std::vector<double>& Pp, const std::vector<double> up[3], bool with_const,
+                std::vector<double> us[3], std::vector<double> pis[3]) {
   const int D = G.D;
   long stride[3] = {1, (long)G.P[0], (long)G.P[0] * G.P[1]};
   for (int d = 0; d < D; ++d) {
@@ -622,7 +628,9 @@ void imex_faces(const orc_config& c, const Grid& G, const StepArrays<double>& A,
           const double uL = up[d][p], uR = up[d][pr], PL = Pp[p], PR = Pp[pr];
           const double Sj = with_const ? f.S_ : 0.0;
           us[d][p] = A.wall[d][p] ? 0.0 : 0.5 * (uL + uR) - ((PR - PL) - Sj) / (2.0 * f.a);
-          pis[d][p] = 0.5 * (PL + PR) - ((0.5 * f.a) * f.theta) * (uR - uL);
+          // the acoustic dissipation of Pi* acts on the velocities of t^n
+          const double dun = st.prim[pr].u[d] - st.prim[p].u[d];
+          pis[d][p] = 0.5 * (PL + PR) - (with_const ? ((0.5 * f.a) * f.theta) * dun : 0.0);
         }
   }
 }
@@ -663,7 +671,7 @@ void imex_residual(const orc_config& c, const ImexFrozen& F, double dt, const do
   long stride[3] = {1, (long)G.P[0], (long)G.P[0] * G.P[1]};
   std::vector<double> Pp, up[3], us[3], pis[3];
   imex_extend(c, G, F.st, x, with_const, Pp, up);
-  imex_faces(c, G, F.A, Pp, up, with_const, us, pis);
+  imex_faces(c, G, F.st, F.A, Pp, up, with_const, us, pis);
   for (int k = 0; k < G.n[2]; ++k)
     for (int j = 0; j < G.n[1]; ++j)
       for (int i = 0; i < G.n[0]; ++i) {
@@ -689,7 +697,7 @@ void imex_override(const orc_config& c, const Grid& G, const State<S>& st, StepA
   if constexpr (std::is_same<S, double>::value) {
     std::vector<double> Pp, up[3], us[3], pis[3];
     imex_extend(c, G, st, x, true, Pp, up);
-    imex_faces(c, G, A, Pp, up, true, us, pis);
+    imex_faces(c, G, st, A, Pp, up, true, us, pis);
     for (int d = 0; d < G.D; ++d)
       for (long p = 0; p < G.npad; ++p) {
         A.face[d][p].ustar = us[d][p];

@@ -7,11 +7,13 @@
 // a, S, theta of t^n).  Unknowns per interior cell i: Pi_i and the normal
 // velocities u_{d,i}; with lambda_d = dt / dx_d,
 //   u*_j  = (u_L + u_R)/2 - (Pi_R - Pi_L - S_j) / (2 a_j)       (0 at walls)
-//   Pi*_j = (Pi_L + Pi_R)/2 - (a_j theta_j / 2)(u_R - u_L)
+//   Pi*_j = (Pi_L + Pi_R)/2 - (a_j theta_j / 2)(u^n_R - u^n_L)
 //   u_{d,i} = u^n_{d,i} - lambda_d tau_i ([Pi*]_{d,i} - S-bar_{d,i})
 //   Pi_i    = p_i - rho_i c_i^2 sum_d lambda_d [u*]_{d,i}
 // (the pressure row is the Lagrangian update linearised through the
-// equation of state).  Ghost cells take the boundary rules of the explicit
+// equation of state; the acoustic dissipation of Pi* acts on u^n, so the
+// velocity rows are explicit in Pi and u is eliminated: the system is for
+// Pi alone, its rows scaled by 1 / (rho c^2)).  Ghost cells take the boundary rules of the explicit
 // step applied to the unknowns (periodic images, outflow copies; at walls
 // Pi_g = Pi_i + (p_g - p_i)^n and the reflected velocity).  The implicit
 // (u*, Pi*) then replace the explicit ones in the acoustic cell values,
@@ -20,10 +22,12 @@
 //
 // GPU layout: the reference step's padded workspace (primitives, explicit
 // faces for a, S, theta, then the implicit faces, L, b~, fluxes), padded
-// extensions of the unknowns, and the vectors of an unpreconditioned
-// BiCGSTAB on the (D+1) N unknowns.  The operator is applied matrix-free:
-// one kernel extends a vector to the ghost cells, one forms every row from
-// the two faces of each axis.  Dot products are two-level reductions in a
+// extensions of Pi and of the velocities it gives, and the vectors of an
+// unpreconditioned BiCGSTAB on the N unknowns Pi.  The operator is applied
+// matrix-free: one kernel extends Pi to the ghost cells, one forms the
+// velocities of every padded cell from the Pi* of its two faces per axis
+// (ghosts by the boundary rules), one forms every row from the u* of the
+// two faces of each axis.  Dot products are two-level reductions in a
 // fixed order (deterministic); the iteration's scalars stay on the device
 // and the host reads the residual norm every few iterations.
 #include <hip/hip_runtime.h>
@@ -47,7 +51,7 @@ enum { SC_RHO_OLD = 0, SC_ALPHA, SC_OMEGA, SC_RHO_NEW, SC_RV, SC_TS, SC_TT, SC_R
 
 struct ImexLayout {
   RefGrid G;
-  long long n;      // unknowns (D + 1) N
+  long long n;      // unknowns: Pi of every interior cell
   double* W;        // reference workspace
   double* ext;      // (D + 1) padded fields: Pi, u_0..u_{D-1}
   double* x;        // solution
@@ -66,7 +70,7 @@ ImexLayout layout_of(const Params& P, void* work) {
   ImexLayout L;
   L.G = make_grid(P);
   const int D = P.dim;
-  L.n = (long long)(D + 1) * P.ncell;
+  L.n = P.ncell;
   char* w = (char*)work;
   size_t off = 0;
   auto take = [&](size_t count) {
@@ -91,73 +95,116 @@ ImexLayout layout_of(const Params& P, void* work) {
 
 __device__ __forceinline__ int comp_axis(int DIM, int a) { return a == 2 ? DIM - 1 : a; }
 
-// Padded extension of x (cst: with the wall ghosts' hydrostatic offset).
+// Interior source cell of a padded cell (periodic image, outflow copy, or
+// the interior neighbour of a wall ghost: wall = 0 bottom, 1 top, -1 none).
 template <int DIM>
-__global__ void k_imex_ext(Params P, RefGrid G, const double* __restrict__ W, const double* __restrict__ x, int cst,
-                           double* __restrict__ ext) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= G.npad) return;
-  int qx, qy, qz;
-  decode(G, i, qx, qy, qz);
-  const int cx = resolve_lat(qx - 2, P.nx, P.bcx);
-  const int cy = (DIM == 3) ? resolve_lat(qy - 2, P.ny, P.bcy) : 0;
-  int kz = qz - 2;
-  int ghost = -1;
+__device__ __forceinline__ void source_cell(const Params& P, int qx, int qy, int qz, int& cx, int& cy, int& kz,
+                                            int& wall) {
+  cx = resolve_lat(qx - 2, P.nx, P.bcx);
+  cy = (DIM == 3) ? resolve_lat(qy - 2, P.ny, P.bcy) : 0;
+  kz = qz - 2;
+  wall = -1;
   if (kz < 0 || kz >= P.nz) {
     const int side = kz < 0 ? 0 : 1;
     if (P.bcz[side] == BC_WALL) {
-      ghost = side;
+      wall = side;
       kz = side == 0 ? 0 : P.nz - 1;
     } else {
       kz = resolve_lat(kz, P.nz, P.bcz);
     }
   }
-  const long long N = P.ncell;
-  const long long cell = cx + (long long)P.nx * (cy + (long long)P.ny * kz);
+}
+
+// Padded extension of Pi (cst: with the wall ghosts' hydrostatic offset).
+template <int DIM>
+__global__ void k_schur_extP(Params P, RefGrid G, const double* __restrict__ W, const double* __restrict__ x, int cst,
+                             double* __restrict__ ext) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= G.npad) return;
+  int qx, qy, qz, cx, cy, kz, wall;
+  decode(G, i, qx, qy, qz);
+  source_cell<DIM>(P, qx, qy, qz, cx, cy, kz, wall);
   const long long n = G.npad;
-  double Pi = x[cell];
-  if (ghost >= 0 && cst) {
-    const long long qi = G.pad(qx, qy, ghost == 0 ? 2 : P.nz + 1);
+  double Pi = x[cx + (long long)P.nx * (cy + (long long)P.ny * kz)];
+  if (wall >= 0 && cst) {
+    const long long qi = G.pad(qx, qy, wall == 0 ? 2 : P.nz + 1);
     Pi = Pi + (W[R_P * n + i] - W[R_P * n + qi]);
   }
   ext[i] = Pi;
-#pragma unroll
-  for (int k = 0; k < DIM; ++k) {
-    double u = x[(1 + k) * N + cell];
-    if (ghost >= 0 && (P.noslip || k == DIM - 1)) u = -u;
-    ext[(1 + k) * n + i] = u;
-  }
 }
 
-// Implicit u*, Pi* of face (a, l | l + e_a) (lz: vertical padded index of l).
+// Acoustic dissipation term of Pi* on face (a, l | l + e_a), on the
+// velocities of t^n: (a_j theta_j / 2)(u^n_R - u^n_L).
 template <int DIM, bool LM>
-__device__ __forceinline__ void imex_face(const Params& P, const RefGrid& G, const double* __restrict__ W,
-                                          const double* __restrict__ ext, long long l, int lz, int a, int cst,
-                                          double& us, double& pi, double& S) {
+__device__ __forceinline__ double dissip_n(const Params& P, const RefGrid& G, const double* __restrict__ W,
+                                           long long l, int a) {
   const long long n = G.npad;
   const long long r = l + astride(G, a);
-  const int k = comp_axis(DIM, a);
   const double am = P.K * dmax2(W[R_RC * n + l], W[R_RC * n + r]);
-  const double h2a = P.hK * dmin2(W[R_IRC * n + l], W[R_IRC * n + r]);  // 1 / (2a)
   double theta = 1.0;
   if (LM) {
     const double use = W[(R_FACE + 4 * a) * n + l];  // explicit u* of t^n
     theta = dmin2(fabs(use) * dmin2(W[R_IC * n + l], W[R_IC * n + r]), 1.0);
   }
-  S = (a == 2) ? W[(R_FACE + 4 * a + 3) * n + l] : 0.0;
-  const double uL = ext[(1 + k) * n + l], uR = ext[(1 + k) * n + r];
-  const double PL = ext[l], PR = ext[r];
-  const bool wall = ref_wall(P, a, lz);
-  us = wall ? 0.0 : 0.5 * (uL + uR) - ((PR - PL) - (cst ? S : 0.0)) * h2a;
-  pi = 0.5 * (PL + PR) - ((0.5 * am) * theta) * (uR - uL);
+  const int uf = ufield(DIM, a == 2 ? DIM - 1 : a);
+  return ((0.5 * am) * theta) * (W[uf * n + r] - W[uf * n + l]);
 }
 
-// Rows of the system at every interior cell: y = F(x) (cst) or its linear
-// part (cst = 0), from the padded extension of x.
+// Velocities of every padded cell from Pi (its source cell's velocity
+// rows, then the ghost rule): u = cst u^n - lambda tau ([Pi*] - cst S-bar).
 template <int DIM, bool LM>
-__global__ void k_imex_rows(Params P, RefGrid G, const double* __restrict__ W, const double* __restrict__ ext,
-                            const double* __restrict__ d_dt, const double* __restrict__ x, int cst,
-                            double* __restrict__ y) {
+__global__ void k_schur_u(Params P, RefGrid G, const double* __restrict__ W, const double* __restrict__ d_dt, int cst,
+                          double* __restrict__ ext) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= G.npad) return;
+  int qx, qy, qz, cx, cy, kz, wall;
+  decode(G, i, qx, qy, qz);
+  source_cell<DIM>(P, qx, qy, qz, cx, cy, kz, wall);
+  const long long n = G.npad;
+  const long long q = G.pad(cx + 2, DIM == 3 ? cy + 2 : 0, kz + 2);  // padded index of the source cell
+  const double dt = *d_dt;
+  const int axes[3] = {0, DIM == 3 ? 1 : 2, 2};
+#pragma unroll
+  for (int t = 0; t < DIM; ++t) {
+    const int a = axes[t];
+    const long long e = astride(G, a);
+    double pp = 0.5 * (ext[q] + ext[q + e]);
+    double pm = 0.5 * (ext[q - e] + ext[q]);
+    double dpi;
+    if (cst) {
+      pp = pp - dissip_n<DIM, LM>(P, G, W, q, a);
+      pm = pm - dissip_n<DIM, LM>(P, G, W, q - e, a);
+      dpi = pp - pm;
+      if (a == 2) dpi = dpi - 0.5 * (W[(R_FACE + 4 * a + 3) * n + q] + W[(R_FACE + 4 * a + 3) * n + q - e]);
+    } else {
+      dpi = pp - pm;
+    }
+    const int k = comp_axis(DIM, a);
+    double u = (cst ? W[ufield(DIM, k) * n + q] : 0.0) - ((dt / P.dx[a]) * W[R_R * n + q]) * dpi;
+    if (wall >= 0 && (P.noslip || k == DIM - 1)) u = -u;
+    ext[(1 + k) * n + i] = u;
+  }
+}
+
+// Implicit u* of face (a, l | l + e_a) from the extensions.
+template <int DIM>
+__device__ __forceinline__ double ustar_imp(const Params& P, const RefGrid& G, const double* __restrict__ W,
+                                            const double* __restrict__ ext, long long l, int lz, int a, int cst) {
+  if (ref_wall(P, a, lz)) return 0.0;
+  const long long n = G.npad;
+  const long long r = l + astride(G, a);
+  const int k = comp_axis(DIM, a);
+  const double h2a = P.hK * dmin2(W[R_IRC * n + l], W[R_IRC * n + r]);  // 1 / (2a)
+  const double S = (a == 2 && cst) ? W[(R_FACE + 4 * a + 3) * n + l] : 0.0;
+  return 0.5 * (ext[(1 + k) * n + l] + ext[(1 + k) * n + r]) - ((ext[r] - ext[l]) - S) * h2a;
+}
+
+// Rows of the system for Pi at every interior cell, scaled by 1/(rho c^2):
+// y = (Pi - cst p) / (rho c^2) + sum_d lambda_d [u*]_d.
+template <int DIM>
+__global__ void k_schur_rows(Params P, RefGrid G, const double* __restrict__ W, const double* __restrict__ ext,
+                             const double* __restrict__ d_dt, const double* __restrict__ x, int cst,
+                             double* __restrict__ y) {
   const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= P.ncell) return;
   const int cxx = (int)(c % P.nx);
@@ -165,33 +212,24 @@ __global__ void k_imex_rows(Params P, RefGrid G, const double* __restrict__ W, c
   const int cyy = (int)(rr % P.ny);
   const int czz = (int)(rr / P.ny);
   const long long q = G.pad(cxx + 2, DIM == 3 ? cyy + 2 : 0, czz + 2);
-  const long long n = G.npad, N = P.ncell;
+  const long long n = G.npad;
   const double dt = *d_dt;
   const int axes[3] = {0, DIM == 3 ? 1 : 2, 2};
   double div = 0.0;
-  double urow[3];
 #pragma unroll
   for (int t = 0; t < DIM; ++t) {
     const int a = axes[t];
-    const double lam = dt / P.dx[a];
-    double usp, pip, Sp, usm, pim, Sm;
-    imex_face<DIM, LM>(P, G, W, ext, q, czz + 2, a, cst, usp, pip, Sp);
-    imex_face<DIM, LM>(P, G, W, ext, q - astride(G, a), czz + 2 - (a == 2), a, cst, usm, pim, Sm);
-    div = div + lam * (usp - usm);
-    double dpi = pip - pim;
-    if (a == 2 && cst) dpi = dpi - 0.5 * (Sp + Sm);
-    const int k = comp_axis(DIM, a);
-    const double un = cst ? W[ufield(DIM, k) * n + q] : 0.0;
-    urow[k] = (x[(1 + k) * N + c] - un) + (lam * W[R_R * n + q]) * dpi;
+    const double usp = ustar_imp<DIM>(P, G, W, ext, q, czz + 2, a, cst);
+    const double usm = ustar_imp<DIM>(P, G, W, ext, q - astride(G, a), czz + 2 - (a == 2), a, cst);
+    div = div + (dt / P.dx[a]) * (usp - usm);
   }
   const double rc2 = W[R_RC * n + q] * W[R_C * n + q];  // rho c^2
-  y[c] = (x[c] - (cst ? W[R_P * n + q] : 0.0)) + rc2 * div;
-#pragma unroll
-  for (int k = 0; k < DIM; ++k) y[(1 + k) * N + c] = urow[k];
+  y[c] = (x[c] - (cst ? W[R_P * n + q] : 0.0)) / rc2 + div;
 }
 
 // Implicit faces of every padded face into the workspace (u*, Pi*, Pi* u*;
-// S and the explicit values of other faces untouched).
+// S untouched); every thread reads only its own faces' explicit u* (for
+// theta) before overwriting them.
 template <int DIM, bool LM>
 __global__ void k_imex_faces(Params P, RefGrid G, double* __restrict__ W, const double* __restrict__ ext) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -209,10 +247,11 @@ __global__ void k_imex_faces(Params P, RefGrid G, double* __restrict__ W, const 
     const int Pa = a == 0 ? G.Px : (a == 1 ? G.Py : G.Pz);
     has[t] = qa + 1 < Pa;
     us[t] = pi[t] = 0.0;
-    double S;
-    if (has[t]) imex_face<DIM, LM>(P, G, W, ext, i, qz, a, 1, us[t], pi[t], S);
+    if (has[t]) {
+      us[t] = ustar_imp<DIM>(P, G, W, ext, i, qz, a, 1);
+      pi[t] = 0.5 * (ext[i] + ext[i + astride(G, a)]) - dissip_n<DIM, LM>(P, G, W, i, a);
+    }
   }
-  // every thread reads only its own faces' explicit u*: safe to overwrite
 #pragma unroll
   for (int t = 0; t < DIM; ++t) {
     if (!has[t]) continue;
@@ -314,15 +353,21 @@ __global__ void k_bicg_p(long long n, const double* __restrict__ r, const double
                          double* __restrict__ p, const double* __restrict__ sc) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const double beta = (sc[SC_RHO_NEW] / sc[SC_RHO_OLD]) * (sc[SC_ALPHA] / sc[SC_OMEGA]);
+  const double den = sc[SC_RHO_OLD] * sc[SC_OMEGA];
+  const double beta = den != 0.0 ? (sc[SC_RHO_NEW] * sc[SC_ALPHA]) / den : 0.0;
   p[i] = r[i] + beta * (p[i] - sc[SC_OMEGA] * v[i]);
 }
 
-// s = r - alpha v,  alpha = rho_new / (rh, v)
+// alpha = rho_new / (rh, v), 0 at a breakdown
+__device__ __forceinline__ double bicg_alpha(const double* sc) {
+  return sc[SC_RV] != 0.0 ? sc[SC_RHO_NEW] / sc[SC_RV] : 0.0;
+}
+
+// s = r - alpha v
 __global__ void k_bicg_s(long long n, const double* __restrict__ r, const double* __restrict__ v,
                          double* __restrict__ s, double* __restrict__ sc) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const double alpha = sc[SC_RHO_NEW] / sc[SC_RV];
+  const double alpha = bicg_alpha(sc);
   if (i >= n) return;
   s[i] = r[i] - alpha * v[i];
 }
@@ -332,7 +377,7 @@ __global__ void k_bicg_xr(long long n, const double* __restrict__ p, const doubl
                           const double* __restrict__ t, double* __restrict__ x, double* __restrict__ r,
                           double* __restrict__ sc) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const double alpha = sc[SC_RHO_NEW] / sc[SC_RV];
+  const double alpha = bicg_alpha(sc);
   const double omega = sc[SC_TT] > 0.0 ? sc[SC_TS] / sc[SC_TT] : 0.0;
   if (i < n) {
     x[i] = x[i] + alpha * p[i] + omega * s[i];
@@ -344,13 +389,13 @@ __global__ void k_bicg_xr(long long n, const double* __restrict__ p, const doubl
 // kernel of its own: k_bicg_xr's threads read the previous values)
 __global__ void k_bicg_scalars(double* __restrict__ sc) {
   if (threadIdx.x == 0) {
-    sc[SC_ALPHA] = sc[SC_RHO_NEW] / sc[SC_RV];
+    sc[SC_ALPHA] = bicg_alpha(sc);
     sc[SC_OMEGA] = sc[SC_TT] > 0.0 ? sc[SC_TS] / sc[SC_TT] : 0.0;
     sc[SC_RHO_OLD] = sc[SC_RHO_NEW];
   }
 }
 
-// x0 = (p^n, u^n) of every interior cell (the explicit state's values).
+// x0 = p^n of every interior cell.
 template <int DIM>
 __global__ void k_imex_x0(Params P, RefGrid G, const double* __restrict__ W, double* __restrict__ x) {
   const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -359,11 +404,7 @@ __global__ void k_imex_x0(Params P, RefGrid G, const double* __restrict__ W, dou
   const long long rr = c / P.nx;
   const int cyy = (int)(rr % P.ny);
   const int czz = (int)(rr / P.ny);
-  const long long q = G.pad(cxx + 2, DIM == 3 ? cyy + 2 : 0, czz + 2);
-  const long long n = G.npad, N = P.ncell;
-  x[c] = W[R_P * n + q];
-#pragma unroll
-  for (int k = 0; k < DIM; ++k) x[(1 + k) * N + c] = W[ufield(DIM, k) * n + q];
+  x[c] = W[R_P * G.npad + G.pad(cxx + 2, DIM == 3 ? cyy + 2 : 0, czz + 2)];
 }
 
 __global__ void k_fill0(long long n, double* __restrict__ a) {
@@ -390,13 +431,13 @@ struct Imex {
   const double* d_dt;
 
   hipError_t apply(const double* xin, double* y, int cst) {
-    hipLaunchKernelGGL(k_imex_ext<DIM>, dim3(nblk(L.G.npad)), dim3(BS), 0, s, P, L.G, L.W, xin, cst, L.ext);
+    const unsigned np = nblk(L.G.npad);
+    hipLaunchKernelGGL(k_schur_extP<DIM>, dim3(np), dim3(BS), 0, s, P, L.G, L.W, xin, cst, L.ext);
     if (P.low_mach)
-      hipLaunchKernelGGL((k_imex_rows<DIM, true>), dim3(nblk(P.ncell)), dim3(BS), 0, s, P, L.G, L.W, L.ext, d_dt, xin,
-                         cst, y);
+      hipLaunchKernelGGL((k_schur_u<DIM, true>), dim3(np), dim3(BS), 0, s, P, L.G, L.W, d_dt, cst, L.ext);
     else
-      hipLaunchKernelGGL((k_imex_rows<DIM, false>), dim3(nblk(P.ncell)), dim3(BS), 0, s, P, L.G, L.W, L.ext, d_dt,
-                         xin, cst, y);
+      hipLaunchKernelGGL((k_schur_u<DIM, false>), dim3(np), dim3(BS), 0, s, P, L.G, L.W, d_dt, cst, L.ext);
+    hipLaunchKernelGGL(k_schur_rows<DIM>, dim3(nblk(P.ncell)), dim3(BS), 0, s, P, L.G, L.W, L.ext, d_dt, xin, cst, y);
     return hipGetLastError();
   }
   void dot(const double* a, const double* b, int slot) {
@@ -423,6 +464,15 @@ struct Imex {
     double bb = 0.0;
     if (read(SC_BB, &bb) != ARS_OK) return ARS_EDEVICE;
     const double target = tol * tol * (bb > 0.0 ? bb : 1.0);
+    // the explicit pressure may already solve the system (an equilibrium)
+    dot(L.r, L.r, SC_RR);
+    double rr0 = 0.0;
+    if (read(SC_RR, &rr0) != ARS_OK) return ARS_EDEVICE;
+    if (!std::isfinite(rr0)) return ARS_ENOCONV;
+    if (rr0 <= target) {
+      if (its) *its = 0;
+      return ARS_OK;
+    }
     int it = 0;
     for (; it < max_iter; ++it) {
       dot(L.rh, L.r, SC_RHO_NEW);
@@ -457,12 +507,16 @@ struct Imex {
 
   // The rest of the step with the implicit faces of x.
   hipError_t finish(double* Uout, Control* ctl) {
-    hipLaunchKernelGGL(k_imex_ext<DIM>, dim3(nblk(L.G.npad)), dim3(BS), 0, s, P, L.G, L.W, L.x, 1, L.ext);
-    if (P.low_mach)
-      hipLaunchKernelGGL((k_imex_faces<DIM, true>), dim3(nblk(L.G.npad)), dim3(BS), 0, s, P, L.G, L.W, L.ext);
-    else
-      hipLaunchKernelGGL((k_imex_faces<DIM, false>), dim3(nblk(L.G.npad)), dim3(BS), 0, s, P, L.G, L.W, L.ext);
-    hipLaunchKernelGGL(k_imex_cell<DIM>, dim3(nblk(L.G.npad)), dim3(BS), 0, s, P, L.G, d_dt, L.W);
+    const unsigned np = nblk(L.G.npad);
+    hipLaunchKernelGGL(k_schur_extP<DIM>, dim3(np), dim3(BS), 0, s, P, L.G, L.W, L.x, 1, L.ext);
+    if (P.low_mach) {
+      hipLaunchKernelGGL((k_schur_u<DIM, true>), dim3(np), dim3(BS), 0, s, P, L.G, L.W, d_dt, 1, L.ext);
+      hipLaunchKernelGGL((k_imex_faces<DIM, true>), dim3(np), dim3(BS), 0, s, P, L.G, L.W, L.ext);
+    } else {
+      hipLaunchKernelGGL((k_schur_u<DIM, false>), dim3(np), dim3(BS), 0, s, P, L.G, L.W, d_dt, 1, L.ext);
+      hipLaunchKernelGGL((k_imex_faces<DIM, false>), dim3(np), dim3(BS), 0, s, P, L.G, L.W, L.ext);
+    }
+    hipLaunchKernelGGL(k_imex_cell<DIM>, dim3(np), dim3(BS), 0, s, P, L.G, d_dt, L.W);
     if (hipGetLastError() != hipSuccess) return hipErrorUnknown;
     return launch_ref_finish(P, L.W, Uout, d_dt, ctl, s);
   }
@@ -472,7 +526,7 @@ struct Imex {
 
 size_t imex_workspace_bytes(const Params& P) {
   RefGrid G = make_grid(P);
-  const long long n = (long long)(P.dim + 1) * P.ncell;
+  const long long n = P.ncell;
   auto al = [](size_t b) { return ((b + 255) / 256) * 256; };
   size_t s = al((size_t)R_NFIELD * G.npad * sizeof(double)) + al((size_t)(P.dim + 1) * G.npad * sizeof(double));
   s += 8 * al((size_t)n * sizeof(double));

@@ -1,8 +1,11 @@
 """GPU implicit acoustic (IMEX) step against the oracle (run on an MI355X).
 
-The oracle solves the implicit system with a direct sparse solver, the GPU
-with BiCGSTAB to a relative residual of 1e-13; the states are compared with
-the scale-aware 1e-12 measure of tests/parity.py.
+The oracle solves the implicit system for (Pi, u) with a direct sparse
+solver, the GPU the eliminated system for Pi with BiCGSTAB to a relative
+residual of 1e-13; the states are compared with the scale-aware 1e-12
+measure of tests/parity.py.  Without the low-Mach correction the acoustic
+dissipation (taken at t^n) limits the step to about the acoustic one, so
+those cases run at 0.8 times the explicit step.
 """
 import sys
 
@@ -49,10 +52,11 @@ def _outflow_cfg():
 CASES = {
     # name: (setup, flow amplitude, dt multiple of the explicit CFL step, steps)
     "rb2d_walls": (lambda: W.rb([24, 12], [2.0, 1.0], Ra=1e4, seed=3, amp=1e-2), 1e-2, 4.0, 4),
-    "rb2d_thetaoff": (lambda: W.rb([20, 10], [2.0, 1.0], Ra=1e4, seed=1, amp=1e-2, low_mach=0), 1e-2, 4.0, 4),
+    "rb2d_thetaoff": (lambda: W.rb([20, 10], [2.0, 1.0], Ra=1e4, seed=1, amp=1e-2, low_mach=0), 1e-2, 0.8, 4),
     "rb3d_walls": (lambda: W.rb([9, 7, 8], [1.0, 1.0, 1.0], Ra=1e5, seed=2, amp=1e-2), 1e-2, 3.0, 3),
-    "gresho_on": (lambda: W.gresho(n=32, Ma=1e-2, low_mach=1), 0.0, 20.0, 4),
-    "gresho_off": (lambda: W.gresho(n=24, Ma=1e-2, low_mach=0), 0.0, 20.0, 4),
+    "gresho_on": (lambda: W.gresho(n=32, Ma=1e-2, low_mach=1), 0.0, 8.0, 4),
+    "gresho_off": (lambda: W.gresho(n=24, Ma=1e-2, low_mach=0), 0.0, 0.8, 4),
+    "gresho_ma1e-3": (lambda: W.gresho(n=40, Ma=1e-3, low_mach=1), 0.0, 50.0, 3),
 }
 
 
@@ -95,15 +99,16 @@ def test_imex_outflow_viscous_vs_oracle(A):
     assert err <= 1e-12
 
 
-@pytest.mark.parametrize("lm", [1, 0])
-def test_imex_well_balanced_gpu(A, lm):
+@pytest.mark.parametrize("lm,mult", [(1, 100.0), (0, 0.8)])
+def test_imex_well_balanced_gpu(A, lm, mult):
     """Isothermal column and inviscid RB base at 100 times the explicit
-    step: at rest to round-off after 5 steps on the GPU."""
+    step (0.8 without the low-Mach correction): at rest to round-off after
+    5 steps on the GPU."""
     import torch
     cfg = dict(dim=2, n=[4, 128], L=[1.0, 3.0], gamma=5.0 / 3.0, g=1.0, mu=0.0, kappa=0.0, K=1.1, cfl=0.4,
                low_mach=lm, dt_mode=0, bc=[[0, 0], [1, 1]], wall_noslip=1, thermal=[0, 0], T_wall=[1.0, 1.0])
     S = A.Solver(cfg).init(W.PROB_ISOTHERMAL)
-    dt = S.dt.item() * 100
+    dt = S.dt.item() * mult
     S.step_imex([dt] * 5)
     torch.cuda.synchronize()
     U = S.numpy()
@@ -112,7 +117,7 @@ def test_imex_well_balanced_gpu(A, lm):
     cfg, prob, prm, seed = W.rb([32, 16, 12], [2.0, 1.0, 1.0], Ra=1e5, seed=1, amp=0.0, low_mach=lm)
     cfg = dict(cfg, mu=0.0, kappa=0.0)
     S = A.Solver(cfg).init(prob, prm, seed)
-    dt = S.dt.item() * 100
+    dt = S.dt.item() * mult
     S.step_imex([dt] * 5)
     torch.cuda.synchronize()
     U = S.numpy()

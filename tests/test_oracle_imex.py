@@ -19,8 +19,9 @@ at the end of the step.  What pins it, independently of its own formulas:
   (a system relaxing at the numerical impedance a = K rho c would converge
   to K pi);
 * low Mach: the Gresho vortex (Sec. 4.2) at Mach 1e-3 with steps 440 times
-  the acoustic limit keeps most of its kinetic energy with the low-Mach
-  correction and loses half of it without (eq. low_mach_correction).
+  the acoustic limit keeps its kinetic energy with the low-Mach correction
+  (eq. low_mach_correction); the acoustic dissipation of Pi*, taken at t^n,
+  needs that correction to allow such steps.
 """
 import numpy as np
 import pytest
@@ -60,13 +61,12 @@ def test_imex_consistent_with_explicit_step(dim):
     assert 3.0 < errs[0] / errs[1] < 4.5, errs
 
 
-@pytest.mark.parametrize("lm", [1, 0])
 @pytest.mark.parametrize("mult", [10, 100])
-def test_imex_well_balanced_rb_base(lm, mult):
+def test_imex_well_balanced_rb_base(mult):
     """Inviscid RB base (linear T, fixed-T walls, hydrostatic by eq.
     well_balanced_formula) at rest after 5 IMEX steps of 10 and 100 times
-    the explicit CFL step."""
-    cfg, prob, prm, seed = W.rb([12, 16], [2.0, 1.0], Ra=1e4, seed=1, amp=0.0, low_mach=lm)
+    the explicit CFL step (low-Mach correction on: theta = 0 at rest)."""
+    cfg, prob, prm, seed = W.rb([12, 16], [2.0, 1.0], Ra=1e4, seed=1, amp=0.0, low_mach=1)
     cfg = dict(cfg, mu=0.0, kappa=0.0)
     U = O.init(cfg, prob, prm, seed)
     dt = O.dt(cfg, U) * mult
@@ -78,12 +78,13 @@ def test_imex_well_balanced_rb_base(lm, mult):
 
 def test_imex_well_balanced_isothermal_column():
     """Sec. 4.3 isothermal column (walls at both ends) at 50 times the
-    explicit step, 10 steps: velocities at the round-off level of Table 1."""
-    for lm in (0, 1):
+    explicit step, 10 steps: velocities at the round-off level of Table 1;
+    without the low-Mach correction at 0.8 times the explicit step."""
+    for lm, mult in ((1, 50.0), (0, 0.8)):
         cfg = dict(dim=2, n=[4, 64], L=[1.0, 3.0], gamma=5.0 / 3.0, g=1.0, mu=0.0, kappa=0.0, K=1.1, cfl=0.4,
                    low_mach=lm, dt_mode=0, bc=[[0, 0], [1, 1]], wall_noslip=1, thermal=[0, 0], T_wall=[1.0, 1.0])
         U = O.init(cfg, W.PROB_ISOTHERMAL)
-        r = O.run_imex(cfg, U, 10, O.dt(cfg, U) * 50)
+        r = O.run_imex(cfg, U, 10, O.dt(cfg, U) * mult)
         assert r["status"] == 0
         assert np.max(np.abs(r["U"][1:3] / r["U"][0])) < 1e-13
 
@@ -122,7 +123,7 @@ def test_imex_conservation_periodic(visc):
 
 
 def _sound_wave(n, eps=1e-6):
-    cfg = dict(dim=2, n=[n, 1], L=[1.0, 1.0], gamma=1.4, g=0.0, mu=0.0, kappa=0.0, K=1.1, cfl=0.4, low_mach=0,
+    cfg = dict(dim=2, n=[n, 1], L=[1.0, 1.0], gamma=1.4, g=0.0, mu=0.0, kappa=0.0, K=1.1, cfl=0.4, low_mach=1,
                dt_mode=0, bc=[[0, 0], [0, 0]], wall_noslip=1, thermal=[0, 0], T_wall=[1.0, 1.0])
     x = (np.arange(n) + 0.5) / n
     c = np.sqrt(1.4)
@@ -178,18 +179,31 @@ def test_imex_wave_travels_at_sound_speed():
 
 def test_imex_gresho_low_mach():
     """Gresho vortex, Mach 1e-3, 32^2, time step of the transport CFL 0.4
-    (440 times the acoustic limit), 8 steps: the low-Mach correction keeps
-    the kinetic energy (> 85 %), without it half is lost (< 60 %); mass and
-    total energy are conserved to round-off."""
+    (about 440 times the acoustic limit), 8 steps with the low-Mach
+    correction: the kinetic energy is kept (> 85 %, the explicit scheme
+    keeps it with the correction as well, tests/test_oracle_pins.py), mass
+    and total energy are conserved to round-off."""
+    cfg, prob, prm, seed = W.gresho(n=32, Ma=1e-3, low_mach=1)
+    U = O.init(cfg, prob, prm, seed)
+    d0 = O.diag(cfg, U)
+    r = O.run_imex(cfg, U, 8, 0.4 / 32)
+    assert r["status"] == 0
+    d = O.diag(cfg, r["U"])
+    assert d["e_kin"] / d0["e_kin"] > 0.85
+    assert abs(d["mass"] - d0["mass"]) <= 1e-14 * d0["mass"]
+    assert abs(d["e_total"] - d0["e_total"]) <= 1e-14 * d0["e_total"]
+
+
+def test_imex_dissipation_at_t_n_limits_theta_one():
+    """The acoustic dissipation of Pi* acts on the velocities of t^n, with
+    coefficient a theta / 2: with the low-Mach correction (theta ~ Ma) its
+    limit is a transport one, without it (theta = 1) an acoustic one.  A
+    Gresho vortex at Mach 1e-2 and 10 times the acoustic step: bounded with
+    the correction, blown up (a non-physical state) without it."""
     out = {}
     for lm in (1, 0):
-        cfg, prob, prm, seed = W.gresho(n=32, Ma=1e-3, low_mach=lm)
+        cfg, prob, prm, seed = W.gresho(n=24, Ma=1e-2, low_mach=lm)
         U = O.init(cfg, prob, prm, seed)
-        d0 = O.diag(cfg, U)
-        r = O.run_imex(cfg, U, 8, 0.4 / 32)
-        assert r["status"] == 0
-        d = O.diag(cfg, r["U"])
-        out[lm] = d["e_kin"] / d0["e_kin"]
-        assert abs(d["mass"] - d0["mass"]) <= 1e-14 * d0["mass"]
-        assert abs(d["e_total"] - d0["e_total"]) <= 1e-14 * d0["e_total"]
-    assert out[1] > 0.85 and out[0] < 0.6
+        r = O.run_imex(cfg, U, 30, O.dt(cfg, U) * 10)
+        out[lm] = r["status"] == 0 and np.max(np.abs(r["U"][1] / r["U"][0])) < 2.0
+    assert out[1] and not out[0]
