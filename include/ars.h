@@ -287,10 +287,23 @@ int ars_step_ref(ars_ctx* ctx, double* d_state, double* d_tmp, void* d_work, voi
  * d_param_grad may be NULL; with mu = kappa = 0 the dissipative terms are
  * absent and no parameter derivative is produced.  d_work_adj: caller
  * buffer of ars_workspace_bytes_adjoint bytes.  Deterministic (no atomics).
- * d_lam_n must not alias d_lam_np1.  Asynchronous. */
+ * d_lam_n must not alias d_lam_np1.  Asynchronous.
+ * 3D problems with periodic lateral sides of at least 5 cells and walls at
+ * both vertical ends (or periodic ends with g = 0), conservative energy
+ * form, run two fused tile marches whose workspace is 12 doubles per cell;
+ * every other configuration runs the reference path below. */
 size_t ars_workspace_bytes_adjoint(const ars_ctx* ctx);
 int ars_step_adjoint(ars_ctx* ctx, const double* d_state_n, const double* d_lam_np1, double* d_lam_n,
                      const double* d_dt, double* d_param_grad, void* d_work_adj, void* stream);
+
+/* Reference path of the adjoint step: the same product by phase kernels
+ * over padded arrays (forward phases recomputed, then the reverse of each
+ * phase as a gather), every configuration, with a workspace of
+ * ars_workspace_bytes_adjoint_ref bytes; same arguments and contract as
+ * ars_step_adjoint.  Kept to check the fused marches. */
+size_t ars_workspace_bytes_adjoint_ref(const ars_ctx* ctx);
+int ars_step_adjoint_ref(ars_ctx* ctx, const double* d_state_n, const double* d_lam_np1, double* d_lam_n,
+                         const double* d_dt, double* d_param_grad, void* d_work_adj, void* stream);
 
 /* Kinetic-energy objective J = sum (1/2) |m|^2 / rho dV of d_state into the
  * device scalar *d_ke, and (if d_grad is not NULL) its gradient dJ/dU in

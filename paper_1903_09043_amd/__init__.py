@@ -90,6 +90,8 @@ SIGNATURES = [
     ("ars_step_ref", C.c_int, [_VP, _VP, _VP, _VP, _VP, C.c_int, _VP, _VP]),
     ("ars_workspace_bytes_adjoint", C.c_size_t, [_VP]),
     ("ars_step_adjoint", C.c_int, [_VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
+    ("ars_workspace_bytes_adjoint_ref", C.c_size_t, [_VP]),
+    ("ars_step_adjoint_ref", C.c_int, [_VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
     ("ars_kinetic_energy", C.c_int, [_VP, _VP, _VP, _VP, _VP, _VP]),
     ("ars_nusselt", C.c_int, [_VP, _VP, C.c_int, _VP, _VP, _VP, _VP]),
     ("ars_spectrum_len", C.c_int, [_VP]),
@@ -383,26 +385,28 @@ class Solver:
                                    C.byref(its), self.stream), "ars_step_imex")
         return its.value
 
-    def adjoint_workspace(self):
-        if getattr(self, "_wadj", None) is None:
-            nb = lib().ars_workspace_bytes_adjoint(self.ctx.h)
-            self._wadj = self.torch.empty(nb, dtype=self.torch.uint8, device=self.device)
-        return self._wadj
+    def adjoint_workspace(self, ref=False):
+        attr = "_wadj_ref" if ref else "_wadj"
+        if getattr(self, attr, None) is None:
+            f = lib().ars_workspace_bytes_adjoint_ref if ref else lib().ars_workspace_bytes_adjoint
+            setattr(self, attr, self.torch.empty(f(self.ctx.h), dtype=self.torch.uint8, device=self.device))
+        return getattr(self, attr)
 
-    def step_adjoint(self, U_n, lam_np1, dt, lam_n=None, param_grad=None):
+    def step_adjoint(self, U_n, lam_np1, dt, lam_n=None, param_grad=None, ref=False):
         """lam_n = (dU^{n+1}/dU^n)^T lam_np1 at frozen dt (a 1-element device
         tensor); param_grad (2-element device tensor) accumulates the mu and
-        kappa derivatives.  Returns lam_n."""
+        kappa derivatives.  ref=True runs the reference (phase-kernel) path.
+        Returns lam_n."""
         t = self.torch
         if lam_n is None:
             lam_n = t.empty_like(lam_np1)
         dt = dt.to(self.device, t.float64).reshape(-1)
-        w = self.adjoint_workspace()
+        w = self.adjoint_workspace(ref)
         L = self.ctx.state_len
-        _check(lib().ars_step_adjoint(self.ctx.h, self._arg(U_n, L, "U_n"), self._arg(lam_np1, L, "lam_np1"),
-                                      self._arg(lam_n, L, "lam_n"), self._arg(dt, 1, "dt"),
-                                      self._arg(param_grad, 2, "param_grad"), _ptr(w), self.stream),
-               "ars_step_adjoint")
+        name = "ars_step_adjoint_ref" if ref else "ars_step_adjoint"
+        _check(getattr(lib(), name)(self.ctx.h, self._arg(U_n, L, "U_n"), self._arg(lam_np1, L, "lam_np1"),
+                                    self._arg(lam_n, L, "lam_n"), self._arg(dt, 1, "dt"),
+                                    self._arg(param_grad, 2, "param_grad"), _ptr(w), self.stream), name)
         return lam_n
 
     def kinetic_energy(self, U=None, grad=None, out=None):

@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libars.so")
 SOURCES = ["ars_api.hip", "ars_fused.hip", "ars_ref.hip", "ars_reduce.hip", "ars_adjoint.hip", "ars_revolve.hip",
            "ars_batch.hip", "ars_tune.hip", "ars_spectrum.hip", "ars_noalloc.hip",
-           "ars_imex.hip"]
+           "ars_imex.hip", "ars_adjf.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

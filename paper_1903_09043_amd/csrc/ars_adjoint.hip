@@ -36,7 +36,7 @@ enum {
   A_NFIELD = A_PB + 9
 };
 
-size_t adjoint_workspace_bytes(const Params& P) {
+size_t adjoint_ref_workspace_bytes(const Params& P) {
   RefGrid G = make_grid(P);
   // fields, then two partial sums (mu, kappa) per block of the flux reverse
   const size_t nblk = (size_t)((G.npad + 255) / 256);
@@ -853,10 +853,25 @@ static hipError_t adjoint_t(const Params& P, const double* Un, const double* lam
   return hipGetLastError();
 }
 
-hipError_t launch_step_adjoint(const Params& P, const double* Un, const double* lam_np1, double* lam_n,
-                               const double* d_dt, double* d_param_grad, void* wadj, hipStream_t s) {
+hipError_t launch_adj_params_final(int nb, const double* partial, double* pgrad, hipStream_t s) {
+  hipLaunchKernelGGL(k_adj_params_final, dim3(1), dim3(256), 0, s, nb, partial, pgrad);
+  return hipGetLastError();
+}
+
+hipError_t launch_step_adjoint_ref(const Params& P, const double* Un, const double* lam_np1, double* lam_n,
+                                   const double* d_dt, double* d_param_grad, void* wadj, hipStream_t s) {
   return P.dim == 3 ? adjoint_t<3>(P, Un, lam_np1, lam_n, d_dt, d_param_grad, wadj, s)
                     : adjoint_t<2>(P, Un, lam_np1, lam_n, d_dt, d_param_grad, wadj, s);
+}
+
+size_t adjoint_workspace_bytes(const Params& P) {
+  return adjf_supported(P) ? adjf_workspace_bytes(P) : adjoint_ref_workspace_bytes(P);
+}
+
+hipError_t launch_step_adjoint(const Params& P, const double* Un, const double* lam_np1, double* lam_n,
+                               const double* d_dt, double* d_param_grad, void* wadj, hipStream_t s) {
+  if (adjf_supported(P)) return launch_step_adjoint_fused(P, Un, lam_np1, lam_n, d_dt, d_param_grad, wadj, s);
+  return launch_step_adjoint_ref(P, Un, lam_np1, lam_n, d_dt, d_param_grad, wadj, s);
 }
 
 }  // namespace ars

@@ -530,6 +530,15 @@ int ars_step_ref(ars_ctx* ctx, double* d_state, double* d_tmp, void* d_work, voi
 }
 
 size_t ars_workspace_bytes_adjoint(const ars_ctx* c) { return c ? ars::adjoint_workspace_bytes(c->P) : 0; }
+size_t ars_workspace_bytes_adjoint_ref(const ars_ctx* c) { return c ? ars::adjoint_ref_workspace_bytes(c->P) : 0; }
+
+int ars_step_adjoint_ref(ars_ctx* ctx, const double* d_state_n, const double* d_lam_np1, double* d_lam_n,
+                         const double* d_dt, double* d_param_grad, void* d_work_adj, void* stream) {
+  if (!ctx || !d_state_n || !d_lam_np1 || !d_lam_n || !d_dt || !d_work_adj || d_lam_n == d_lam_np1)
+    return ARS_EINVAL;
+  return check(ars::launch_step_adjoint_ref(ctx->P, d_state_n, d_lam_np1, d_lam_n, d_dt, d_param_grad, d_work_adj,
+                                            (hipStream_t)stream));
+}
 
 int ars_step_adjoint(ars_ctx* ctx, const double* d_state_n, const double* d_lam_np1, double* d_lam_n,
                      const double* d_dt, double* d_param_grad, void* d_work_adj, void* stream) {

@@ -51,10 +51,19 @@ size_t imex_workspace_bytes(const Params& P);
 int step_imex(const Params& P, double* d_state, double* d_tmp, Control* ctl, void* wimex, int nsteps,
               const double* d_dt_sched, double* d_t, double tol, int max_iter, int* h_iters, hipStream_t s);
 
-// Adjoint step (ars_adjoint.hip).
+// Adjoint step: the fused marches (ars_adjf.hip) where adjf_supported,
+// else the phase kernels (ars_adjoint.hip), which are also the reference.
 size_t adjoint_workspace_bytes(const Params& P);
 hipError_t launch_step_adjoint(const Params& P, const double* Un, const double* lam_np1, double* lam_n,
                                const double* d_dt, double* d_param_grad, void* wadj, hipStream_t s);
+size_t adjoint_ref_workspace_bytes(const Params& P);
+hipError_t launch_step_adjoint_ref(const Params& P, const double* Un, const double* lam_np1, double* lam_n,
+                                   const double* d_dt, double* d_param_grad, void* wadj, hipStream_t s);
+bool adjf_supported(const Params& P);
+size_t adjf_workspace_bytes(const Params& P);
+hipError_t launch_step_adjoint_fused(const Params& P, const double* Un, const double* lam_np1, double* lam_n,
+                                     const double* d_dt, double* d_param_grad, void* wadj, hipStream_t s);
+hipError_t launch_adj_params_final(int nb, const double* partial, double* pgrad, hipStream_t s);
 
 // Derived kernel parameters of a validated configuration (ars_api.hip).
 Params params_of(const ars_config* c);
