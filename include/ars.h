@@ -290,7 +290,7 @@ int ars_step_ref(ars_ctx* ctx, double* d_state, double* d_tmp, void* d_work, voi
  * d_lam_n must not alias d_lam_np1.  Asynchronous.
  * 3D problems with periodic lateral sides of at least 5 cells and walls at
  * both vertical ends (or periodic ends with g = 0), conservative energy
- * form, run two fused tile marches whose workspace is 12 doubles per cell;
+ * form, run three fused tile marches whose workspace is 17 doubles per cell;
  * every other configuration runs the reference path below. */
 size_t ars_workspace_bytes_adjoint(const ars_ctx* ctx);
 int ars_step_adjoint(ars_ctx* ctx, const double* d_state_n, const double* d_lam_np1, double* d_lam_n,

@@ -3,28 +3,33 @@
 // g = 0, periodic ends) along the vertical axis:
 //   lam^n = (dU^{n+1}/dU^n)^T lam^{n+1},  <lam^{n+1}, dU^{n+1}/d(mu, kappa)>.
 //
-// Two tile marches along the vertical axis replace the phase kernels of
+// Three tile marches along the vertical axis replace the phase kernels of
 // ars_adjoint.hip (which stay as the reference path and serve every other
 // configuration):
 //
-//  A  (halo 2) recomputes the forward step of eq. all_regime_scheme plane by
-//     plane exactly as the fused step does (primitives, acoustic faces,
-//     acoustic cell values b~ = (b - A)/L), forms the flux adjoints
-//     Gb = lam_a (nbar(R) - nbar(L)) from lam^{n+1}, reverses the transport
-//     fluxes (u*, Pi* adjoints of every face, b~ adjoint of every cell), the
-//     acoustic cell values (adjoints of L, A, S-bar and the direct
-//     conserved-value term) and the viscous and heat fluxes of Sec. 2.2; the
-//     velocity and temperature adjoints of the viscous stencils are gathered
-//     through LDS (every face publishes what it owes its neighbours, every
-//     cell collects in a fixed order) and taken through the primitive map at
-//     once.  It writes per cell the adjoints of (L, A_m, A_E, S-bar) and the
-//     (u*, Pi*) adjoints of its +x, +y, +z faces (12 fields), and
-//     lam^n = lam^{n+1} + (direct and viscous terms).
+//  A  (halo 2) recomputes the acoustic part of the step of eq.
+//     all_regime_scheme plane by plane exactly as the fused step does
+//     (primitives, acoustic faces, acoustic cell values b~ = (b - A)/L),
+//     forms the flux adjoints Gb = lam_a (nbar(R) - nbar(L)) from
+//     lam^{n+1}, reverses the transport fluxes (u*, Pi* adjoints of every
+//     face, b~ adjoint of every cell) and the acoustic cell values (adjoints
+//     of L, A, S-bar and the direct conserved-value term).  It writes per
+//     cell the adjoints of (L, A_m, A_E, S-bar) and the (u*, Pi*) adjoints
+//     of its +x, +y, +z faces (12 fields), and lam^n = lam^{n+1} + the
+//     direct term.
+//  V  (halo 2) reverses the viscous and heat fluxes of Sec. 2.2: every face
+//     publishes through LDS what it owes the cells of its stencil, every
+//     cell collects in a fixed order; the velocity and temperature adjoints
+//     of each cell (with those of its wall ghosts, through the ghost map)
+//     are written as 5 more fields, and the mu/kappa derivatives are summed
+//     per workgroup.
 //  B  (halo 1) reverses the acoustic face solver (Sec. 2.1.2 with eq.
 //     low_mach_correction and the gravity source of eq. well_balanced_formula)
 //     of every face from those 12 fields and the recomputed primitives,
 //     gathers the primitive adjoints of each cell (and of its wall ghosts),
-//     takes them through the primitive map and adds them to lam^n.
+//     adds the viscous ones of V, takes the sum through the primitive map
+//     and adds it to lam^n.  Every plane's inputs are loaded one plane
+//     ahead.
 //
 // Periodic lateral sides make every position of a tile a distinct cell of
 // the grid (at least 5 cells per lateral axis), so every face is one
@@ -44,11 +49,14 @@ namespace ars {
 enum {
   AF_CB = 0,   // adjoints of L, A_mx, A_my, A_mz, A_E, S-bar of the cell
   AF_FB = 6,   // (u*, Pi*) adjoints of the cell's +x, +y, +z faces from the flux reverse
-  AF_NF = 12
+  AF_PV = 12,  // (rho, u0, u1, u2, T) adjoints from the viscous and heat fluxes
+  AF_NF = 17
 };
 
-// Tiles (positions, outputs + halo): A has a 2-cell halo, B a 1-cell halo.
-constexpr int AF_AX = 24, AF_AY = 16;
+// Tiles (positions = outputs + halo): A and V have a 2-cell halo, B a
+// 1-cell halo.
+constexpr int AF_AX = 36, AF_AY = 14;
+constexpr int AF_VX = 36, AF_VY = 14;
 constexpr int AF_BX = 32, AF_BY = 16;
 
 bool adjf_supported(const Params& P) {
@@ -77,11 +85,12 @@ static int adjf_num_cu() {
   return ncu;
 }
 
-// Workgroups of march A (one mu/kappa partial pair each): one per CU, never
-// more than (tile, plane) pairs / 8.
-static int adjf_groups_a(const Params& P) {
-  const long long pairs = adjf_tiles(P, AF_AX, AF_AY, 2) * P.nz;
-  long long g = std::min(adjf_num_cu(), 1024);
+// Workgroups of a march: `per_cu` per compute unit (at most 1024 in all, so
+// that the mu/kappa partials of V fit their slots), never more than
+// (tile, plane) pairs / 8.
+static int adjf_groups(const Params& P, int EX, int EY, int halo, int per_cu) {
+  const long long pairs = adjf_tiles(P, EX, EY, halo) * P.nz;
+  long long g = std::min(per_cu * adjf_num_cu(), 1024);
   g = std::min(g, std::max(1ll, pairs / 8));
   return (int)g;
 }
@@ -310,36 +319,36 @@ __device__ __forceinline__ void nbar_of(const Params& P, int q, bool ghost, cons
 }
 
 // ------------------------------------------------------------------------
-// March A
+// March A: acoustic and transport reverse
 // ------------------------------------------------------------------------
 struct AdjIOF {
   const double* U;     // U^n
   const double* lam1;  // lam^{n+1}
-  double* lam0;        // lam^n (A writes the partial sum, B completes it)
+  double* lam0;        // lam^n (A writes the partial sum, V and B complete it)
   double* W;           // AF_NF fields
-  double* partial;     // mu/kappa partials, 2 per workgroup of A
+  double* partial;     // mu/kappa partials, 2 per workgroup of V
   const double* dt;
   int ntx, nty;
 };
 
+// nbar at a plane from lam^{n+1} (zero at wall ghosts, whose lam is zero)
+__device__ __forceinline__ double nbar_v(const Params& P, int v, double phi, const double* l) {
+  return v == 0 ? l[0] - phi * l[4] : l[v];
+}
+
 // LDS fields of march A (x NPOS doubles)
 enum {
   LA_XA = 0,   // rc, 1/rc, 1/c, p, ux, uy of plane p
-  LA_V = 6,    // ux, uy, uz, T of plane p-1
-  LA_DZ = 10,  // u(p) - u(p-2)
-  LA_NB = 13,  // nbar of plane p-1
-  LA_F = 18,   // own +x / +y faces of plane p: us, pi (x), us, pi (y)
-  LA_B = 22,   // b~ of plane p-1
-  LA_MX = 27,  // messages of the +x face of plane p-1 (8)
-  LA_MY = 35,  // messages of the +y face of plane p-1 (8)
-  LA_MZ = 43,  // messages of the face (p-2 | p-1) (4)
-  LA_TOTAL = 47
+  LA_F = 6,    // own +x / +y faces of plane p: us, pi (x), us, pi (y)
+  LA_B = 10,   // b~ of plane p-1
+  LA_NB = 15,  // nbar of plane p-1, two slots (plane parity)
+  LA_TOTAL = 25
 };
 
-template <bool LM, bool DISS, int EX, int EY>
+template <bool LM, int EX, int EY>
 __device__ __forceinline__ void adj_march_a(const Params& P, const AdjIOF& io, double* __restrict__ sm, const int tx,
                                             const int ty, const int z0, const int z1, const double lx,
-                                            const double ly, const double lz, double& mu_acc, double& ka_acc) {
+                                            const double ly, const double lz) {
   constexpr int NV = 5;
   constexpr int NPOS = EX * EY;
   constexpr int TX = EX - 4, TY = EY - 4;
@@ -347,44 +356,24 @@ __device__ __forceinline__ void adj_march_a(const Params& P, const AdjIOF& io, d
   const long long N = P.ncell;
   const int tid = threadIdx.x;
   const int px = tid % EX, py = tid / EX;
-  const bool hxp = px + 1 < EX, hxm = px > 0, hyp = py + 1 < EY, hym = py > 0;
-  const int pxp = hxp ? tid + 1 : tid, pxm = hxm ? tid - 1 : tid;
-  const int pyp = hyp ? tid + EX : tid, pym = hym ? tid - EX : tid;
-  const int pxpyp = (hxp && hyp) ? tid + EX + 1 : tid;
-  const int pxpym = (hxp && hym) ? tid - EX + 1 : tid;
-  const int pxmyp = (hxm && hyp) ? tid + EX - 1 : tid;
-  const int pxmym = (hxm && hym) ? tid - EX - 1 : tid;
+  const int pxp = px + 1 < EX ? tid + 1 : tid, pxm = px > 0 ? tid - 1 : tid;
+  const int pyp = py + 1 < EY ? tid + EX : tid, pym = py > 0 ? tid - EX : tid;
   const int gx = tx * TX + px - 2, gy = ty * TY + py - 2;
   const int cx = resolve_lat(gx, P.nx, P.bcx), cy = resolve_lat(gy, P.ny, P.bcy);
   const long long col = (long long)cx + (long long)P.nx * cy;
   const bool out = px >= 2 && px < EX - 2 && gx < P.nx && py >= 2 && py < EY - 2 && gy < P.ny;
   const bool needL = px >= 1 && px <= EX - 2 && py >= 1 && py <= EY - 2;
-  const bool visX = px >= 1 && px <= EX - 3 && py >= 1 && py <= EY - 2;
-  const bool visY = px >= 1 && px <= EX - 2 && py >= 1 && py <= EY - 3;
-  const bool visZ = needL;
-  const bool zper = P.bcz[0] == BC_PERIODIC;
-  const double qx = P.qidx[0], qy = P.qidx[1], qz = P.qidx[2];
 
   double Unx[NV], Lnx[NV];
-  double U1[NV], U2[NV];           // conserved values of planes p-1, p-2
+  double U1[NV];                   // conserved values of plane p-1
   double l1[NV], l2[NV];           // lam^{n+1} of planes p-1, p-2 (0 at wall ghosts)
-  double nb1[NV], nb2[NV];         // nbar of planes p-1, p-2
-  Prim<3> q0, q1;                  // primitives of planes p, p-1
-  double u2[3] = {0, 0, 0}, T2 = 0.0;
+  Prim<3> q1;                      // primitives of plane p-1
   double zAus = 0, zApi = 0, zAP = 0, zAS = 0;
-  double zBus = 0, zBpi = 0, zBP = 0, zBS = 0;
   double bt1[NV], bt2[NV], L1 = 1.0, L2 = 1.0;
   double Fo1[6];
-  double dX2[4] = {0, 0, 0, 0};
-  double btb1[NV], btb2[NV];       // b~ adjoints of planes p-1, p-2
-  double vbA[4], vbB[4], vbC[4];   // (u, T) adjoints of planes p, p-1, p-2
-  double gcar[NV];                 // bottom wall ghost's share of lam^n of plane 0
+  double btb2[NV];                 // b~ adjoint of plane p-2 (all but its top face)
 #pragma unroll
-  for (int v = 0; v < NV; ++v) {
-    U1[v] = U2[v] = l1[v] = l2[v] = nb1[v] = nb2[v] = bt1[v] = bt2[v] = btb1[v] = btb2[v] = gcar[v] = 0.0;
-  }
-#pragma unroll
-  for (int k = 0; k < 4; ++k) vbA[k] = vbB[k] = vbC[k] = 0.0;
+  for (int v = 0; v < NV; ++v) U1[v] = l1[v] = l2[v] = bt1[v] = bt2[v] = btb2[v] = 0.0;
 #pragma unroll
   for (int i = 0; i < 6; ++i) Fo1[i] = 0.0;
   q1 = Prim<3>{};
@@ -395,35 +384,35 @@ __device__ __forceinline__ void adj_march_a(const Params& P, const AdjIOF& io, d
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       Unx[v] = io.U[b + v * N];
-      Lnx[v] = ghost_nx >= 0 ? 0.0 : io.lam1[b + v * N];
+      Lnx[v] = io.lam1[b + v * N];  // a valid cell in every case; zeroed at wall ghosts when used
     }
   }
-  auto plane = [&](const int p) __attribute__((always_inline)) {
+  for (int p = z0 - 2; p <= z1 + 1; ++p) {
     // ======================= phase 1 =======================================
-    double Uc[NV], l0[NV], nb0[NV];
+    const int ghost = ghost_nx;
+    double Uc[NV], l0[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       Uc[v] = Unx[v];
-      l0[v] = Lnx[v];
+      l0[v] = ghost >= 0 ? 0.0 : Lnx[v];  // wall ghosts are not updated: no lam
     }
-    const int ghost = ghost_nx;
     if (p + 1 <= z1 + 1) {
       const int src = plane_src(P, p + 1, ghost_nx);
       const long long b = col + PS * src;
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
         Unx[v] = io.U[b + v * N];
-        Lnx[v] = ghost_nx >= 0 ? 0.0 : io.lam1[b + v * N];
+        Lnx[v] = io.lam1[b + v * N];
       }
     }
-    nbar_of(P, p, ghost >= 0, l0, nb0);
-    q0 = cons_to_prim<3>(P, Uc);
+    Prim<3> q0 = cons_to_prim<3>(P, Uc);
     if (ghost >= 0) {
       const int kg = ghost == 0 ? -1 : P.nz;
       const int ki = ghost == 0 ? 0 : P.nz - 1;
       q0 = wall_ghost<3>(P, q0, ghost, phi_at(P, kg) - phi_at(P, ki));
     }
     const double phip = phi_at(P, p), phi1 = phi_at(P, p - 1), phi2 = phi_at(P, p - 2);
+    double zBus = 0, zBpi = 0, zBP = 0, zBS = 0;
     if (p >= z0 - 1) face_vert<LM, 3>(P, q1, q0, phip - phi1, wall_face_below(P, p - 1), zBus, zBpi, zBP, zBS);
     sm[(LA_XA + 0) * NPOS + tid] = q0.rc;
     sm[(LA_XA + 1) * NPOS + tid] = q0.irc;
@@ -431,15 +420,13 @@ __device__ __forceinline__ void adj_march_a(const Params& P, const AdjIOF& io, d
     sm[(LA_XA + 3) * NPOS + tid] = q0.p;
     sm[(LA_XA + 4) * NPOS + tid] = q0.u[0];
     sm[(LA_XA + 5) * NPOS + tid] = q0.u[1];
-    if (DISS) {
+    const int nbs = LA_NB + 5 * (p & 1);
+    double nb1[NV];
 #pragma unroll
-      for (int k = 0; k < 3; ++k) sm[(LA_V + k) * NPOS + tid] = q1.u[k];
-      sm[(LA_V + 3) * NPOS + tid] = q1.T;
-#pragma unroll
-      for (int k = 0; k < 3; ++k) sm[(LA_DZ + k) * NPOS + tid] = q0.u[k] - u2[k];
+    for (int v = 0; v < NV; ++v) {
+      nb1[v] = nbar_v(P, v, phi1, l1);
+      sm[(nbs + v) * NPOS + tid] = nb1[v];
     }
-#pragma unroll
-    for (int v = 0; v < NV; ++v) sm[(LA_NB + v) * NPOS + tid] = nb1[v];
     __syncthreads();  // ------------------------------------------- bar 1
 
     // ======================= phase 2 =======================================
@@ -478,16 +465,19 @@ __device__ __forceinline__ void adj_march_a(const Params& P, const AdjIOF& io, d
     }
     // b~ adjoint of plane p-1 from its -x / -y faces when it is their upwind
     // (right) cell
+    double btb1[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) btb1[v] = 0.0;
     if (out && p - 1 >= z0 && p - 1 < z1) {
       const double usxm = sm[(LA_F + 0) * NPOS + pxm];
       if (!(usxm >= 0.0)) {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) btb1[v] += (lx * (nb1[v] - sm[(LA_NB + v) * NPOS + pxm])) * usxm;
+        for (int v = 0; v < NV; ++v) btb1[v] += (lx * (nb1[v] - sm[(nbs + v) * NPOS + pxm])) * usxm;
       }
       const double usym = sm[(LA_F + 2) * NPOS + pym];
       if (!(usym >= 0.0)) {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) btb1[v] += (ly * (nb1[v] - sm[(LA_NB + v) * NPOS + pym])) * usym;
+        for (int v = 0; v < NV; ++v) btb1[v] += (ly * (nb1[v] - sm[(nbs + v) * NPOS + pym])) * usym;
       }
     }
     // own lateral acoustic faces of plane p (forward)
@@ -503,14 +493,6 @@ __device__ __forceinline__ void adj_march_a(const Params& P, const AdjIOF& io, d
 #pragma unroll
       for (int i = 0; i < 6; ++i) Fn[i] = 0.0;
     }
-    // tangential differences of plane p-1 (vertical viscous faces)
-    double dX1[4] = {0.0, 0.0, 0.0, 0.0};
-    if (DISS && visZ) {
-      dX1[0] = sm[(LA_V + 0) * NPOS + pxp] - sm[(LA_V + 0) * NPOS + pxm];
-      dX1[1] = sm[(LA_V + 2) * NPOS + pxp] - sm[(LA_V + 2) * NPOS + pxm];
-      dX1[2] = sm[(LA_V + 1) * NPOS + pyp] - sm[(LA_V + 1) * NPOS + pym];
-      dX1[3] = sm[(LA_V + 2) * NPOS + pyp] - sm[(LA_V + 2) * NPOS + pym];
-    }
     __syncthreads();  // ------------------------------------------- bar 1b
 
     // ======================= phase 3 =======================================
@@ -518,106 +500,44 @@ __device__ __forceinline__ void adj_march_a(const Params& P, const AdjIOF& io, d
     sm[(LA_F + 1) * NPOS + tid] = Fn[1];
     sm[(LA_F + 2) * NPOS + tid] = Fn[3];
     sm[(LA_F + 3) * NPOS + tid] = Fn[4];
-
-    double Mo[20];
-#pragma unroll
-    for (int i = 0; i < 20; ++i) Mo[i] = 0.0;
-    const int m = p - 1;  // plane of the lateral faces reversed now
-    const bool realm = zper || (m >= 0 && m < P.nz);
-    const bool latT = out && m >= z0 && m < z1;
-    const bool latV = DISS && realm && m >= z0 - 1 && m <= z1;
-#pragma unroll
-    for (int dir = 0; dir < 2; ++dir) {
-      const bool vis = latV && (dir == 0 ? visX : visY);
-      if (!(latT || vis)) continue;
-      const int nb = dir == 0 ? pxp : pyp;
-      const double lam_a = dir == 0 ? lx : ly;
-      double Gb[NV];
-#pragma unroll
-      for (int v = 0; v < NV; ++v) Gb[v] = lam_a * (sm[(LA_NB + v) * NPOS + nb] - nb1[v]);
-      if (latT) {
-        const double us = Fo1[3 * dir + 0];
-        const double pi = Fo1[3 * dir + 1];
-        const bool upL = us >= 0.0;
-        double bu[NV];
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-          const double bn = sm[(LA_B + v) * NPOS + nb];
-          bu[v] = upL ? bt1[v] : bn;
-        }
-        double usb = 0.0;
-#pragma unroll
-        for (int v = 0; v < NV - 1; ++v) usb += Gb[v] * bu[v];
-        usb += Gb[NV - 1] * (bu[NV - 1] + pi);
-        const double pib = Gb[1 + dir] + Gb[NV - 1] * us;
-        if (upL) {
-#pragma unroll
-          for (int v = 0; v < NV; ++v) btb1[v] += Gb[v] * us;
-        }
+    if (out) {
+      // transport reverse of the own +x / +y faces of plane p-1
+      const int m = p - 1;
+      if (m >= z0 && m < z1) {
         const long long cell = col + PS * m;
-        io.W[(AF_FB + 2 * dir + 0) * N + cell] = usb;
-        io.W[(AF_FB + 2 * dir + 1) * N + cell] = pib;
-      }
-      if (DISS && vis) {
-        // forward gradient of the face (as the fused step forms it)
-        double uR[3], TR;
 #pragma unroll
-        for (int k = 0; k < 3; ++k) uR[k] = sm[(LA_V + k) * NPOS + nb];
-        TR = sm[(LA_V + 3) * NPOS + nb];
-        double g[3][3];
+        for (int dir = 0; dir < 2; ++dir) {
+          const int nb = dir == 0 ? pxp : pyp;
+          const double lam_a = dir == 0 ? lx : ly;
+          const double us = Fo1[3 * dir + 0];
+          const double pi = Fo1[3 * dir + 1];
+          const bool upL = us >= 0.0;
+          double Gb[NV], bu[NV];
 #pragma unroll
-        for (int a = 0; a < 3; ++a)
+          for (int v = 0; v < NV; ++v) {
+            Gb[v] = lam_a * (sm[(nbs + v) * NPOS + nb] - nb1[v]);
+            const double bn = sm[(LA_B + v) * NPOS + nb];
+            bu[v] = upL ? bt1[v] : bn;
+          }
+          double usb = 0.0;
 #pragma unroll
-          for (int k = 0; k < 3; ++k) g[a][k] = 0.0;
-        const double idn = P.idx[dir];
+          for (int v = 0; v < NV - 1; ++v) usb += Gb[v] * bu[v];
+          usb += Gb[NV - 1] * (bu[NV - 1] + pi);
+          const double pib = Gb[1 + dir] + Gb[NV - 1] * us;
+          if (upL) {
 #pragma unroll
-        for (int k = 0; k < 3; ++k) g[dir][k] = (uR[k] - q1.u[k]) * idn;
-        const int a = 1 - dir;
-        const int pa_p = a == 1 ? pyp : pxp;
-        const int pa_m = a == 1 ? pym : pxm;
-        const int nb_p = a == 1 ? (dir == 0 ? pxpyp : pyp) : (dir == 1 ? pxpyp : pxp);
-        const int nb_m = a == 1 ? (dir == 0 ? pxpym : pym) : (dir == 1 ? pxmyp : pxm);
-        const double qa = P.qidx[a];
-        g[a][dir] = ((sm[(LA_V + dir) * NPOS + pa_p] - sm[(LA_V + dir) * NPOS + pa_m]) +
-                     (sm[(LA_V + dir) * NPOS + nb_p] - sm[(LA_V + dir) * NPOS + nb_m])) * qa;
-        g[a][a] = ((sm[(LA_V + a) * NPOS + pa_p] - sm[(LA_V + a) * NPOS + pa_m]) +
-                   (sm[(LA_V + a) * NPOS + nb_p] - sm[(LA_V + a) * NPOS + nb_m])) * qa;
-        g[2][dir] = ((q0.u[dir] - u2[dir]) + sm[(LA_DZ + dir) * NPOS + nb]) * qz;
-        g[2][2] = ((q0.u[2] - u2[2]) + sm[(LA_DZ + 2) * NPOS + nb]) * qz;
-        double uLb[3], uRb[3], TLb, TRb, gb[3][3], mub, kab;
-        visc_adj(P, dir, idn, g, q1.u, uR, q1.T, TR, Gb, uLb, uRb, TLb, TRb, gb, mub, kab);
-#pragma unroll
-        for (int k = 0; k < 3; ++k) vbB[k] += uLb[k];
-        vbB[3] += TLb;
-        // own column's share of the vertical tangential rows (planes p, p-2)
-        vbA[dir] += qz * gb[2][dir];
-        vbA[2] += qz * gb[2][2];
-        vbC[dir] -= qz * gb[2][dir];
-        vbC[2] -= qz * gb[2][2];
-        double* M = Mo + 8 * dir;
-        M[0] = uRb[0];
-        M[1] = uRb[1];
-        M[2] = uRb[2];
-        M[3] = TRb;
-        M[4] = gb[a][dir];
-        M[5] = gb[a][a];
-        M[6] = gb[2][dir];
-        M[7] = gb[2][2];
-        if (latT) {
-          mu_acc += mub;
-          ka_acc += kab;
+            for (int v = 0; v < NV; ++v) btb1[v] += Gb[v] * us;
+          }
+          io.W[(AF_FB + 2 * dir + 0) * N + cell] = usb;
+          io.W[(AF_FB + 2 * dir + 1) * N + cell] = pib;
         }
       }
-    }
-
-    // vertical face (p-2 | p-1)
-    const bool vzx = (p - 1 >= z0) && (p - 1 <= z1);
-    if (vzx && (out || (DISS && visZ))) {
-      const bool wall = wall_face_below(P, p - 2);
-      double Gb[NV];
+      // transport reverse of the vertical face (p-2 | p-1)
+      if ((p - 1 >= z0) && (p - 1 <= z1)) {
+        const bool wall = wall_face_below(P, p - 2);
+        double Gb[NV];
 #pragma unroll
-      for (int v = 0; v < NV; ++v) Gb[v] = lz * (nb1[v] - nb2[v]);
-      if (out) {
+        for (int v = 0; v < NV; ++v) Gb[v] = lz * (nb1[v] - nbar_v(P, v, phi2, l2));
         double usb = 0.0, pib = Gb[3];
         if (!wall) {
           const bool upL = zAus >= 0.0;
@@ -642,93 +562,303 @@ __device__ __forceinline__ void adj_march_a(const Params& P, const AdjIOF& io, d
           io.W[(AF_FB + 5) * N + cell] = pib;
         }
       }
-      if (DISS && visZ) {
-        double g[3][3];
+      // acoustic cell values of plane p-2, reversed; lam^n starts there
+      if (p - 2 >= z0 && p - 2 < z1) {
+        const double iL = rcp_nr(L2);
+        double Lb = 0.0, Ab[NV], consb[NV];
 #pragma unroll
-        for (int a = 0; a < 3; ++a)
-#pragma unroll
-          for (int k = 0; k < 3; ++k) g[a][k] = 0.0;
-        const double idn = P.idx[2];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) g[2][k] = (q1.u[k] - u2[k]) * idn;
-        g[0][0] = (dX2[0] + dX1[0]) * qx;
-        g[0][2] = (dX2[1] + dX1[1]) * qx;
-        g[1][1] = (dX2[2] + dX1[2]) * qy;
-        g[1][2] = (dX2[3] + dX1[3]) * qy;
-        double uLb[3], uRb[3], TLb, TRb, gb[3][3], mub, kab;
-        visc_adj(P, 2, idn, g, u2, q1.u, T2, q1.T, Gb, uLb, uRb, TLb, TRb, gb, mub, kab);
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          vbC[k] += uLb[k];
-          vbB[k] += uRb[k];
+        for (int v = 0; v < NV; ++v) {
+          consb[v] = btb2[v] * iL;
+          Ab[v] = -btb2[v] * iL;
+          Lb += btb2[v] * bt2[v];
         }
-        vbC[3] += TLb;
-        vbB[3] += TRb;
-        Mo[16] = gb[0][0];
-        Mo[17] = gb[0][2];
-        Mo[18] = gb[1][1];
-        Mo[19] = gb[1][2];
-        const bool own = (p - 2 >= z0 && p - 2 < z1) || (p - 2 == -1 && z0 == 0 && P.bcz[0] == BC_WALL);
-        if (out && own) {
-          mu_acc += mub;
-          ka_acc += kab;
-        }
+        Lb = -Lb * iL;
+        consb[0] += phi2 * consb[NV - 1];  // calE = E + rho Phi
+        // A_mz = lam_z ((Pi+ - Pi-) - S-bar); the update adds lam_z S-bar to m_z
+        const double sbb = -lz * Ab[3] + lz * l2[3];
+        const long long cell = col + PS * (p - 2);
+        io.W[(AF_CB + 0) * N + cell] = Lb;
+        io.W[(AF_CB + 1) * N + cell] = Ab[1];
+        io.W[(AF_CB + 2) * N + cell] = Ab[2];
+        io.W[(AF_CB + 3) * N + cell] = Ab[3];
+        io.W[(AF_CB + 4) * N + cell] = Ab[4];
+        io.W[(AF_CB + 5) * N + cell] = sbb;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) io.lam0[cell + v * N] = l2[v] + consb[v];
       }
     }
+    // rotate the vertical window
+    q1 = q0;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      U1[v] = Uc[v];
+      l2[v] = l1[v];
+      l1[v] = l0[v];
+      bt2[v] = bt1[v];
+      btb2[v] = btb1[v];
+    }
+    L2 = L1;
+    zAus = zBus; zApi = zBpi; zAP = zBP; zAS = zBS;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) Fo1[i] = Fn[i];
+  }
+}
 
-    // acoustic cell values of plane p-2, reversed
-    const bool outp = out && p - 2 >= z0 && p - 2 < z1;
-    double consb[NV];
-    if (outp) {
-      const double iL = rcp_nr(L2);
-      double Lb = 0.0, Ab[NV];
+template <bool LM, int EX, int EY>
+__global__ void __launch_bounds__(EX* EY) k_adjf_a(Params P, AdjIOF io) {
+  __shared__ double sm[LA_TOTAL * EX * EY];
+  const double dt = *io.dt;
+  const double lx = dt / P.dx[0], ly = dt / P.dx[1], lz = dt / P.dx[2];
+  const long long total = (long long)io.ntx * io.nty * P.nz;
+  const int G = gridDim.x, b = blockIdx.x;
+  long long cur = total * b / G;
+  const long long stop = total * (b + 1) / G;
+  while (cur < stop) {
+    const int tile = (int)(cur / P.nz);
+    const int z0 = (int)(cur % P.nz);
+    const int z1 = (int)min((long long)P.nz, (long long)z0 + (stop - cur));
+    cur += z1 - z0;
+    adj_march_a<LM, EX, EY>(P, io, sm, tile % io.ntx, tile / io.ntx, z0, z1, lx, ly, lz);
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------------
+// March V: viscous and heat-flux reverse
+// ------------------------------------------------------------------------
+enum {
+  LV_V = 0,    // ux, uy, uz, T of plane p-1
+  LV_DZ = 4,   // u(p) - u(p-2)
+  LV_NB = 7,   // nbar of plane p-1
+  LV_MX = 12,  // messages of the +x face of plane p-1 (8)
+  LV_MY = 20,  // messages of the +y face of plane p-1 (8)
+  LV_MZ = 28,  // messages of the face (p-2 | p-1) (4)
+  LV_TOTAL = 32
+};
+
+template <int EX, int EY>
+__device__ __forceinline__ void adj_march_v(const Params& P, const AdjIOF& io, double* __restrict__ sm, const int tx,
+                                            const int ty, const int z0, const int z1, const double lx,
+                                            const double ly, const double lz, double& mu_acc, double& ka_acc) {
+  constexpr int NV = 5;
+  constexpr int NPOS = EX * EY;
+  constexpr int TX = EX - 4, TY = EY - 4;
+  const long long PS = (long long)P.nx * P.ny;
+  const long long N = P.ncell;
+  const int tid = threadIdx.x;
+  const int px = tid % EX, py = tid / EX;
+  const bool hxp = px + 1 < EX, hxm = px > 0, hyp = py + 1 < EY, hym = py > 0;
+  const int pxp = hxp ? tid + 1 : tid, pxm = hxm ? tid - 1 : tid;
+  const int pyp = hyp ? tid + EX : tid, pym = hym ? tid - EX : tid;
+  const int pxpyp = (hxp && hyp) ? tid + EX + 1 : tid;
+  const int pxpym = (hxp && hym) ? tid - EX + 1 : tid;
+  const int pxmyp = (hxm && hyp) ? tid + EX - 1 : tid;
+  const int pxmym = (hxm && hym) ? tid - EX - 1 : tid;
+  const int gx = tx * TX + px - 2, gy = ty * TY + py - 2;
+  const int cx = resolve_lat(gx, P.nx, P.bcx), cy = resolve_lat(gy, P.ny, P.bcy);
+  const long long col = (long long)cx + (long long)P.nx * cy;
+  const bool out = px >= 2 && px < EX - 2 && gx < P.nx && py >= 2 && py < EY - 2 && gy < P.ny;
+  // owners of faces whose stencil reaches an output cell
+  const bool visX = px >= 1 && px <= EX - 3 && py >= 1 && py <= EY - 2;
+  const bool visY = px >= 1 && px <= EX - 2 && py >= 1 && py <= EY - 3;
+  const bool visZ = px >= 1 && px <= EX - 2 && py >= 1 && py <= EY - 2;
+  const bool zper = P.bcz[0] == BC_PERIODIC;
+  const bool wlo = P.bcz[0] == BC_WALL, whi = P.bcz[1] == BC_WALL;
+  const double qx = P.qidx[0], qy = P.qidx[1], qz = P.qidx[2];
+
+  double Unx[NV], Lnx[NV];
+  double l1[NV], l2[NV];           // lam^{n+1} of planes p-1, p-2 (0 at wall ghosts)
+  double u1[3] = {0, 0, 0}, T1 = 0.0, u2[3] = {0, 0, 0}, T2 = 0.0;  // planes p-1, p-2
+  double dX2[4] = {0, 0, 0, 0};    // tangential differences of plane p-2
+  double vbB[4] = {0, 0, 0, 0}, vbC[4] = {0, 0, 0, 0};  // (u, T) adjoints of planes p-1, p-2
+  double gcar[5] = {0, 0, 0, 0, 0};  // bottom wall ghost's (rho, u, T) share of plane 0
+#pragma unroll
+  for (int v = 0; v < NV; ++v) l1[v] = l2[v] = 0.0;
+  int ghost_nx;
+  {
+    const int src = plane_src(P, z0 - 2, ghost_nx);
+    const long long b = col + PS * src;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      Unx[v] = io.U[b + v * N];
+      Lnx[v] = io.lam1[b + v * N];  // a valid cell in every case; zeroed at wall ghosts when used
+    }
+  }
+  for (int p = z0 - 2; p <= z1 + 1; ++p) {
+    // ======================= phase 1 =======================================
+    const int ghost = ghost_nx;
+    double Uc[NV], l0[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      Uc[v] = Unx[v];
+      l0[v] = ghost >= 0 ? 0.0 : Lnx[v];  // wall ghosts are not updated: no lam
+    }
+    if (p + 1 <= z1 + 1) {
+      const int src = plane_src(P, p + 1, ghost_nx);
+      const long long b = col + PS * src;
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        consb[v] = btb2[v] * iL;
-        Ab[v] = -btb2[v] * iL;
-        Lb += btb2[v] * bt2[v];
+        Unx[v] = io.U[b + v * N];
+        Lnx[v] = io.lam1[b + v * N];
       }
-      Lb = -Lb * iL;
-      consb[0] += phi2 * consb[NV - 1];  // calE = E + rho Phi
-      // A_mz = lam_z ((Pi+ - Pi-) - S-bar); the update adds lam_z S-bar to m_z
-      const double sbb = -lz * Ab[3] + lz * nb2[3];
-      const long long cell = col + PS * (p - 2);
-      io.W[(AF_CB + 0) * N + cell] = Lb;
-      io.W[(AF_CB + 1) * N + cell] = Ab[1];
-      io.W[(AF_CB + 2) * N + cell] = Ab[2];
-      io.W[(AF_CB + 3) * N + cell] = Ab[3];
-      io.W[(AF_CB + 4) * N + cell] = Ab[4];
-      io.W[(AF_CB + 5) * N + cell] = sbb;
     }
-    if (DISS) {
+    Prim<3> q0 = cons_to_prim<3>(P, Uc);
+    if (ghost >= 0) {
+      const int kg = ghost == 0 ? -1 : P.nz;
+      const int ki = ghost == 0 ? 0 : P.nz - 1;
+      q0 = wall_ghost<3>(P, q0, ghost, phi_at(P, kg) - phi_at(P, ki));
+    }
+    const double phi1 = phi_at(P, p - 1), phi2 = phi_at(P, p - 2);
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        sm[(LA_MX + i) * NPOS + tid] = Mo[i];
-        sm[(LA_MY + i) * NPOS + tid] = Mo[8 + i];
+    for (int k = 0; k < 3; ++k) {
+      sm[(LV_V + k) * NPOS + tid] = u1[k];
+      sm[(LV_DZ + k) * NPOS + tid] = q0.u[k] - u2[k];
+    }
+    sm[(LV_V + 3) * NPOS + tid] = T1;
+    double nb1[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      nb1[v] = nbar_v(P, v, phi1, l1);
+      sm[(LV_NB + v) * NPOS + tid] = nb1[v];
+    }
+    __syncthreads();  // ------------------------------------------- bar 1
+
+    // ======================= phase 2 =======================================
+    double vbA[4] = {0, 0, 0, 0};   // (u, T) adjoint of plane p
+    double Mo[20];
+#pragma unroll
+    for (int i = 0; i < 20; ++i) Mo[i] = 0.0;
+    // tangential differences of plane p-1 (vertical faces)
+    double dX1[4] = {0.0, 0.0, 0.0, 0.0};
+    if (visZ) {
+      dX1[0] = sm[(LV_V + 0) * NPOS + pxp] - sm[(LV_V + 0) * NPOS + pxm];
+      dX1[1] = sm[(LV_V + 2) * NPOS + pxp] - sm[(LV_V + 2) * NPOS + pxm];
+      dX1[2] = sm[(LV_V + 1) * NPOS + pyp] - sm[(LV_V + 1) * NPOS + pym];
+      dX1[3] = sm[(LV_V + 2) * NPOS + pyp] - sm[(LV_V + 2) * NPOS + pym];
+    }
+    // lateral faces of plane m = p-1
+    const int m = p - 1;
+    const bool latV = (zper || (m >= 0 && m < P.nz)) && m >= z0 - 1 && m <= z1;
+    const bool own_m = out && m >= z0 && m < z1;
+#pragma unroll
+    for (int dir = 0; dir < 2; ++dir) {
+      if (!(latV && (dir == 0 ? visX : visY))) continue;
+      const int nb = dir == 0 ? pxp : pyp;
+      const double lam_a = dir == 0 ? lx : ly;
+      double Gb[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) Gb[v] = lam_a * (sm[(LV_NB + v) * NPOS + nb] - nb1[v]);
+      double uR[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) uR[k] = sm[(LV_V + k) * NPOS + nb];
+      const double TR = sm[(LV_V + 3) * NPOS + nb];
+      double g[3][3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) g[a][k] = 0.0;
+      const double idn = P.idx[dir];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) g[dir][k] = (uR[k] - u1[k]) * idn;
+      const int a = 1 - dir;
+      const int pa_p = a == 1 ? pyp : pxp;
+      const int pa_m = a == 1 ? pym : pxm;
+      const int nb_p = a == 1 ? (dir == 0 ? pxpyp : pyp) : (dir == 1 ? pxpyp : pxp);
+      const int nb_m = a == 1 ? (dir == 0 ? pxpym : pym) : (dir == 1 ? pxmyp : pxm);
+      const double qa = P.qidx[a];
+      g[a][dir] = ((sm[(LV_V + dir) * NPOS + pa_p] - sm[(LV_V + dir) * NPOS + pa_m]) +
+                   (sm[(LV_V + dir) * NPOS + nb_p] - sm[(LV_V + dir) * NPOS + nb_m])) * qa;
+      g[a][a] = ((sm[(LV_V + a) * NPOS + pa_p] - sm[(LV_V + a) * NPOS + pa_m]) +
+                 (sm[(LV_V + a) * NPOS + nb_p] - sm[(LV_V + a) * NPOS + nb_m])) * qa;
+      g[2][dir] = ((q0.u[dir] - u2[dir]) + sm[(LV_DZ + dir) * NPOS + nb]) * qz;
+      g[2][2] = ((q0.u[2] - u2[2]) + sm[(LV_DZ + 2) * NPOS + nb]) * qz;
+      double uLb[3], uRb[3], TLb, TRb, gb[3][3], mub, kab;
+      visc_adj(P, dir, idn, g, u1, uR, T1, TR, Gb, uLb, uRb, TLb, TRb, gb, mub, kab);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) vbB[k] += uLb[k];
+      vbB[3] += TLb;
+      // own column's share of the vertical tangential rows (planes p, p-2)
+      vbA[dir] += qz * gb[2][dir];
+      vbA[2] += qz * gb[2][2];
+      vbC[dir] -= qz * gb[2][dir];
+      vbC[2] -= qz * gb[2][2];
+      double* M = Mo + 8 * dir;
+      M[0] = uRb[0];
+      M[1] = uRb[1];
+      M[2] = uRb[2];
+      M[3] = TRb;
+      M[4] = gb[a][dir];
+      M[5] = gb[a][a];
+      M[6] = gb[2][dir];
+      M[7] = gb[2][2];
+      if (own_m) {
+        mu_acc += mub;
+        ka_acc += kab;
       }
-#pragma unroll
-      for (int i = 0; i < 4; ++i) sm[(LA_MZ + i) * NPOS + tid] = Mo[16 + i];
     }
+    // vertical face (p-2 | p-1)
+    if ((p - 1 >= z0) && (p - 1 <= z1) && visZ) {
+      double Gb[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) Gb[v] = lz * (nb1[v] - nbar_v(P, v, phi2, l2));
+      double g[3][3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) g[a][k] = 0.0;
+      const double idn = P.idx[2];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) g[2][k] = (u1[k] - u2[k]) * idn;
+      g[0][0] = (dX2[0] + dX1[0]) * qx;
+      g[0][2] = (dX2[1] + dX1[1]) * qx;
+      g[1][1] = (dX2[2] + dX1[2]) * qy;
+      g[1][2] = (dX2[3] + dX1[3]) * qy;
+      double uLb[3], uRb[3], TLb, TRb, gb[3][3], mub, kab;
+      visc_adj(P, 2, idn, g, u2, u1, T2, T1, Gb, uLb, uRb, TLb, TRb, gb, mub, kab);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        vbC[k] += uLb[k];
+        vbB[k] += uRb[k];
+      }
+      vbC[3] += TLb;
+      vbB[3] += TRb;
+      Mo[16] = gb[0][0];
+      Mo[17] = gb[0][2];
+      Mo[18] = gb[1][1];
+      Mo[19] = gb[1][2];
+      const bool own = (p - 2 >= z0 && p - 2 < z1) || (p - 2 == -1 && z0 == 0 && wlo);
+      if (out && own) {
+        mu_acc += mub;
+        ka_acc += kab;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      sm[(LV_MX + i) * NPOS + tid] = Mo[i];
+      sm[(LV_MY + i) * NPOS + tid] = Mo[8 + i];
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) sm[(LV_MZ + i) * NPOS + tid] = Mo[16 + i];
     __syncthreads();  // ------------------------------------------- bar 2
 
-    // ======================= phase 4 =======================================
-    if (DISS && out) {
+    // ======================= phase 3 =======================================
+    if (out) {
       // normal parts of the -x / -y faces of plane p-1
 #pragma unroll
-      for (int i = 0; i < 4; ++i) vbB[i] += sm[(LA_MX + i) * NPOS + pxm] + sm[(LA_MY + i) * NPOS + pym];
+      for (int i = 0; i < 4; ++i) vbB[i] += sm[(LV_MX + i) * NPOS + pxm] + sm[(LV_MY + i) * NPOS + pym];
       // lateral tangential rows of the x faces (y rows) and y faces (x rows)
-      vbB[0] += qy * ((sm[(LA_MX + 4) * NPOS + pym] - sm[(LA_MX + 4) * NPOS + pyp]) +
-                      (sm[(LA_MX + 4) * NPOS + pxmym] - sm[(LA_MX + 4) * NPOS + pxmyp]));
-      vbB[1] += qy * ((sm[(LA_MX + 5) * NPOS + pym] - sm[(LA_MX + 5) * NPOS + pyp]) +
-                      (sm[(LA_MX + 5) * NPOS + pxmym] - sm[(LA_MX + 5) * NPOS + pxmyp]));
-      vbB[1] += qx * ((sm[(LA_MY + 4) * NPOS + pxm] - sm[(LA_MY + 4) * NPOS + pxp]) +
-                      (sm[(LA_MY + 4) * NPOS + pxmym] - sm[(LA_MY + 4) * NPOS + pxpym]));
-      vbB[0] += qx * ((sm[(LA_MY + 5) * NPOS + pxm] - sm[(LA_MY + 5) * NPOS + pxp]) +
-                      (sm[(LA_MY + 5) * NPOS + pxmym] - sm[(LA_MY + 5) * NPOS + pxpym]));
+      vbB[0] += qy * ((sm[(LV_MX + 4) * NPOS + pym] - sm[(LV_MX + 4) * NPOS + pyp]) +
+                      (sm[(LV_MX + 4) * NPOS + pxmym] - sm[(LV_MX + 4) * NPOS + pxmyp]));
+      vbB[1] += qy * ((sm[(LV_MX + 5) * NPOS + pym] - sm[(LV_MX + 5) * NPOS + pyp]) +
+                      (sm[(LV_MX + 5) * NPOS + pxmym] - sm[(LV_MX + 5) * NPOS + pxmyp]));
+      vbB[1] += qx * ((sm[(LV_MY + 4) * NPOS + pxm] - sm[(LV_MY + 4) * NPOS + pxp]) +
+                      (sm[(LV_MY + 4) * NPOS + pxmym] - sm[(LV_MY + 4) * NPOS + pxpym]));
+      vbB[0] += qx * ((sm[(LV_MY + 5) * NPOS + pxm] - sm[(LV_MY + 5) * NPOS + pxp]) +
+                      (sm[(LV_MY + 5) * NPOS + pxmym] - sm[(LV_MY + 5) * NPOS + pxpym]));
       // vertical tangential rows of the -x / -y faces (planes p and p-2)
       {
-        const double a0 = qz * sm[(LA_MX + 6) * NPOS + pxm], a2 = qz * sm[(LA_MX + 7) * NPOS + pxm];
-        const double b1 = qz * sm[(LA_MY + 6) * NPOS + pym], b2 = qz * sm[(LA_MY + 7) * NPOS + pym];
+        const double a0 = qz * sm[(LV_MX + 6) * NPOS + pxm], a2 = qz * sm[(LV_MX + 7) * NPOS + pxm];
+        const double b1 = qz * sm[(LV_MY + 6) * NPOS + pym], b2 = qz * sm[(LV_MY + 7) * NPOS + pym];
         vbA[0] += a0;
         vbA[2] += a2;
         vbA[1] += b1;
@@ -740,10 +870,10 @@ __device__ __forceinline__ void adj_march_a(const Params& P, const AdjIOF& io, d
       }
       // lateral tangential rows of the vertical faces of the neighbouring columns
       {
-        const double x0 = qx * (sm[(LA_MZ + 0) * NPOS + pxm] - sm[(LA_MZ + 0) * NPOS + pxp]);
-        const double x2 = qx * (sm[(LA_MZ + 1) * NPOS + pxm] - sm[(LA_MZ + 1) * NPOS + pxp]);
-        const double y1 = qy * (sm[(LA_MZ + 2) * NPOS + pym] - sm[(LA_MZ + 2) * NPOS + pyp]);
-        const double y2 = qy * (sm[(LA_MZ + 3) * NPOS + pym] - sm[(LA_MZ + 3) * NPOS + pyp]);
+        const double x0 = qx * (sm[(LV_MZ + 0) * NPOS + pxm] - sm[(LV_MZ + 0) * NPOS + pxp]);
+        const double x2 = qx * (sm[(LV_MZ + 1) * NPOS + pxm] - sm[(LV_MZ + 1) * NPOS + pxp]);
+        const double y1 = qy * (sm[(LV_MZ + 2) * NPOS + pym] - sm[(LV_MZ + 2) * NPOS + pyp]);
+        const double y2 = qy * (sm[(LV_MZ + 3) * NPOS + pym] - sm[(LV_MZ + 3) * NPOS + pyp]);
         vbC[0] += x0;
         vbB[0] += x0;
         vbC[2] += x2;
@@ -753,79 +883,80 @@ __device__ __forceinline__ void adj_march_a(const Params& P, const AdjIOF& io, d
         vbC[2] += y2;
         vbB[2] += y2;
       }
-    }
-    if (DISS && out && p - 2 == -1 && z0 == 0 && P.bcz[0] == BC_WALL) {
-      // bottom wall ghost (plane -1, built from plane 0 = p-1): its viscous
-      // adjoints go to plane 0 through the ghost map
-      const Prim<3> gq = wall_ghost<3>(P, q1, 0, phi_at(P, -1) - phi_at(P, 0));
-      const double gb[9] = {0.0, vbC[0], vbC[1], vbC[2], 0.0, 0.0, 0.0, 0.0, vbC[3]};
-      double ib[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-      ghost_adj(P, 0, phi_at(P, -1) - phi_at(P, 0), q1, gq, gb, ib);
-      prim_adj(P, q1, U1 + 1, ib, gcar);
-    }
-    if (outp) {
-      const Prim<3> qo = cons_to_prim<3>(P, U2);
-      double pb[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-      if (DISS) {
-        pb[1] = vbC[0];
-        pb[2] = vbC[1];
-        pb[3] = vbC[2];
-        pb[8] = vbC[3];
-        if (p - 2 == P.nz - 1 && P.bcz[1] == BC_WALL) {
-          // top wall ghost (plane nz = p-1, built from this plane)
-          const double gb[9] = {0.0, vbB[0], vbB[1], vbB[2], 0.0, 0.0, 0.0, 0.0, vbB[3]};
-          ghost_adj(P, 1, phi_at(P, P.nz) - phi_at(P, P.nz - 1), qo, q1, gb, pb);
-        }
-      }
-      double Ub[NV];
-      prim_adj(P, qo, U2 + 1, pb, Ub);
-      const bool bot = (p - 2 == 0) && P.bcz[0] == BC_WALL;
-      const long long cell = col + PS * (p - 2);
+      if (p - 2 == -1 && z0 == 0 && wlo) {
+        // bottom wall ghost (plane -1, built from plane 0 = p-1): its
+        // adjoints go to the primitives of plane 0 through the ghost map
+        double U0c[NV];
 #pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        double s = (l2[v] + consb[v]) + Ub[v];
-        if (bot) s = s + gcar[v];
-        io.lam0[cell + v * N] = s;
+        for (int v = 0; v < NV; ++v) U0c[v] = io.U[col + v * N];
+        const Prim<3> qi = cons_to_prim<3>(P, U0c);
+        const double d = phi_at(P, -1) - phi_at(P, 0);
+        const Prim<3> gq = wall_ghost<3>(P, qi, 0, d);
+        const double gb[9] = {0.0, vbC[0], vbC[1], vbC[2], 0.0, 0.0, 0.0, 0.0, vbC[3]};
+        double ib[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+        ghost_adj(P, 0, d, qi, gq, gb, ib);
+        gcar[0] = ib[0];
+        gcar[1] = ib[1];
+        gcar[2] = ib[2];
+        gcar[3] = ib[3];
+        gcar[4] = ib[8];
+      }
+      if (p - 2 >= z0 && p - 2 < z1) {
+        // (rho, u, T) adjoints of plane p-2, for the primitive map of B
+        const long long cell = col + PS * (p - 2);
+        double pb[9] = {0.0, vbC[0], vbC[1], vbC[2], 0.0, 0.0, 0.0, 0.0, vbC[3]};
+        if (p - 2 == P.nz - 1 && whi) {
+          // top wall ghost (plane nz = p-1, built from this plane)
+          double Uo[NV];
+#pragma unroll
+          for (int v = 0; v < NV; ++v) Uo[v] = io.U[cell + v * N];
+          const Prim<3> qo = cons_to_prim<3>(P, Uo);
+          const double d = phi_at(P, P.nz) - phi_at(P, P.nz - 1);
+          const Prim<3> gq = wall_ghost<3>(P, qo, 1, d);
+          const double gb[9] = {0.0, vbB[0], vbB[1], vbB[2], 0.0, 0.0, 0.0, 0.0, vbB[3]};
+          ghost_adj(P, 1, d, qo, gq, gb, pb);
+        }
+        if ((p - 2 == 0) && wlo) {
+          pb[0] += gcar[0];
+          pb[1] += gcar[1];
+          pb[2] += gcar[2];
+          pb[3] += gcar[3];
+          pb[8] += gcar[4];
+        }
+        io.W[(AF_PV + 0) * N + cell] = pb[0];
+        io.W[(AF_PV + 1) * N + cell] = pb[1];
+        io.W[(AF_PV + 2) * N + cell] = pb[2];
+        io.W[(AF_PV + 3) * N + cell] = pb[3];
+        io.W[(AF_PV + 4) * N + cell] = pb[8];
       }
     }
-
     // rotate the vertical window
 #pragma unroll
-    for (int k = 0; k < 3; ++k) u2[k] = q1.u[k];
-    T2 = q1.T;
-    q1 = q0;
+    for (int k = 0; k < 3; ++k) {
+      u2[k] = u1[k];
+      u1[k] = q0.u[k];
+    }
+    T2 = T1;
+    T1 = q0.T;
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      U2[v] = U1[v];
-      U1[v] = Uc[v];
       l2[v] = l1[v];
       l1[v] = l0[v];
-      nb2[v] = nb1[v];
-      nb1[v] = nb0[v];
-      bt2[v] = bt1[v];
-      btb2[v] = btb1[v];
-      btb1[v] = 0.0;
     }
-    L2 = L1;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       vbC[k] = vbB[k];
       vbB[k] = vbA[k];
-      vbA[k] = 0.0;
     }
-    zAus = zBus; zApi = zBpi; zAP = zBP; zAS = zBS;
-#pragma unroll
-    for (int i = 0; i < 6; ++i) Fo1[i] = Fn[i];
 #pragma unroll
     for (int i = 0; i < 4; ++i) dX2[i] = dX1[i];
-  };
-  for (int p = z0 - 2; p <= z1 + 1; ++p) plane(p);
+  }
 }
 
-template <bool LM, bool DISS, int EX, int EY>
-__global__ void __launch_bounds__(EX* EY) k_adjf_a(Params P, AdjIOF io) {
+template <int EX, int EY>
+__global__ void __launch_bounds__(EX* EY) k_adjf_v(Params P, AdjIOF io) {
   constexpr int NPOS = EX * EY;
-  __shared__ double sm[LA_TOTAL * NPOS];
+  __shared__ double sm[LV_TOTAL * NPOS];
   __shared__ double red[2][(NPOS + 63) / 64];
   const double dt = *io.dt;
   const double lx = dt / P.dx[0], ly = dt / P.dx[1], lz = dt / P.dx[2];
@@ -839,17 +970,17 @@ __global__ void __launch_bounds__(EX* EY) k_adjf_a(Params P, AdjIOF io) {
     const int z0 = (int)(cur % P.nz);
     const int z1 = (int)min((long long)P.nz, (long long)z0 + (stop - cur));
     cur += z1 - z0;
-    adj_march_a<LM, DISS, EX, EY>(P, io, sm, tile % io.ntx, tile / io.ntx, z0, z1, lx, ly, lz, mu_acc, ka_acc);
+    adj_march_v<EX, EY>(P, io, sm, tile % io.ntx, tile / io.ntx, z0, z1, lx, ly, lz, mu_acc, ka_acc);
     __syncthreads();
   }
-  if (!DISS) return;
-  // workgroup sums of the mu / kappa partials in a fixed order
+  // workgroup sums of the mu / kappa partials in a fixed order (a partial
+  // last wave has no lanes past NPOS: its missing lanes add zeros)
+  const int tid = threadIdx.x;
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) {
     mu_acc += __shfl_xor(mu_acc, off, 64);
     ka_acc += __shfl_xor(ka_acc, off, 64);
   }
-  const int tid = threadIdx.x;
   if ((tid & 63) == 0) {
     red[0][tid >> 6] = mu_acc;
     red[1][tid >> 6] = ka_acc;
@@ -865,7 +996,6 @@ __global__ void __launch_bounds__(EX* EY) k_adjf_a(Params P, AdjIOF io) {
     io.partial[2 * b + 1] = c;
   }
 }
-
 // ------------------------------------------------------------------------
 // March B
 // ------------------------------------------------------------------------
@@ -899,31 +1029,54 @@ __device__ __forceinline__ void adj_march_b(const Params& P, const AdjIOF& io, d
   const bool ownY = py <= EY - 2 && px >= 1 && px <= EX - 2;
   const bool wlo = P.bcz[0] == BC_WALL, whi = P.bcz[1] == BC_WALL;
 
+  // plane data, loaded one plane ahead: U and the acoustic workspace fields
+  // of plane q (zeroed at wall ghosts when used), and the partial lam^n and
+  // viscous (rho, u, T) adjoints of plane q-1, finished in the trip that
+  // uses them (all addresses valid: ghost and out-of-range planes load a
+  // clamped plane that is never used)
+  constexpr int NW = AF_PV;
+  double Un[NV], Wn[NW], Ln[NV], Vn[5];
+  int ghn;
+  auto load = [&](int q) __attribute__((always_inline)) {
+    const int src = plane_src(P, q, ghn);
+    const long long cs = col + PS * src;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Un[v] = io.U[cs + v * N];
+#pragma unroll
+    for (int i = 0; i < NW; ++i) Wn[i] = io.W[i * N + cs];
+    const long long cf = col + PS * min(max(q - 1, 0), P.nz - 1);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Ln[v] = io.lam0[cf + v * N];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) Vn[k] = io.W[(AF_PV + k) * N + cf];
+  };
   Prim<3> q1 = Prim<3>{};
   double U1[NV] = {0, 0, 0, 0, 0};
-  double pb1[9];                        // primitive adjoints of plane p-1
+  double pb1[8];                        // face adjoints of (rho, u, p, rc, 1/rc, 1/c) of plane p-1
   double cb1[4] = {0, 0, 0, 0};         // adjoints of L, A_mz, A_E, S-bar of plane p-1
   double fz1[2] = {0, 0};               // (u*, Pi*) adjoints of the face (p-1 | p)
-  double gcar[NV] = {0, 0, 0, 0, 0};    // bottom wall ghost's share of plane 0
 #pragma unroll
-  for (int k = 0; k < 9; ++k) pb1[k] = 0.0;
+  for (int k = 0; k < 8; ++k) pb1[k] = 0.0;
+  load(z0 - 1);
 
   for (int p = z0 - 1; p <= z1; ++p) {
-    int ghost;
-    const int src = plane_src(P, p, ghost);
-    const long long cs = col + PS * src;
-    double Uc[NV];
+    const int ghost = ghn;
+    double Uc[NV], w[NW], lo[NV], pv[5];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) Uc[v] = io.U[cs + v * N];
-    double cb[6], fb[6];
-    const bool gh = ghost >= 0;
-#pragma unroll
-    for (int i = 0; i < 6; ++i) {
-      cb[i] = gh ? 0.0 : io.W[(AF_CB + i) * N + cs];
-      fb[i] = gh ? 0.0 : io.W[(AF_FB + i) * N + cs];
+    for (int v = 0; v < NV; ++v) {
+      Uc[v] = Un[v];
+      lo[v] = Ln[v];
     }
+#pragma unroll
+    for (int i = 0; i < NW; ++i) w[i] = ghost >= 0 ? 0.0 : Wn[i];  // wall ghosts carry none
+#pragma unroll
+    for (int k = 0; k < 5; ++k) pv[k] = Vn[k];
+    const bool fin = out && p - 1 >= z0 && p - 1 < z1;
+    if (p + 1 <= z1) load(p + 1);
+    const double* cb = w + AF_CB;
+    const double* fb = w + AF_FB;
     Prim<3> q0 = cons_to_prim<3>(P, Uc);
-    if (gh) {
+    if (ghost >= 0) {
       const int kg = ghost == 0 ? -1 : P.nz;
       const int ki = ghost == 0 ? 0 : P.nz - 1;
       q0 = wall_ghost<3>(P, q0, ghost, phi_at(P, kg) - phi_at(P, ki));
@@ -940,9 +1093,9 @@ __device__ __forceinline__ void adj_march_b(const Params& P, const AdjIOF& io, d
     sm[(LB_CB + 3) * NPOS + tid] = cb[4];
     __syncthreads();  // ------------------------------------------- bar 1
 
-    double pb0[9];
+    double pb0[8];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) pb0[k] = 0.0;
+    for (int k = 0; k < 8; ++k) pb0[k] = 0.0;
     const bool lat = p >= z0 && p < z1;
 #pragma unroll
     for (int dir = 0; dir < 2; ++dir) {
@@ -1018,33 +1171,44 @@ __device__ __forceinline__ void adj_march_b(const Params& P, const AdjIOF& io, d
       pb0[7] += sm[(LB_RY + 4) * NPOS + pym];
     }
     if (out && p - 1 == -1 && wlo && z0 == 0) {
-      // bottom wall ghost (plane -1 = p-1, built from plane 0 = p)
+      // bottom wall ghost (plane -1 = p-1, built from plane 0 = p): its
+      // share of lam^n of plane 0 joins the partial lam^n of plane 0 that
+      // load(1) fetched at the top of this trip (z1 >= 1)
+      const double gb[9] = {pb1[0], pb1[1], pb1[2], pb1[3], pb1[4], pb1[5], pb1[6], pb1[7], 0.0};
       double ib[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-      ghost_adj(P, 0, phi_at(P, -1) - phi_at(P, 0), q0, q1, pb1, ib);
-      prim_adj(P, q0, Uc + 1, ib, gcar);
+      ghost_adj(P, 0, phi_at(P, -1) - phi_at(P, 0), q0, q1, gb, ib);
+      double gU[NV];
+      prim_adj(P, q0, Uc + 1, ib, gU);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) Ln[v] = Ln[v] + gU[v];
     }
-    if (out && p - 1 >= z0 && p - 1 < z1) {
+    if (fin) {
+      double pb[9] = {pb1[0], pb1[1], pb1[2], pb1[3], pb1[4], pb1[5], pb1[6], pb1[7], 0.0};
       if (p == P.nz && whi) {
         // top wall ghost (plane nz = p, built from plane nz-1 = p-1)
-        ghost_adj(P, 1, phi_at(P, P.nz) - phi_at(P, P.nz - 1), q1, q0, pb0, pb1);
+        const double gb[9] = {pb0[0], pb0[1], pb0[2], pb0[3], pb0[4], pb0[5], pb0[6], pb0[7], 0.0};
+        ghost_adj(P, 1, phi_at(P, P.nz) - phi_at(P, P.nz - 1), q1, q0, gb, pb);
+      }
+      // viscous and heat-flux share (march V, which runs when diss)
+      if (P.diss) {
+        pb[0] += pv[0];
+        pb[1] += pv[1];
+        pb[2] += pv[2];
+        pb[3] += pv[3];
+        pb[8] += pv[4];
       }
       double Ub[NV];
-      prim_adj(P, q1, U1 + 1, pb1, Ub);
-      const bool bot = (p - 1 == 0) && wlo;
+      prim_adj(P, q1, U1 + 1, pb, Ub);
       const long long cell = col + PS * (p - 1);
 #pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        double s = io.lam0[cell + v * N] + Ub[v];
-        if (bot) s = s + gcar[v];
-        io.lam0[cell + v * N] = s;
-      }
+      for (int v = 0; v < NV; ++v) io.lam0[cell + v * N] = lo[v] + Ub[v];
     }
     // rotate
     q1 = q0;
 #pragma unroll
     for (int v = 0; v < NV; ++v) U1[v] = Uc[v];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) pb1[k] = pb0[k];
+    for (int k = 0; k < 8; ++k) pb1[k] = pb0[k];
     cb1[0] = cb[0];
     cb1[1] = cb[3];
     cb1[2] = cb[4];
@@ -1053,7 +1217,6 @@ __device__ __forceinline__ void adj_march_b(const Params& P, const AdjIOF& io, d
     fz1[1] = fb[5];
   }
 }
-
 template <bool LM, int EX, int EY>
 __global__ void __launch_bounds__(EX* EY) k_adjf_b(Params P, AdjIOF io) {
   __shared__ double sm[LB_TOTAL * EX * EY];
@@ -1086,30 +1249,31 @@ static hipError_t adjf_t(const Params& P, const double* Un, const double* lam1, 
   io.W = (double*)wadj;
   io.partial = io.W + (size_t)AF_NF * P.ncell;
   io.dt = d_dt;
-  // march A
-  {
-    constexpr int TX = AF_AX - 4, TY = AF_AY - 4;
-    io.ntx = (P.nx + TX - 1) / TX;
-    io.nty = (P.ny + TY - 1) / TY;
-    const int g = adjf_groups_a(P);
-    hipLaunchKernelGGL((k_adjf_a<LM, DISS, AF_AX, AF_AY>), dim3((unsigned)g), dim3(AF_AX * AF_AY), 0, s, P, io);
-    hipError_t e = hipGetLastError();
+  // A: lam^n = lam^{n+1} + direct term; L, A, S-bar and face adjoints
+  io.ntx = (P.nx + AF_AX - 5) / (AF_AX - 4);
+  io.nty = (P.ny + AF_AY - 5) / (AF_AY - 4);
+  int g = adjf_groups(P, AF_AX, AF_AY, 2, 1);
+  hipLaunchKernelGGL((k_adjf_a<LM, AF_AX, AF_AY>), dim3((unsigned)g), dim3(AF_AX * AF_AY), 0, s, P, io);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  // V: + viscous and heat-flux terms, mu/kappa derivatives
+  if (DISS) {
+    io.ntx = (P.nx + AF_VX - 5) / (AF_VX - 4);
+    io.nty = (P.ny + AF_VY - 5) / (AF_VY - 4);
+    g = adjf_groups(P, AF_VX, AF_VY, 2, 1);
+    hipLaunchKernelGGL((k_adjf_v<AF_VX, AF_VY>), dim3((unsigned)g), dim3(AF_VX * AF_VY), 0, s, P, io);
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if (DISS && pgrad) {
+    if (pgrad) {
       e = launch_adj_params_final(g, io.partial, pgrad, s);
       if (e != hipSuccess) return e;
     }
   }
-  // march B
-  {
-    constexpr int TX = AF_BX - 2, TY = AF_BY - 2;
-    io.ntx = (P.nx + TX - 1) / TX;
-    io.nty = (P.ny + TY - 1) / TY;
-    const long long pairs = (long long)io.ntx * io.nty * P.nz;
-    long long g = 2ll * adjf_num_cu();
-    g = std::min(g, std::max(1ll, pairs / 8));
-    hipLaunchKernelGGL((k_adjf_b<LM, AF_BX, AF_BY>), dim3((unsigned)g), dim3(AF_BX * AF_BY), 0, s, P, io);
-  }
+  // B: + acoustic face-solver terms
+  io.ntx = (P.nx + AF_BX - 3) / (AF_BX - 2);
+  io.nty = (P.ny + AF_BY - 3) / (AF_BY - 2);
+  g = adjf_groups(P, AF_BX, AF_BY, 1, 2);
+  hipLaunchKernelGGL((k_adjf_b<LM, AF_BX, AF_BY>), dim3((unsigned)g), dim3(AF_BX * AF_BY), 0, s, P, io);
   return hipGetLastError();
 }
 
