@@ -95,6 +95,11 @@ static int adjf_groups(const Params& P, int EX, int EY, int halo, int per_cu) {
   return (int)g;
 }
 
+// Share of workgroup b: workgroups are dealt to the 8 XCDs in turn, so the
+// shares of one XCD are made consecutive (neighbours in space, whose halo
+// re-reads then hit that XCD's L2).
+__device__ __forceinline__ int xcd_share(int b, int G) { return (G % 8 == 0) ? (b % 8) * (G / 8) + b / 8 : b; }
+
 size_t adjf_workspace_bytes(const Params& P) {
   return (size_t)AF_NF * (size_t)P.ncell * sizeof(double) + 2 * 1024 * sizeof(double);
 }
@@ -119,8 +124,8 @@ __device__ __forceinline__ void prim_adj(const Params& P, const Prim<3>& q, cons
   // T = p r
   p_b += T_b * q.r;
   rb += T_b * q.p;
-  // c = sqrt(gamma p r)
-  const double Xb = cb * 0.5 / q.c;
+  // c = sqrt(gamma p r): dc/dX = 1/(2c) = ic/2
+  const double Xb = (cb * 0.5) * q.ic;
   p_b += Xb * P.gamma * q.r;
   rb += Xb * P.gamma * q.p;
   // p = (gamma - 1)(E - kin), kin = sum m_k u_k / 2, u_k = m_k r
@@ -150,7 +155,7 @@ __device__ __forceinline__ void ghost_adj(const Params& P, int side, double delt
   double cb = -icb * g.ic * g.ic;
   double rhob = gb[0] + gb[5] * g.c;
   cb += gb[5] * g.rho;
-  const double Xb = cb * 0.5 / g.c;
+  const double Xb = (cb * 0.5) * g.ic;
   double pb = gb[4] + Xb * P.gamma * g.r;
   rb += Xb * P.gamma * g.p;
   rhob += -rb * g.r * g.r;
@@ -611,8 +616,9 @@ __global__ void __launch_bounds__(EX* EY) k_adjf_a(Params P, AdjIOF io) {
   const double lx = dt / P.dx[0], ly = dt / P.dx[1], lz = dt / P.dx[2];
   const long long total = (long long)io.ntx * io.nty * P.nz;
   const int G = gridDim.x, b = blockIdx.x;
-  long long cur = total * b / G;
-  const long long stop = total * (b + 1) / G;
+  const int lw = xcd_share(b, G);
+  long long cur = total * lw / G;
+  const long long stop = total * (lw + 1) / G;
   while (cur < stop) {
     const int tile = (int)(cur / P.nz);
     const int z0 = (int)(cur % P.nz);
@@ -962,8 +968,9 @@ __global__ void __launch_bounds__(EX* EY) k_adjf_v(Params P, AdjIOF io) {
   const double lx = dt / P.dx[0], ly = dt / P.dx[1], lz = dt / P.dx[2];
   const long long total = (long long)io.ntx * io.nty * P.nz;
   const int G = gridDim.x, b = blockIdx.x;
-  long long cur = total * b / G;
-  const long long stop = total * (b + 1) / G;
+  const int lw = xcd_share(b, G);
+  long long cur = total * lw / G;
+  const long long stop = total * (lw + 1) / G;
   double mu_acc = 0.0, ka_acc = 0.0;
   while (cur < stop) {
     const int tile = (int)(cur / P.nz);
@@ -1042,8 +1049,13 @@ __device__ __forceinline__ void adj_march_b(const Params& P, const AdjIOF& io, d
     const long long cs = col + PS * src;
 #pragma unroll
     for (int v = 0; v < NV; ++v) Un[v] = io.U[cs + v * N];
+    if (ghn >= 0) {  // uniform: wall ghosts carry no adjoints
 #pragma unroll
-    for (int i = 0; i < NW; ++i) Wn[i] = io.W[i * N + cs];
+      for (int i = 0; i < NW; ++i) Wn[i] = 0.0;
+    } else {
+#pragma unroll
+      for (int i = 0; i < NW; ++i) Wn[i] = io.W[i * N + cs];
+    }
     const long long cf = col + PS * min(max(q - 1, 0), P.nz - 1);
 #pragma unroll
     for (int v = 0; v < NV; ++v) Ln[v] = io.lam0[cf + v * N];
@@ -1068,7 +1080,7 @@ __device__ __forceinline__ void adj_march_b(const Params& P, const AdjIOF& io, d
       lo[v] = Ln[v];
     }
 #pragma unroll
-    for (int i = 0; i < NW; ++i) w[i] = ghost >= 0 ? 0.0 : Wn[i];  // wall ghosts carry none
+    for (int i = 0; i < NW; ++i) w[i] = Wn[i];
 #pragma unroll
     for (int k = 0; k < 5; ++k) pv[k] = Vn[k];
     const bool fin = out && p - 1 >= z0 && p - 1 < z1;
@@ -1224,8 +1236,9 @@ __global__ void __launch_bounds__(EX* EY) k_adjf_b(Params P, AdjIOF io) {
   const double lx = dt / P.dx[0], ly = dt / P.dx[1], lz = dt / P.dx[2];
   const long long total = (long long)io.ntx * io.nty * P.nz;
   const int G = gridDim.x, b = blockIdx.x;
-  long long cur = total * b / G;
-  const long long stop = total * (b + 1) / G;
+  const int lw = xcd_share(b, G);
+  long long cur = total * lw / G;
+  const long long stop = total * (lw + 1) / G;
   while (cur < stop) {
     const int tile = (int)(cur / P.nz);
     const int z0 = (int)(cur % P.nz);
@@ -1272,7 +1285,7 @@ static hipError_t adjf_t(const Params& P, const double* Un, const double* lam1, 
   // B: + acoustic face-solver terms
   io.ntx = (P.nx + AF_BX - 3) / (AF_BX - 2);
   io.nty = (P.ny + AF_BY - 3) / (AF_BY - 2);
-  g = adjf_groups(P, AF_BX, AF_BY, 1, 2);
+  g = adjf_groups(P, AF_BX, AF_BY, 1, 1);
   hipLaunchKernelGGL((k_adjf_b<LM, AF_BX, AF_BY>), dim3((unsigned)g), dim3(AF_BX * AF_BY), 0, s, P, io);
   return hipGetLastError();
 }
