@@ -1044,6 +1044,11 @@ __device__ __forceinline__ void adj_march_b(const Params& P, const AdjIOF& io, d
   constexpr int NW = AF_PV;
   double Un[NV], Wn[NW], Ln[NV], Vn[5];
   int ghn;
+  // Halo positions load only what they publish or use (U; L, A_mx, A_my,
+  // A_E; the (u*, Pi*) adjoints of the lateral face they own): the rest is
+  // read by output cells only.  The loads land one trip later, so the lanes
+  // that skip them leave registers that are never read.
+  const bool hx = !out && px == 0, hy = !out && py == 0;  // owners of an output's -x / -y face
   auto load = [&](int q) __attribute__((always_inline)) {
     const int src = plane_src(P, q, ghn);
     const long long cs = col + PS * src;
@@ -1054,13 +1059,19 @@ __device__ __forceinline__ void adj_march_b(const Params& P, const AdjIOF& io, d
       for (int i = 0; i < NW; ++i) Wn[i] = 0.0;
     } else {
 #pragma unroll
-      for (int i = 0; i < NW; ++i) Wn[i] = io.W[i * N + cs];
+      for (int i = 0; i < NW; ++i) {
+        const bool need = out || i == AF_CB + 0 || i == AF_CB + 1 || i == AF_CB + 2 || i == AF_CB + 4 ||
+                          (hx && (i == AF_FB + 0 || i == AF_FB + 1)) || (hy && (i == AF_FB + 2 || i == AF_FB + 3));
+        Wn[i] = need ? io.W[i * N + cs] : 0.0;
+      }
     }
-    const long long cf = col + PS * min(max(q - 1, 0), P.nz - 1);
+    if (out) {
+      const long long cf = col + PS * min(max(q - 1, 0), P.nz - 1);
 #pragma unroll
-    for (int v = 0; v < NV; ++v) Ln[v] = io.lam0[cf + v * N];
+      for (int v = 0; v < NV; ++v) Ln[v] = io.lam0[cf + v * N];
 #pragma unroll
-    for (int k = 0; k < 5; ++k) Vn[k] = io.W[(AF_PV + k) * N + cf];
+      for (int k = 0; k < 5; ++k) Vn[k] = io.W[(AF_PV + k) * N + cf];
+    }
   };
   Prim<3> q1 = Prim<3>{};
   double U1[NV] = {0, 0, 0, 0, 0};
