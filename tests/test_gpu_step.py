@@ -307,12 +307,19 @@ def test_full_size_256cubed_100_steps_from_init(A):
     t_gpu = S.t.item()
     del S
     say("256^3 x 100 oracle (threads=%d)" % O.num_threads())
-    r = O.run(cfg, O.init(cfg, prob, prm, seed), 100)
-    assert r["status"] == 0
-    np.testing.assert_allclose(log.cpu().numpy(), r["dt_log"][:100], rtol=1e-13)
-    assert abs(t_gpu - r["t"]) <= 1e-13 * r["t"]
-    err = close(cfg, U, r["U"])
-    say("256^3 x 100 max rel err", err, "bitwise", bitwise(U, r["U"]))
+    # ten runs of ten steps (each step's dt from its own state, as in one
+    # run of 100), reporting progress: the oracle takes minutes here
+    Uo, t, dts = O.init(cfg, prob, prm, seed), 0.0, []
+    for k in range(10):
+        r = O.run(cfg, Uo, 10, t0=t)
+        assert r["status"] == 0
+        Uo, t = r["U"], r["t"]
+        dts.append(r["dt_log"])
+        say("oracle steps", 10 * (k + 1), "t", t)
+    np.testing.assert_allclose(log.cpu().numpy(), np.concatenate(dts), rtol=1e-13)
+    assert abs(t_gpu - t) <= 1e-13 * t
+    err = close(cfg, U, Uo)
+    say("256^3 x 100 max rel err", err, "bitwise", bitwise(U, Uo))
     assert err <= 1e-12
 
 
@@ -333,11 +340,17 @@ def test_gresho_1024_full_size(A, lm):
     torch.cuda.synchronize()
     U = S.numpy()
     say("gresho 1024 lm", lm, "oracle x 1000 (threads=%d)" % O.num_threads())
-    r = O.run(cfg, O.init(cfg, prob, prm, seed), 1000)
-    assert r["status"] == 0
-    np.testing.assert_allclose(log.cpu().numpy(), r["dt_log"][:1000], rtol=1e-13)
-    err = close(cfg, U, r["U"])
-    say("gresho 1024 lm", lm, "1000 steps max rel err", err, "bitwise", bitwise(U, r["U"]))
+    # ten runs of 100 steps with progress (each step's dt from its own state)
+    Uo, t, dts = O.init(cfg, prob, prm, seed), 0.0, []
+    for k in range(10):
+        r = O.run(cfg, Uo, 100, t0=t)
+        assert r["status"] == 0
+        Uo, t = r["U"], r["t"]
+        dts.append(r["dt_log"])
+        say("oracle steps", 100 * (k + 1), "t", t)
+    np.testing.assert_allclose(log.cpu().numpy(), np.concatenate(dts), rtol=1e-13)
+    err = close(cfg, U, Uo)
+    say("gresho 1024 lm", lm, "1000 steps max rel err", err, "bitwise", bitwise(U, Uo))
     assert err <= 1e-12
     S.step(4000)
     d = S.diagnostics()
