@@ -436,7 +436,7 @@ __device__ __forceinline__ void adj_march_a(const Params& P, const AdjIOF& io, d
 
     // ======================= phase 2 =======================================
     // acoustic cell values of plane p-1 (forward)
-    const bool doL = (p - 1 >= z0 - 1) && (p - 1 <= z1) && needL;
+    const bool doL = (p - 1 >= z0 - 1) && (p - 1 <= z1);
     if (doL) {
       const double usxm = sm[(LA_F + 0) * NPOS + pxm];
       const double pixm = sm[(LA_F + 1) * NPOS + pxm];
@@ -473,7 +473,7 @@ __device__ __forceinline__ void adj_march_a(const Params& P, const AdjIOF& io, d
     double btb1[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) btb1[v] = 0.0;
-    if (out && p - 1 >= z0 && p - 1 < z1) {
+    if (p - 1 >= z0 && p - 1 < z1) {
       const double usxm = sm[(LA_F + 0) * NPOS + pxm];
       if (!(usxm >= 0.0)) {
 #pragma unroll
@@ -505,7 +505,7 @@ __device__ __forceinline__ void adj_march_a(const Params& P, const AdjIOF& io, d
     sm[(LA_F + 1) * NPOS + tid] = Fn[1];
     sm[(LA_F + 2) * NPOS + tid] = Fn[3];
     sm[(LA_F + 3) * NPOS + tid] = Fn[4];
-    if (out) {
+    {
       // transport reverse of the own +x / +y faces of plane p-1
       const int m = p - 1;
       if (m >= z0 && m < z1) {
@@ -533,8 +533,10 @@ __device__ __forceinline__ void adj_march_a(const Params& P, const AdjIOF& io, d
 #pragma unroll
             for (int v = 0; v < NV; ++v) btb1[v] += Gb[v] * us;
           }
-          io.W[(AF_FB + 2 * dir + 0) * N + cell] = usb;
-          io.W[(AF_FB + 2 * dir + 1) * N + cell] = pib;
+          if (out) {
+            io.W[(AF_FB + 2 * dir + 0) * N + cell] = usb;
+            io.W[(AF_FB + 2 * dir + 1) * N + cell] = pib;
+          }
         }
       }
       // transport reverse of the vertical face (p-2 | p-1)
@@ -561,7 +563,7 @@ __device__ __forceinline__ void adj_march_a(const Params& P, const AdjIOF& io, d
             for (int v = 0; v < NV; ++v) btb1[v] += Gb[v] * zAus;
           }
         }
-        if (p - 2 >= z0 && p - 2 < z1) {
+        if (out && p - 2 >= z0 && p - 2 < z1) {
           const long long cell = col + PS * (p - 2);
           io.W[(AF_FB + 4) * N + cell] = usb;
           io.W[(AF_FB + 5) * N + cell] = pib;
@@ -582,14 +584,16 @@ __device__ __forceinline__ void adj_march_a(const Params& P, const AdjIOF& io, d
         // A_mz = lam_z ((Pi+ - Pi-) - S-bar); the update adds lam_z S-bar to m_z
         const double sbb = -lz * Ab[3] + lz * l2[3];
         const long long cell = col + PS * (p - 2);
-        io.W[(AF_CB + 0) * N + cell] = Lb;
-        io.W[(AF_CB + 1) * N + cell] = Ab[1];
-        io.W[(AF_CB + 2) * N + cell] = Ab[2];
-        io.W[(AF_CB + 3) * N + cell] = Ab[3];
-        io.W[(AF_CB + 4) * N + cell] = Ab[4];
-        io.W[(AF_CB + 5) * N + cell] = sbb;
+        if (out) {
+          io.W[(AF_CB + 0) * N + cell] = Lb;
+          io.W[(AF_CB + 1) * N + cell] = Ab[1];
+          io.W[(AF_CB + 2) * N + cell] = Ab[2];
+          io.W[(AF_CB + 3) * N + cell] = Ab[3];
+          io.W[(AF_CB + 4) * N + cell] = Ab[4];
+          io.W[(AF_CB + 5) * N + cell] = sbb;
 #pragma unroll
-        for (int v = 0; v < NV; ++v) io.lam0[cell + v * N] = l2[v] + consb[v];
+          for (int v = 0; v < NV; ++v) io.lam0[cell + v * N] = l2[v] + consb[v];
+        }
       }
     }
     // rotate the vertical window
@@ -736,7 +740,7 @@ __device__ __forceinline__ void adj_march_v(const Params& P, const AdjIOF& io, d
     for (int i = 0; i < 20; ++i) Mo[i] = 0.0;
     // tangential differences of plane p-1 (vertical faces)
     double dX1[4] = {0.0, 0.0, 0.0, 0.0};
-    if (visZ) {
+    {
       dX1[0] = sm[(LV_V + 0) * NPOS + pxp] - sm[(LV_V + 0) * NPOS + pxm];
       dX1[1] = sm[(LV_V + 2) * NPOS + pxp] - sm[(LV_V + 2) * NPOS + pxm];
       dX1[2] = sm[(LV_V + 1) * NPOS + pyp] - sm[(LV_V + 1) * NPOS + pym];
@@ -748,7 +752,7 @@ __device__ __forceinline__ void adj_march_v(const Params& P, const AdjIOF& io, d
     const bool own_m = out && m >= z0 && m < z1;
 #pragma unroll
     for (int dir = 0; dir < 2; ++dir) {
-      if (!(latV && (dir == 0 ? visX : visY))) continue;
+      if (!latV) continue;
       const int nb = dir == 0 ? pxp : pyp;
       const double lam_a = dir == 0 ? lx : ly;
       double Gb[NV];
@@ -803,7 +807,7 @@ __device__ __forceinline__ void adj_march_v(const Params& P, const AdjIOF& io, d
       }
     }
     // vertical face (p-2 | p-1)
-    if ((p - 1 >= z0) && (p - 1 <= z1) && visZ) {
+    if ((p - 1 >= z0) && (p - 1 <= z1)) {
       double Gb[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v) Gb[v] = lz * (nb1[v] - nbar_v(P, v, phi2, l2));
@@ -848,7 +852,7 @@ __device__ __forceinline__ void adj_march_v(const Params& P, const AdjIOF& io, d
     __syncthreads();  // ------------------------------------------- bar 2
 
     // ======================= phase 3 =======================================
-    if (out) {
+    {
       // normal parts of the -x / -y faces of plane p-1
 #pragma unroll
       for (int i = 0; i < 4; ++i) vbB[i] += sm[(LV_MX + i) * NPOS + pxm] + sm[(LV_MY + i) * NPOS + pym];
@@ -929,11 +933,13 @@ __device__ __forceinline__ void adj_march_v(const Params& P, const AdjIOF& io, d
           pb[3] += gcar[3];
           pb[8] += gcar[4];
         }
-        io.W[(AF_PV + 0) * N + cell] = pb[0];
-        io.W[(AF_PV + 1) * N + cell] = pb[1];
-        io.W[(AF_PV + 2) * N + cell] = pb[2];
-        io.W[(AF_PV + 3) * N + cell] = pb[3];
-        io.W[(AF_PV + 4) * N + cell] = pb[8];
+        if (out) {
+          io.W[(AF_PV + 0) * N + cell] = pb[0];
+          io.W[(AF_PV + 1) * N + cell] = pb[1];
+          io.W[(AF_PV + 2) * N + cell] = pb[2];
+          io.W[(AF_PV + 3) * N + cell] = pb[3];
+          io.W[(AF_PV + 4) * N + cell] = pb[8];
+        }
       }
     }
     // rotate the vertical window
