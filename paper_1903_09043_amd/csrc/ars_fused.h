@@ -215,13 +215,12 @@ __device__ __forceinline__ void march_tile(const Params& P, const double* __rest
       for (int k = 0; k < DIM; ++k) sm[(Ly::DZ + k) * NPOS + tid] = q0.u[k] - u2[k];
     }
     // Step 2a needs only the -x/-y faces of plane p-1 (published before the
-    // previous barrier) and this column's z faces, so it may run before or
-    // after bar 1.  3D runs it after bar 1 and publishes F behind a second
-    // barrier (this balances the work between barriers against the
-    // halo-only waves); 2D runs it before bar 1 and needs no second barrier
-    // (both orders measured on both).
-    constexpr bool EARLY_L = (DIM == 2);
-    if constexpr (!EARLY_L) plane_sync<DIM>();  // ------------------------ bar 1
+    // previous barrier) and this column's z faces, so it runs before bar 1,
+    // and F of plane p is published after bar 1, when every reader of F of
+    // plane p-1 has passed it: two barriers per plane.  (With the stages on
+    // every lane this is 1 % faster in 3D than running step 2a after bar 1
+    // and publishing F behind a third barrier, which was the faster order
+    // while 3D guarded its stages per position.)
 
     // ================= step 2a: acoustic cell values of plane p-1 ===========
     const bool doL = (p - 1 >= z0 - 1) && (p - 1 <= z1);
@@ -278,7 +277,7 @@ __device__ __forceinline__ void march_tile(const Params& P, const double* __rest
         badcell = min(badcell, cell);
       }
     }
-    if constexpr (EARLY_L) plane_sync<DIM>();  // ------------------------- bar 1
+    plane_sync<DIM>();  // ------------------------------------------------ bar 1
 
     // ================= step 2b: own lateral acoustic faces of plane p =======
     double Fn[3 * (DIM - 1)];
@@ -295,7 +294,6 @@ __device__ __forceinline__ void march_tile(const Params& P, const double* __rest
 #pragma unroll
       for (int i = 0; i < 3 * (DIM - 1); ++i) Fn[i] = 0.0;
     }
-    if constexpr (!EARLY_L) plane_sync<DIM>();  // ----------------------- bar 1b
 
     // ================= step 3 ==============================================
 #pragma unroll

@@ -15,7 +15,7 @@
 //      B   transported values b~ of plane p-1
 //      GX  own +x/+y total face fluxes of plane p-1
 //    Per plane: faces at p, acoustic cell values at p-1, fluxes at p-1 and
-//    the update of plane p-2; 3 barriers in 3D, 2 in the 2D row segments.
+//    the update of plane p-2; 2 barriers per plane.
 //  * Every face is evaluated once; the only HBM traffic is the read of U^n
 //    and the write of U^{n+1} (plus halo re-reads that hit L2).
 //  * Epilogue: the rate of the NEW state for the next CFL time step is
