@@ -223,11 +223,13 @@ def imex_leg(torch, A, W, n=1024, Ma=1e-3, expl_steps=5000, tol=1e-10):
             "unknowns": 3 * n * n}
 
 
-def adjoint_leg(torch, A, W, nsteps=200, slots=16, reps=20, end_to_end=True):
-    """Adjoint/forward ratio on the 3D RB 128^3 workload: per step (one
-    adjoint step vs one fused step, both warm, median of `reps`) and end to
-    end (full gradient: forward, recomputation by the revolve plan and the
-    adjoint sweep, over the forward run alone)."""
+def adjoint_leg(torch, A, W, nsteps=200, slots=16, reps=10, end_to_end=True, k=20):
+    """Adjoint/forward ratio on the 3D RB 128^3 workload: per step (k
+    consecutive adjoint steps vs k consecutive fused steps at the same
+    frozen dt, each sequence warm and timed as a whole, median of `reps`,
+    divided by k: both sides carry their launches, neither a copy) and end
+    to end (full gradient: forward, recomputation by the revolve plan and
+    the adjoint sweep, over the forward run alone)."""
     from paper_1903_09043_amd.adjoint import RBProblem, rb_kinetic_energy
     cfg, prob, prm, seed = W.rb3d_ra1e5()
     pb = RBProblem(cfg, prob, prm, nsteps, slots)
@@ -241,12 +243,17 @@ def adjoint_leg(torch, A, W, nsteps=200, slots=16, reps=20, end_to_end=True):
     lam_n = torch.empty_like(lam)
     pg = torch.zeros(2, dtype=torch.float64, device="cuda")
     U0 = S.U.clone()
-    S.step_adjoint(U0, lam, dt, lam_n=lam_n, param_grad=pg)
-    S.step_sched(dt)
+    dtk = dt.reshape(1).repeat(k).contiguous()  # k steps at the same dt (an even count: no copy back)
+
+    def adjoint_k():
+        for _ in range(k):
+            S.step_adjoint(U0, lam, dt, lam_n=lam_n, param_grad=pg)
+    adjoint_k()
+    S.step_sched(dtk)
     fwd, adj = [], []
     for _ in range(reps):
-        fwd.append(timed(torch, lambda: S.step_sched(dt)))
-        adj.append(timed(torch, lambda: S.step_adjoint(U0, lam, dt, lam_n=lam_n, param_grad=pg)))
+        fwd.append(timed(torch, lambda: S.step_sched(dtk)) / k)
+        adj.append(timed(torch, adjoint_k) / k)
     fwd.sort()
     adj.sort()
     f_ms, a_ms = fwd[reps // 2], adj[reps // 2]
