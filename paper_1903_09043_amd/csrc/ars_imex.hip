@@ -23,7 +23,9 @@
 // GPU layout: the reference step's padded workspace (primitives, explicit
 // faces for a, S, theta, then the implicit faces, L, b~, fluxes), padded
 // extensions of Pi and of the velocities it gives, and the vectors of an
-// unpreconditioned BiCGSTAB on the N unknowns Pi.  The operator is applied
+// unpreconditioned Krylov solver on the N unknowns Pi: conjugate gradients
+// when every side is periodic (the operator is then symmetric positive
+// definite), BiCGSTAB otherwise.  The operator is applied
 // matrix-free: one kernel extends Pi to the ghost cells, one forms the
 // velocities of every padded cell from the Pi* of its two faces per axis
 // (ghosts by the boundary rules), one forms every row from the u* of the
@@ -45,9 +47,13 @@ namespace ars {
 namespace {
 
 constexpr int DOT_BLOCKS = 1024;
+constexpr int CG_BLOCKS = 1024;  // blocks of the CG kernels (<= the partial-sum slots)
 constexpr int BS = 256;
+constexpr int CG_CHECK = 16;  // CG iterations between host reads of the residual
 // scalar slots of the iteration
-enum { SC_RHO_OLD = 0, SC_ALPHA, SC_OMEGA, SC_RHO_NEW, SC_RV, SC_TS, SC_TT, SC_RR, SC_BB, SC_N = 16 };
+enum { SC_RHO_OLD = 0, SC_ALPHA, SC_OMEGA, SC_RHO_NEW, SC_RV, SC_TS, SC_TT, SC_RR, SC_BB,
+       SC_CG_RR,      // (r, r) of CG iterations 0, 2, 4, ... (SC_CG_RR + 1: 1, 3, 5, ...)
+       SC_CG_CHK = 11, SC_N = 16 };
 
 struct ImexLayout {
   RefGrid G;
@@ -62,7 +68,7 @@ struct ImexLayout {
   double* sv;
   double* t;
   double* b;
-  double* part;     // DOT_BLOCKS partial sums
+  double* part;     // partial sums (one per block of a reduction; CG: two sets)
   double* sc;       // scalars
 };
 
@@ -88,7 +94,7 @@ ImexLayout layout_of(const Params& P, void* work) {
   L.sv = take(L.n);
   L.t = take(L.n);
   L.b = take(L.n);
-  L.part = take(DOT_BLOCKS);
+  L.part = take(2 * (CG_BLOCKS > DOT_BLOCKS ? CG_BLOCKS : DOT_BLOCKS));
   L.sc = take(SC_N);
   return L;
 }
@@ -395,6 +401,171 @@ __global__ void k_bicg_scalars(double* __restrict__ sc) {
   }
 }
 
+// Conjugate gradients (every side periodic: the eliminated operator is
+// symmetric positive definite, diag(1/(rho c^2)) + lambda^2 K^T tau K +
+// lambda G^T (1/(2a)) G with K the central difference of the two face
+// averages and G the face difference; walls and outflow copies break the
+// symmetry and keep BiCGSTAB).  With no ghost rule left but the periodic
+// image, the operator is a star stencil of radius 2 on the unknowns, so an
+// iteration is two streaming kernels: (1) p = r + beta p_old and q = A p
+// on the fly (p_old and r read with periodic wrap), with the block sums of
+// (p, q); (2) x += alpha p, r -= alpha q, with those of (r, r).  Each
+// kernel starts by adding the other's block sums itself, every block in the
+// same fixed order (so every block forms the same alpha or beta bit for bit,
+// and no one-block launch sits between them).  A last-block-arrives
+// reduction would need device-scope fences (one per block, an L2 write-back
+// each on a part whose XCDs have L2s of their own), which cost far more.
+
+// Coefficients of the homogeneous operator per interior cell: tau, 1/(rho c)
+// and 1/(rho c^2) (the rows' scale), out of the padded workspace.
+template <int DIM>
+__global__ void k_cg_coef(Params P, RefGrid G, const double* __restrict__ W, double* __restrict__ tau,
+                          double* __restrict__ irc, double* __restrict__ irc2) {
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= P.ncell) return;
+  const int cx = (int)(c % P.nx);
+  const long long rr = c / P.nx;
+  const int cy = (int)(rr % P.ny);
+  const int cz = (int)(rr / P.ny);
+  const long long q = G.pad(cx + 2, DIM == 3 ? cy + 2 : 0, cz + 2);
+  const long long n = G.npad;
+  tau[c] = W[R_R * n + q];
+  irc[c] = W[R_IRC * n + q];
+  irc2[c] = 1.0 / (W[R_RC * n + q] * W[R_C * n + q]);
+}
+
+// Index offsets of the periodic neighbours k - 2, k - 1, k + 1, k + 2 of
+// coordinate k on an axis of m >= 2 cells and stride st.
+__device__ __forceinline__ void wrap_offsets(int k, int m, int st, int& om2, int& om1, int& op1, int& op2) {
+  om2 = (k >= 2 ? -2 : m - 2) * st;
+  om1 = (k >= 1 ? -1 : m - 1) * st;
+  op1 = (k + 1 < m ? 1 : 1 - m) * st;
+  op2 = (k + 2 < m ? 2 : 2 - m) * st;
+}
+
+// Block sum of s in a fixed order (a butterfly within each wave, then the
+// waves' sums in order); every thread gets it.  The caller separates two
+// calls with a barrier.
+__device__ __forceinline__ double block_sum(double s) {
+  __shared__ double sh[BS / 64];
+#pragma unroll
+  for (int m = 32; m > 0; m >>= 1) s = s + __shfl_xor(s, m, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+  __syncthreads();
+  double t = sh[0];
+#pragma unroll
+  for (int w = 1; w < BS / 64; ++w) t = t + sh[w];
+  return t;
+}
+
+// Sum of a reduction's block sums in a fixed order, in one block (thread 0
+// holds it).
+__device__ __forceinline__ double sum_parts(const double* __restrict__ part, int nb) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nb; i += BS) s = s + part[i];
+  return block_sum(s);
+}
+
+// Work units of k_cg_apply: a row of x cells (fixed y, z) cut into chunks
+// of BS; each block takes a contiguous run of units, and the runs of the
+// blocks one XCD receives (blocks go to the XCDs in turn) are contiguous, so
+// the rows a row's stencil reaches are mostly read through the same L2.
+// Cell indices are 32-bit (the host takes this path below 2^31 cells).
+template <int DIM>
+__global__ __launch_bounds__(BS) void k_cg_apply(Params P, const double* __restrict__ d_dt, const double* __restrict__ r,
+                                                 const double* __restrict__ pold, double* __restrict__ pnew,
+                                                 const double* __restrict__ tau, const double* __restrict__ irc,
+                                                 const double* __restrict__ irc2, double* __restrict__ q,
+                                                 const double* __restrict__ part_rr, double* __restrict__ part_pq,
+                                                 double* __restrict__ sc, int it) {
+  // beta = (r, r) / (r, r) of the previous iteration (0 in the first);
+  // every block adds the block sums of (r, r) in the same order
+  double beta = 0.0;
+  if (it > 0) {
+    const double rr = sum_parts(part_rr, gridDim.x);
+    const double old = sc[SC_CG_RR + ((it - 1) & 1)];
+    beta = old != 0.0 ? rr / old : 0.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) sc[SC_CG_RR + (it & 1)] = rr;
+    __syncthreads();
+  }
+  const double dt = *d_dt;
+  const int axes[3] = {0, DIM == 3 ? 1 : 2, 2};
+  const int ext[3] = {P.nx, P.ny, P.nz};
+  const int str[3] = {1, P.nx, P.nx * P.ny};
+  double lam[DIM];
+#pragma unroll
+  for (int t = 0; t < DIM; ++t) lam[t] = dt / P.dx[axes[t]];
+  const double hK = P.hK;
+  const int nch = (P.nx + BS - 1) / BS;
+  const int units = P.ny * P.nz * nch;
+  const unsigned G = gridDim.x, b = blockIdx.x;
+  const unsigned lw = (G % 8 == 0) ? (b % 8) * (G / 8) + b / 8 : b;
+  const int u0 = (int)((long long)units * lw / G), u1 = (int)((long long)units * (lw + 1) / G);
+  double s = 0.0;
+  for (int u = u0; u < u1; ++u) {
+    const int row = u / nch;
+    const int cx = (u - row * nch) * BS + (int)threadIdx.x;
+    if (cx >= P.nx) continue;
+    const int crd[3] = {cx, DIM == 3 ? row % P.ny : 0, DIM == 3 ? row / P.ny : row};
+    const int c = row * P.nx + cx;
+    const double P0 = r[c] + beta * pold[c];
+    const double t0 = tau[c], i0 = irc[c];
+    double div = 0.0;
+#pragma unroll
+    for (int t = 0; t < DIM; ++t) {
+      const int a = axes[t];
+      int om2, om1, op1, op2;
+      wrap_offsets(crd[a], ext[a], str[a], om2, om1, op1, op2);
+      const double Pm2 = r[c + om2] + beta * pold[c + om2];
+      const double Pm1 = r[c + om1] + beta * pold[c + om1];
+      const double Pp1 = r[c + op1] + beta * pold[c + op1];
+      const double Pp2 = r[c + op2] + beta * pold[c + op2];
+      // velocities of the cells c - e, c, c + e: u = -lambda tau [Pi*],
+      // [Pi*] = (Pi_{+1} - Pi_{-1}) / 2 of the cell's neighbours
+      const double um = -(lam[t] * tau[c + om1]) * (0.5 * (P0 - Pm2));
+      const double uc = -(lam[t] * t0) * (0.5 * (Pp1 - Pm1));
+      const double up = -(lam[t] * tau[c + op1]) * (0.5 * (Pp2 - P0));
+      // u* of the faces c - e | c and c | c + e
+      const double usm = 0.5 * (um + uc) - (P0 - Pm1) * (hK * dmin2(irc[c + om1], i0));
+      const double usp = 0.5 * (uc + up) - (Pp1 - P0) * (hK * dmin2(i0, irc[c + op1]));
+      div = div + lam[t] * (usp - usm);
+    }
+    const double y = P0 * irc2[c] + div;
+    pnew[c] = P0;
+    q[c] = y;
+    s = s + P0 * y;
+  }
+  const double tot = block_sum(s);
+  if (threadIdx.x == 0) part_pq[blockIdx.x] = tot;
+}
+
+// alpha = (r, r) / (p, q), every block adding the block sums of (p, q) in
+// the same order; then x += alpha p, r -= alpha q and the block sums of
+// the new (r, r).
+__global__ __launch_bounds__(BS) void k_cg_xr(long long n, const double* __restrict__ p, const double* __restrict__ q,
+                                              double* __restrict__ x, double* __restrict__ r,
+                                              const double* __restrict__ part_pq, double* __restrict__ part_rr,
+                                              const double* __restrict__ sc, int it) {
+  const double pq = sum_parts(part_pq, gridDim.x);
+  const double alpha = pq != 0.0 ? sc[SC_CG_RR + (it & 1)] / pq : 0.0;
+  __syncthreads();
+  double s = 0.0;
+  for (long long i = (long long)blockIdx.x * BS + threadIdx.x; i < n; i += (long long)gridDim.x * BS) {
+    x[i] = x[i] + alpha * p[i];
+    const double ri = r[i] - alpha * q[i];
+    r[i] = ri;
+    s = s + ri * ri;
+  }
+  const double tot = block_sum(s);
+  if (threadIdx.x == 0) part_rr[blockIdx.x] = tot;
+}
+
+// (r, r) of the last iteration, for the host's convergence test.
+__global__ __launch_bounds__(BS) void k_cg_check(const double* __restrict__ part_rr, int nb, double* __restrict__ sc) {
+  const double rr = sum_parts(part_rr, nb);
+  if (threadIdx.x == 0) sc[SC_CG_CHK] = rr;
+}
+
 // x0 = p^n of every interior cell.
 template <int DIM>
 __global__ void k_imex_x0(Params P, RefGrid G, const double* __restrict__ W, double* __restrict__ x) {
@@ -505,6 +676,63 @@ struct Imex {
     return hipGetLastError() == hipSuccess ? ARS_OK : ARS_EDEVICE;
   }
 
+  // Conjugate gradients on the same system (every side periodic).  The
+  // BiCGSTAB-only vectors hold the coefficients (rh: tau, sv: 1/(rho c),
+  // t: 1/(rho c^2)) and b, once the first residual is formed, the second p.
+  int solve_cg(double tol, int max_iter, int* its) {
+    const unsigned nb = nblk(L.n);
+    const unsigned gb = nb < (unsigned)CG_BLOCKS ? nb : (unsigned)CG_BLOCKS;
+    hipLaunchKernelGGL(k_fill0, dim3(nb), dim3(BS), 0, s, L.n, L.t);
+    if (apply(L.t, L.b, 1) != hipSuccess) return ARS_EDEVICE;
+    hipLaunchKernelGGL(k_neg, dim3(nb), dim3(BS), 0, s, L.n, L.b);
+    hipLaunchKernelGGL(k_imex_x0<DIM>, dim3(nblk(P.ncell)), dim3(BS), 0, s, P, L.G, L.W, L.x);
+    if (apply(L.x, L.r, 0) != hipSuccess) return ARS_EDEVICE;
+    // r = b - A x0 (also clears p and v, and copies r to rh, overwritten next)
+    hipLaunchKernelGGL(k_bicg_start, dim3(nb), dim3(BS), 0, s, L.n, L.b, L.r, L.rh, L.p, L.v, L.sc);
+    dot(L.b, L.b, SC_BB);
+    double bb = 0.0;
+    if (read(SC_BB, &bb) != ARS_OK) return ARS_EDEVICE;
+    const double target = tol * tol * (bb > 0.0 ? bb : 1.0);
+    dot(L.r, L.r, SC_RR);
+    double rr0 = 0.0;
+    if (read(SC_RR, &rr0) != ARS_OK) return ARS_EDEVICE;
+    if (!std::isfinite(rr0)) return ARS_ENOCONV;
+    if (rr0 <= target) {
+      if (its) *its = 0;
+      return ARS_OK;
+    }
+    hipLaunchKernelGGL(k_cg_coef<DIM>, dim3(nblk(P.ncell)), dim3(BS), 0, s, P, L.G, L.W, L.rh, L.sv, L.t);
+    dot(L.r, L.r, SC_CG_RR);  // (r, r) of iteration 0
+    double* const part_pq = L.part;
+    double* const part_rr = L.part + (CG_BLOCKS > DOT_BLOCKS ? CG_BLOCKS : DOT_BLOCKS);
+    double* pv[2] = {L.p, L.b};  // p = 0 on entry, so the first p is r
+    int it = 0;
+    for (; it < max_iter; ++it) {
+      double* po = pv[it & 1];
+      double* pn = pv[(it + 1) & 1];
+      hipLaunchKernelGGL(k_cg_apply<DIM>, dim3(gb), dim3(BS), 0, s, P, d_dt, L.r, po, pn, L.rh, L.sv, L.t, L.v,
+                         part_rr, part_pq, L.sc, it);
+      hipLaunchKernelGGL(k_cg_xr, dim3(gb), dim3(BS), 0, s, L.n, pn, L.v, L.x, L.r, part_pq, part_rr, L.sc, it);
+      if (it % CG_CHECK == CG_CHECK - 1 || it + 1 == max_iter) {
+        hipLaunchKernelGGL(k_cg_check, dim3(1), dim3(BS), 0, s, part_rr, (int)gb, L.sc);
+        double rr = 0.0;
+        if (read(SC_CG_CHK, &rr) != ARS_OK) return ARS_EDEVICE;
+        if (!std::isfinite(rr)) return ARS_ENOCONV;
+        if (rr <= target) {
+          ++it;
+          break;
+        }
+      }
+    }
+    if (its) *its = it;
+    if (it >= max_iter) {
+      double rr = 0.0;
+      if (read(SC_CG_CHK, &rr) != ARS_OK) return ARS_EDEVICE;
+      if (!(rr <= target)) return ARS_ENOCONV;
+    }
+    return hipGetLastError() == hipSuccess ? ARS_OK : ARS_EDEVICE;
+  }
+
   // The rest of the step with the implicit faces of x.
   hipError_t finish(double* Uout, Control* ctl) {
     const unsigned np = nblk(L.G.npad);
@@ -530,7 +758,7 @@ size_t imex_workspace_bytes(const Params& P) {
   auto al = [](size_t b) { return ((b + 255) / 256) * 256; };
   size_t s = al((size_t)R_NFIELD * G.npad * sizeof(double)) + al((size_t)(P.dim + 1) * G.npad * sizeof(double));
   s += 8 * al((size_t)n * sizeof(double));
-  s += al(DOT_BLOCKS * sizeof(double)) + al(SC_N * sizeof(double));
+  s += al(2 * (CG_BLOCKS > DOT_BLOCKS ? CG_BLOCKS : DOT_BLOCKS) * sizeof(double)) + al(SC_N * sizeof(double));
   return s;
 }
 
@@ -545,7 +773,9 @@ static int imex_steps(const Params& P, double* d_state, double* d_tmp, Control* 
     M.d_dt = d_dt_sched + st;
     if (launch_ref_forward(P, src, M.L.W, M.d_dt, s) != hipSuccess) return ARS_EDEVICE;
     int its = 0;
-    const int rc = M.solve(tol, max_iter, &its);
+    const bool periodic = P.bcx[0] == BC_PERIODIC && P.bcz[0] == BC_PERIODIC && (DIM == 2 || P.bcy[0] == BC_PERIODIC) &&
+                          P.nx >= 2 && P.nz >= 2 && (DIM == 2 || P.ny >= 2) && P.ncell < (1LL << 31) - (long long)BS;
+    const int rc = periodic ? M.solve_cg(tol, max_iter, &its) : M.solve(tol, max_iter, &its);
     total += its;
     if (rc != ARS_OK) {
       if (h_iters) *h_iters = total;
