@@ -186,10 +186,13 @@ int ars_init_state_host(const ars_ctx* ctx, int problem, const double* params, i
  * ars_state_len()/(dim+2) doubles in the layout of one state variable.
  * d_u0 (nullable): device initial velocity, dim fields in the momentum
  * layout; NULL is rest, and then the state equals ars_init_state with the
- * SplitMix64 perturbation replaced by dT.  Builds the base on the host,
- * copies it to d_state and adds dT on the device (synchronous on
- * `stream`).  EINVAL for a configuration without walls on the vertical
- * axis or a NULL pointer. */
+ * SplitMix64 perturbation replaced by dT.  Forms the base density column
+ * (nz values) on the host, copies it to a device buffer the context owns
+ * (allocated on the first call, on the current device; freed by
+ * ars_destroy) and writes every cell on the device (synchronous on
+ * `stream`; calls on one context must not overlap).  EINVAL for a
+ * configuration without walls on the vertical axis or a NULL pointer,
+ * ENOMEM when the column buffer cannot be allocated. */
 int ars_init_rb_dT(ars_ctx* ctx, const double* params, int n_params, const double* d_dT, const double* d_u0,
                    double* d_state, void* stream);
 /* Transpose of the map dT -> U^0 of ars_init_rb_dT at the state it built:
@@ -238,6 +241,19 @@ int ars_step_noalloc(ars_ctx* ctx, double* d_state, int n_steps, double* d_t, do
  * *d_t advanced; *d_dt untouched. */
 int ars_step_sched(ars_ctx* ctx, double* d_state, double* d_tmp, void* d_work, int n_steps,
                    const double* d_dt_sched, double* d_t, void* stream);
+
+/* The same n_steps >= 1 steps out of place, with no copy: step 1 reads
+ * d_in (never written), the intermediate states alternate between the
+ * scratch states d_a and d_b (steps 1, 3, ... write d_a, steps 2, 4, ...
+ * d_b), and the last step writes d_out instead.  For a checkpointing
+ * schedule whose state lives in several buffers (the adjoint's revolve
+ * plan: restore, advance, store): the restore is a choice of d_in, the
+ * store a choice of d_out.  EINVAL for a NULL pointer, n_steps < 1,
+ * d_a == d_b, d_in equal to d_a or d_b, d_out equal to d_a or d_b, or
+ * d_out == d_in with n_steps == 1 (a step cannot run in place).
+ * Asynchronous; *d_t advanced. */
+int ars_step_sched_to(ars_ctx* ctx, const double* d_in, double* d_a, double* d_b, double* d_out, void* d_work,
+                      int n_steps, const double* d_dt_sched, double* d_t, void* stream);
 
 /* Implicit acoustic (IMEX) step: the further work named in the paper's
  * Conclusion (solve the acoustic part implicitly to lift the acoustic CFL

@@ -73,6 +73,45 @@ class RBProblem:
         return self.build(self._base, dT0).clone()
 
 
+def run_plan(S, plan, snaps, log, lam, lam_next, pg):
+    """Execute a revolve plan without state copies: the current state is
+    wherever it was last written (a snapshot or one of four scratch
+    states); a restore only selects its snapshot, an advance runs out of
+    place (ars_step_sched_to) with its last step written straight into the
+    snapshot a following store names, and the adjoint step reads the
+    current state in place.  lam and lam_next alternate; returns the one
+    that holds the last adjoint."""
+    # four scratch states: with the current state and the output among
+    # them, two remain for the advance's ping-pong
+    scratch = [S.U, S.tmp, torch.empty_like(S.U), torch.empty_like(S.U)]
+    cur = snaps[0]
+    i = 0
+    while i < len(plan):
+        op, step, arg = plan[i]
+        if op == OP_RESTORE:
+            cur = snaps[arg]
+        elif op == OP_ADVANCE and arg > step:
+            nxt = plan[i + 1] if i + 1 < len(plan) else None
+            out = None
+            if nxt is not None and nxt[0] == OP_STORE and (snaps[nxt[2]] is not cur or arg - step >= 2):
+                out = snaps[nxt[2]]
+                i += 1  # the store is this advance's last write
+            free = [b for b in scratch if b is not cur and b is not out]
+            if out is None:
+                out = free.pop()
+            S.step_sched_to(cur, out, free[0], free[1], log[step:arg])
+            cur = out
+        elif op == OP_STORE:
+            if snaps[arg] is not cur:
+                snaps[arg].copy_(cur)
+                cur = snaps[arg]
+        elif op == OP_ADJOINT:
+            S.step_adjoint(cur, lam, log[step:step + 1], lam_n=lam_next, param_grad=pg)
+            lam, lam_next = lam_next, lam
+        i += 1
+    return lam
+
+
 class _RBObjective(torch.autograd.Function):
     @staticmethod
     def forward(ctx, dT0, mu, kappa, problem):
@@ -108,16 +147,7 @@ class _RBObjective(torch.autograd.Function):
         lam = gradN * gJ.to(gradN.dtype)
         lam_next = torch.empty_like(lam)
         pg = torch.zeros(2, dtype=torch.float64, device=problem.device)
-        for op, step, arg in plan:
-            if op == OP_RESTORE:
-                S.U.copy_(snaps[arg])
-            elif op == OP_ADVANCE:
-                S.step_sched(log[step:arg])
-            elif op == OP_STORE:
-                snaps[arg].copy_(S.U)
-            elif op == OP_ADJOINT:
-                S.step_adjoint(S.U, lam, log[step:step + 1], lam_n=lam_next, param_grad=pg)
-                lam, lam_next = lam_next, lam
+        lam = run_plan(S, plan, snaps, log, lam, lam_next, pg)
         g_dT = S.init_rb_dT_adjoint(U0, lam)
         return g_dT, pg[0].reshape(()), pg[1].reshape(()), None
 

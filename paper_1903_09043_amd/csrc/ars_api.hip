@@ -96,28 +96,28 @@ ars::Control* ctl_of(void* w) { return (ars::Control*)w; }
 
 // U^0 of a Rayleigh-Benard base with a temperature perturbation field: the
 // density of d_state (the uploaded base) is kept, the energy is rebuilt from
-// the level's linear temperature (the formula of the host initial state).
+// the level's linear temperature (the formula of the host initial state);
+// rho of level k from the base column.
 template <int DIM>
-static __global__ void k_rb_dT(ars::Params P, double Tb, double Tt, double Lz, const double* __restrict__ dT,
-                        const double* __restrict__ u0, double* __restrict__ U) {
+static __global__ void k_rb_dT(ars::Params P, double Tb, double Tt, double Lz, const double* __restrict__ col,
+                               const double* __restrict__ dT, const double* __restrict__ u0, double* __restrict__ U) {
   const long long N = P.ncell;
   const long long plane = (long long)P.nx * P.ny;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (long long)gridDim.x * blockDim.x) {
     const int k = (int)(i / plane);
     const double zk = ((double)k + 0.5) * P.dx[2];
     const double T = Tb + (Tt - Tb) * (zk / Lz);
-    const double rho = U[i];
+    const double rho = col[k];
+    U[i] = rho;
     double E = (rho * (T + dT[i])) / P.gm1;
-    if (u0) {
-      double mm = 0.0;
+    double mm = 0.0;
 #pragma unroll
-      for (int a = 0; a < DIM; ++a) {
-        const double m = rho * u0[a * N + i];
-        U[(1 + a) * N + i] = m;
-        mm = mm + m * m;
-      }
-      E = E + (0.5 * mm) / rho;
+    for (int a = 0; a < DIM; ++a) {
+      const double m = u0 ? rho * u0[a * N + i] : 0.0;
+      U[(1 + a) * N + i] = m;
+      mm = mm + m * m;
     }
+    if (u0) E = E + (0.5 * mm) / rho;
     U[(DIM + 1) * N + i] = E;
   }
 }
@@ -223,7 +223,10 @@ int ars_create(const ars_config* cfg, ars_ctx** out) {
   return ARS_OK;
 }
 
-void ars_destroy(ars_ctx* c) { delete c; }
+void ars_destroy(ars_ctx* c) {
+  if (c && c->d_col) (void)hipFree(c->d_col);
+  delete c;
+}
 
 size_t ars_state_len(const ars_ctx* c) { return c ? c->len : 0; }
 
@@ -276,6 +279,31 @@ int ars_workspace_init(ars_ctx* c, void* d_work, void* stream) {
 }
 
 // -------------------------------------------------------------- init states
+// Column profile of the discrete hydrostatic equilibrium: linear T (or
+// T = 1), densities by the recursion of eq. well_balanced_formula with
+// p = rho T (r0: the bottom density, <= 0 for T_bottom; ignored when iso).
+static void hydrostatic_column(const ars_ctx* ctx, bool iso, double Tb, double Tt, double r0,
+                               std::vector<double>& Tcol, std::vector<double>& rcol) {
+  const ars_config& c = ctx->cfg;
+  const ars::Params& P = ctx->P;
+  const double dz = P.dx[2];
+  const double Lz = c.L[c.dim - 1];
+  auto phi = [&](int k) { return c.g * (((double)k + 0.5) * dz); };
+  Tcol.resize(P.nz);
+  rcol.resize(P.nz);
+  for (int k = 0; k < P.nz; ++k) {
+    const double zk = ((double)k + 0.5) * dz;
+    Tcol[k] = Tb + (Tt - Tb) * (zk / Lz);
+  }
+  if (iso) r0 = std::exp(-(c.g * (0.5 * dz)));
+  if (!(r0 > 0.0)) r0 = Tcol[0];
+  rcol[0] = r0;
+  for (int k = 1; k < P.nz; ++k) {
+    const double delta = phi(k) - phi(k - 1);
+    rcol[k] = (rcol[k - 1] * (Tcol[k - 1] - 0.5 * delta)) / (Tcol[k] + 0.5 * delta);
+  }
+}
+
 int ars_init_state_host(const ars_ctx* ctx, int problem, const double* prm, int nprm, uint64_t seed,
                         double* h) {
   if (!ctx || !h || (nprm > 0 && !prm) || nprm < 0) return ARS_EINVAL;
@@ -304,26 +332,12 @@ int ars_init_state_host(const ars_ctx* ctx, int problem, const double* prm, int 
     }
     case ARS_PROB_RB:
     case ARS_PROB_ISOTHERMAL: {
-      // Column profile of the discrete hydrostatic equilibrium: linear T
-      // (or T = 1), densities by the recursion of eq. well_balanced_formula
-      // with p = rho T.
       const bool iso = problem == ARS_PROB_ISOTHERMAL;
       const double Tb = iso ? 1.0 : param(0, 1.0);
       const double Tt = iso ? 1.0 : param(1, 0.5);
       const double amp = iso ? 0.0 : param(3, 0.0);
-      const double Lz = c.L[D - 1];
-      std::vector<double> Tcol(P.nz), rcol(P.nz);
-      for (int k = 0; k < P.nz; ++k) {
-        const double zk = ((double)k + 0.5) * dz;
-        Tcol[k] = Tb + (Tt - Tb) * (zk / Lz);
-      }
-      double r0 = iso ? std::exp(-(c.g * (0.5 * dz))) : param(2, -1.0);
-      if (!(r0 > 0.0)) r0 = Tcol[0];
-      rcol[0] = r0;
-      for (int k = 1; k < P.nz; ++k) {
-        const double delta = phi(k) - phi(k - 1);
-        rcol[k] = (rcol[k - 1] * (Tcol[k - 1] - 0.5 * delta)) / (Tcol[k] + 0.5 * delta);
-      }
+      std::vector<double> Tcol, rcol;
+      hydrostatic_column(ctx, iso, Tb, Tt, param(2, -1.0), Tcol, rcol);
       uint64_t st = seed;
       const long long plane = (long long)P.nx * P.ny;
       for (long long i = 0; i < N; ++i) {
@@ -408,16 +422,34 @@ int ars_init_rb_dT(ars_ctx* ctx, const double* prm, int nprm, const double* d_dT
   const ars_config& c = ctx->cfg;
   const int z = c.dim - 1;
   if (c.bc[z][0] != ARS_BC_WALL || c.bc[z][1] != ARS_BC_WALL) return ARS_EINVAL;
-  double base[4] = {1.0, 0.5, -1.0, 0.0};
+  double base[3] = {1.0, 0.5, -1.0};
   for (int i = 0; i < nprm && i < 3; ++i) base[i] = prm[i];
-  int rc = ars_init_state(ctx, ARS_PROB_RB, base, 4, 0, d_state, stream);
-  if (rc != ARS_OK) return rc;
+  std::vector<double> Tcol, rcol;
+  hydrostatic_column(ctx, false, base[0], base[1], base[2], Tcol, rcol);
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return ARS_EDEVICE;
+  if (ctx->d_col && ctx->d_col_dev != dev) {
+    (void)hipFree(ctx->d_col);
+    ctx->d_col = nullptr;
+  }
+  if (!ctx->d_col) {
+    if (hipMalloc((void**)&ctx->d_col, (size_t)ctx->P.nz * sizeof(double)) != hipSuccess) {
+      ctx->d_col = nullptr;
+      return ARS_ENOMEM;
+    }
+    ctx->d_col_dev = dev;
+  }
   hipStream_t s = (hipStream_t)stream;
+  if (hipMemcpyAsync(ctx->d_col, rcol.data(), (size_t)ctx->P.nz * sizeof(double), hipMemcpyHostToDevice, s) !=
+      hipSuccess)
+    return ARS_EDEVICE;
   const unsigned nb = flat_blocks(ctx->P.ncell);
   if (c.dim == 3)
-    hipLaunchKernelGGL(k_rb_dT<3>, dim3(nb), dim3(256), 0, s, ctx->P, base[0], base[1], c.L[z], d_dT, d_u0, d_state);
+    hipLaunchKernelGGL(k_rb_dT<3>, dim3(nb), dim3(256), 0, s, ctx->P, base[0], base[1], c.L[z], ctx->d_col, d_dT,
+                       d_u0, d_state);
   else
-    hipLaunchKernelGGL(k_rb_dT<2>, dim3(nb), dim3(256), 0, s, ctx->P, base[0], base[1], c.L[z], d_dT, d_u0, d_state);
+    hipLaunchKernelGGL(k_rb_dT<2>, dim3(nb), dim3(256), 0, s, ctx->P, base[0], base[1], c.L[z], ctx->d_col, d_dT,
+                       d_u0, d_state);
   if (hipGetLastError() != hipSuccess) return ARS_EDEVICE;
   return check(hipStreamSynchronize(s));
 }
@@ -491,6 +523,30 @@ int ars_step_sched(ars_ctx* ctx, double* d_state, double* d_tmp, void* d_work, i
   if (src != d_state) {
     if (hipMemcpyAsync(d_state, src, ctx->len * sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess)
       return ARS_EDEVICE;
+  }
+  return ARS_OK;
+}
+
+int ars_step_sched_to(ars_ctx* ctx, const double* d_in, double* d_a, double* d_b, double* d_out, void* d_work,
+                      int n, const double* d_dt_sched, double* d_t, void* stream) {
+  if (!ctx || !d_in || !d_a || !d_b || !d_out || !d_work || !d_dt_sched || n < 1 || d_a == d_b || d_in == d_a ||
+      d_in == d_b || d_out == d_a || d_out == d_b || (n == 1 && d_out == d_in))
+    return ARS_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  ars::Control* ctl = ctl_of(d_work);
+  const double* src = d_in;
+  for (int st = 0; st < n; ++st) {
+    double* dst = st + 1 == n ? d_out : (st % 2 == 0 ? d_a : d_b);
+    ars::StepIO io{};
+    io.rate_in = nullptr;
+    io.dt_in = d_dt_sched + st;
+    io.rate_out = nullptr;
+    io.clear_slot = nullptr;
+    io.t = d_t;
+    io.dt_log = nullptr;
+    io.ctl = ctl;
+    if (ars::launch_step_fused(ctx->P, src, dst, io, ctx->ts, s) != hipSuccess) return ARS_EDEVICE;
+    src = dst;
   }
   return ARS_OK;
 }

@@ -157,6 +157,24 @@ def test_energy_form_validation():
     assert rc == A.EINVAL
 
 
+def test_step_sched_to_rejects_aliasing():
+    """ars_step_sched_to checks its buffers before any launch: distinct
+    scratch states, an input and an output that are not scratch, no
+    single step in place, at least one step."""
+    import ctypes as C
+    cfg, prob, prm, seed = W.rb([8, 6], [2.0, 1.0])
+    ctx = A.Context(cfg)
+    f = A.lib().ars_step_sched_to
+    i, a, b, o, w, d = (C.c_void_p(k) for k in (1, 2, 3, 4, 5, 6))
+    assert f(ctx.h, i, a, a, o, w, 2, d, None, None) == A.EINVAL   # a == b
+    assert f(ctx.h, a, a, b, o, w, 2, d, None, None) == A.EINVAL   # in == a
+    assert f(ctx.h, i, a, b, b, w, 2, d, None, None) == A.EINVAL   # out == b
+    assert f(ctx.h, i, a, b, i, w, 1, d, None, None) == A.EINVAL   # one step in place
+    assert f(ctx.h, i, a, b, o, w, 0, d, None, None) == A.EINVAL   # no step
+    assert f(ctx.h, i, a, b, o, None, 2, d, None, None) == A.EINVAL  # no workspace
+    assert f(ctx.h, i, a, b, o, w, 2, None, None, None) == A.EINVAL  # no schedule
+
+
 def test_spectrum_host_side():
     """Shell counts and scratch size of the plane spectrum, and its argument
     checks, which return before any device use."""

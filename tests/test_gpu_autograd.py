@@ -54,6 +54,31 @@ def test_checkpointed_gradient_equals_store_all(T):
     assert J0 == J1 and np.array_equal(g0, g1) and m0 == m1 and k0 == k1
 
 
+def test_step_sched_to_equals_step_sched(T):
+    """ars_step_sched_to (out of place, no copy; the adjoint sweep's
+    advances) gives the states of ars_step_sched bit for bit, leaves its
+    input untouched, and may write its output over its input from two
+    steps on."""
+    pb, cfg = make_problem(T, 3)
+    S = pb.solver(cfg["mu"], cfg["kappa"])
+    U0 = pb.build(S, T.zeros(pb.rho.shape, dtype=T.float64, device="cuda")).clone()
+    dts = T.full((3,), S.compute_dt().item(), dtype=T.float64, device="cuda")
+    a, b, out = (T.empty_like(U0) for _ in range(3))
+    want = {}
+    for n in (1, 2, 3):
+        S.U.copy_(U0)
+        S.step_sched(dts[:n])
+        want[n] = S.U.clone()
+        keep = U0.clone()
+        S.step_sched_to(U0, out, a, b, dts[:n])
+        T.cuda.synchronize()
+        say("step_sched_to", n, "bitwise", T.equal(out, want[n]))
+        assert T.equal(out, want[n]) and T.equal(U0, keep)
+    buf = U0.clone()
+    S.step_sched_to(buf, buf, a, b, dts[:2])
+    assert T.equal(buf, want[2])
+
+
 @pytest.mark.parametrize("energy_form", [0, 1])
 def test_gradient_vs_central_differences(T, energy_form):
     """Both energy forms (the relaxed total energy and App. B)."""

@@ -52,3 +52,53 @@ def test_plan_simulation(n, s):
     assert order == list(range(n - 1, -1, -1))
     assert advanced == fwd == A.revolve_cost(n, s)
     assert max(slots) < s
+
+
+class _LabelSolver:
+    """Stand-in for the solver: a state buffer holds the index of the step
+    whose state it is (NaN once clobbered as ping-pong scratch), and the
+    calls check what ars_step_sched_to and the adjoint step require."""
+
+    def __init__(self, torch):
+        self.torch = torch
+        self.U = torch.full((1,), float("nan"), dtype=torch.float64)
+        self.tmp = torch.full((1,), float("nan"), dtype=torch.float64)
+        self.seen = []
+        self.copies = 0
+
+    def step_sched_to(self, U_in, U_out, a, b, dt_sched):
+        n = dt_sched.numel()
+        assert n >= 1 and a is not b
+        assert U_in is not a and U_in is not b and U_out is not a and U_out is not b
+        assert not (n == 1 and U_out is U_in)
+        start = U_in.item()
+        assert start == start, "advance from a clobbered buffer"
+        if n >= 2:
+            a.fill_(float("nan"))
+        if n >= 3:
+            b.fill_(float("nan"))
+        U_out.fill_(start + n)
+
+    def step_adjoint(self, U_n, lam, dt, lam_n=None, param_grad=None):
+        self.seen.append((int(dt[0].item()), U_n.item()))
+        lam_n.copy_(lam + 1)
+
+
+@pytest.mark.parametrize("n,s", [(200, 16), (50, 4), (10, 3), (7, 7), (30, 1), (5, 2), (1, 1)])
+def test_copy_free_plan_executor(n, s):
+    """The adjoint sweep's executor (no state copies) hands every adjoint
+    step n-1, ..., 0 the state of its own step, never advances in place or
+    from a clobbered buffer, and returns the last adjoint."""
+    import torch
+    from paper_1903_09043_amd.adjoint import run_plan
+    plan, _ = A.revolve_plan(n, s)
+    S = _LabelSolver(torch)
+    U0 = torch.zeros(1, dtype=torch.float64)
+    snaps = [U0] + [torch.full((1,), float("nan"), dtype=torch.float64) for _ in range(s - 1)]
+    log = torch.arange(n, dtype=torch.float64)  # dt of step k = k: the adjoint step sees its index
+    lam = torch.zeros(1, dtype=torch.float64)
+    lam_next = torch.empty_like(lam)
+    out = run_plan(S, plan, snaps, log, lam, lam_next, None)
+    assert S.seen == [(k, float(k)) for k in range(n - 1, -1, -1)]
+    assert out.item() == n
+    assert U0.item() == 0.0
