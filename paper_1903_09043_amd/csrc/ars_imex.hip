@@ -466,6 +466,21 @@ __device__ __forceinline__ double sum_parts(const double* __restrict__ part, int
   return block_sum(s);
 }
 
+// beta = (r, r) / (r, r) of the previous iteration (0 in the first) from
+// the nb block sums of (r, r); every block adds them in the same order, and
+// block 0 keeps this iteration's (r, r) for the next one and for alpha.
+__device__ __forceinline__ double cg_beta(const double* __restrict__ part_rr, int nb, double* __restrict__ sc, int it) {
+  double beta = 0.0;
+  if (it > 0) {
+    const double rr = sum_parts(part_rr, nb);
+    const double old = sc[SC_CG_RR + ((it - 1) & 1)];
+    beta = old != 0.0 ? rr / old : 0.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) sc[SC_CG_RR + (it & 1)] = rr;
+    __syncthreads();
+  }
+  return beta;
+}
+
 // Work units of k_cg_apply: a row of x cells (fixed y, z) cut into chunks
 // of BS; each block takes a contiguous run of units, and the runs of the
 // blocks one XCD receives (blocks go to the XCDs in turn) are contiguous, so
@@ -476,18 +491,9 @@ __global__ __launch_bounds__(BS) void k_cg_apply(Params P, const double* __restr
                                                  const double* __restrict__ pold, double* __restrict__ pnew,
                                                  const double* __restrict__ tau, const double* __restrict__ irc,
                                                  const double* __restrict__ irc2, double* __restrict__ q,
-                                                 const double* __restrict__ part_rr, double* __restrict__ part_pq,
-                                                 double* __restrict__ sc, int it) {
-  // beta = (r, r) / (r, r) of the previous iteration (0 in the first);
-  // every block adds the block sums of (r, r) in the same order
-  double beta = 0.0;
-  if (it > 0) {
-    const double rr = sum_parts(part_rr, gridDim.x);
-    const double old = sc[SC_CG_RR + ((it - 1) & 1)];
-    beta = old != 0.0 ? rr / old : 0.0;
-    if (blockIdx.x == 0 && threadIdx.x == 0) sc[SC_CG_RR + (it & 1)] = rr;
-    __syncthreads();
-  }
+                                                 const double* __restrict__ part_rr, int nb_rr,
+                                                 double* __restrict__ part_pq, double* __restrict__ sc, int it) {
+  const double beta = cg_beta(part_rr, nb_rr, sc, it);
   const double dt = *d_dt;
   const int axes[3] = {0, DIM == 3 ? 1 : 2, 2};
   const int ext[3] = {P.nx, P.ny, P.nz};
@@ -539,14 +545,111 @@ __global__ __launch_bounds__(BS) void k_cg_apply(Params P, const double* __restr
   if (threadIdx.x == 0) part_pq[blockIdx.x] = tot;
 }
 
+// The same product for 2D, through LDS: a tile of CT_X x CT_Z cells
+// stages p (formed from r and p_old) with its periodic halo of 2, and tau
+// and 1/(rho c) with their halo of 1, so each value is read from memory
+// once per tile instead of once per stencil point (29 loads a cell become
+// about 6).  Tiles in row-major order, a contiguous run per block and the
+// blocks of one XCD together, as above.
+constexpr int CT_X = 64, CT_Z = 16;
+constexpr int CP_X = CT_X + 4, CP_Z = CT_Z + 4;  // p with halo 2
+constexpr int CC_X = CT_X + 2, CC_Z = CT_Z + 2;  // tau, 1/(rho c) with halo 1
+static_assert((CT_X * CT_Z) % BS == 0 && CT_X % 64 == 0, "tile rows are whole waves");
+
+__global__ __launch_bounds__(BS) void k_cg_apply_2d(Params P, const double* __restrict__ d_dt,
+                                                    const double* __restrict__ r, const double* __restrict__ pold,
+                                                    double* __restrict__ pnew, const double* __restrict__ tau,
+                                                    const double* __restrict__ irc, const double* __restrict__ irc2,
+                                                    double* __restrict__ q, const double* __restrict__ part_rr,
+                                                    int nb_rr, double* __restrict__ part_pq, double* __restrict__ sc,
+                                                    int it) {
+  __shared__ double sP[CP_Z][CP_X];
+  __shared__ double sT[CC_Z][CC_X];
+  __shared__ double sI[CC_Z][CC_X];
+  __shared__ int colm[CP_X];
+  __shared__ int rowm[CP_Z];
+  const double beta = cg_beta(part_rr, nb_rr, sc, it);
+  const double dt = *d_dt;
+  const double lx = dt / P.dx[0], lz = dt / P.dx[2], hK = P.hK;
+  const int nx = P.nx, nz = P.nz;
+  const int tx = (nx + CT_X - 1) / CT_X;
+  const int tiles = tx * ((nz + CT_Z - 1) / CT_Z);
+  const unsigned G = gridDim.x, b = blockIdx.x;
+  const unsigned lw = (G % 8 == 0) ? (b % 8) * (G / 8) + b / 8 : b;
+  const int t0 = (int)((long long)tiles * lw / G), t1 = (int)((long long)tiles * (lw + 1) / G);
+  const int tid = threadIdx.x;
+  double s = 0.0;
+  for (int t = t0; t < t1; ++t) {
+    const int x0 = (t % tx) * CT_X, z0 = (t / tx) * CT_Z;
+    // periodic images of the tile's columns and rows (halo 2)
+    if (tid < CP_X) {
+      int g = (x0 + tid - 2) % nx;
+      colm[tid] = g < 0 ? g + nx : g;
+    } else if (tid < CP_X + CP_Z) {
+      int g = (z0 + (tid - CP_X) - 2) % nz;
+      rowm[tid - CP_X] = (g < 0 ? g + nz : g) * nx;
+    }
+    __syncthreads();
+    for (int e = tid; e < CP_X * CP_Z; e += BS) {
+      const int j = e / CP_X, i = e - j * CP_X;
+      const int idx = rowm[j] + colm[i];
+      const double v = r[idx] + beta * pold[idx];
+      sP[j][i] = v;
+      if (j >= 2 && j < CT_Z + 2 && i >= 2 && i < CT_X + 2 && x0 + i - 2 < nx && z0 + j - 2 < nz) pnew[idx] = v;
+    }
+    for (int e = tid; e < CC_X * CC_Z; e += BS) {
+      const int j = e / CC_X, i = e - j * CC_X;
+      const int idx = rowm[j + 1] + colm[i + 1];
+      sT[j][i] = tau[idx];
+      sI[j][i] = irc[idx];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < CT_X * CT_Z / BS; ++k) {
+      const int e = tid + k * BS;
+      const int i = e % CT_X, j = e / CT_X;
+      const int gx = x0 + i, gz = z0 + j;
+      if (gx < nx && gz < nz) {
+        const double P0 = sP[j + 2][i + 2], t0c = sT[j + 1][i + 1], i0 = sI[j + 1][i + 1];
+        double div = 0.0;
+        {  // x: velocities of the cells c - e, c, c + e, then u* of the two faces
+          const double Pm2 = sP[j + 2][i], Pm1 = sP[j + 2][i + 1], Pp1 = sP[j + 2][i + 3], Pp2 = sP[j + 2][i + 4];
+          const double um = -(lx * sT[j + 1][i]) * (0.5 * (P0 - Pm2));
+          const double uc = -(lx * t0c) * (0.5 * (Pp1 - Pm1));
+          const double up = -(lx * sT[j + 1][i + 2]) * (0.5 * (Pp2 - P0));
+          const double usm = 0.5 * (um + uc) - (P0 - Pm1) * (hK * dmin2(sI[j + 1][i], i0));
+          const double usp = 0.5 * (uc + up) - (Pp1 - P0) * (hK * dmin2(i0, sI[j + 1][i + 2]));
+          div = div + lx * (usp - usm);
+        }
+        {  // z
+          const double Pm2 = sP[j][i + 2], Pm1 = sP[j + 1][i + 2], Pp1 = sP[j + 3][i + 2], Pp2 = sP[j + 4][i + 2];
+          const double um = -(lz * sT[j][i + 1]) * (0.5 * (P0 - Pm2));
+          const double uc = -(lz * t0c) * (0.5 * (Pp1 - Pm1));
+          const double up = -(lz * sT[j + 2][i + 1]) * (0.5 * (Pp2 - P0));
+          const double usm = 0.5 * (um + uc) - (P0 - Pm1) * (hK * dmin2(sI[j][i + 1], i0));
+          const double usp = 0.5 * (uc + up) - (Pp1 - P0) * (hK * dmin2(i0, sI[j + 2][i + 1]));
+          div = div + lz * (usp - usm);
+        }
+        const int c = gz * nx + gx;
+        const double y = P0 * irc2[c] + div;
+        q[c] = y;
+        s = s + P0 * y;
+      }
+    }
+    __syncthreads();  // the next tile overwrites the LDS
+  }
+  const double tot = block_sum(s);
+  if (threadIdx.x == 0) part_pq[blockIdx.x] = tot;
+}
+
 // alpha = (r, r) / (p, q), every block adding the block sums of (p, q) in
 // the same order; then x += alpha p, r -= alpha q and the block sums of
 // the new (r, r).
 __global__ __launch_bounds__(BS) void k_cg_xr(long long n, const double* __restrict__ p, const double* __restrict__ q,
                                               double* __restrict__ x, double* __restrict__ r,
-                                              const double* __restrict__ part_pq, double* __restrict__ part_rr,
-                                              const double* __restrict__ sc, int it) {
-  const double pq = sum_parts(part_pq, gridDim.x);
+                                              const double* __restrict__ part_pq, int nb_pq,
+                                              double* __restrict__ part_rr, const double* __restrict__ sc, int it) {
+  const double pq = sum_parts(part_pq, nb_pq);
   const double alpha = pq != 0.0 ? sc[SC_CG_RR + (it & 1)] / pq : 0.0;
   __syncthreads();
   double s = 0.0;
@@ -681,7 +784,12 @@ struct Imex {
   // t: 1/(rho c^2)) and b, once the first residual is formed, the second p.
   int solve_cg(double tol, int max_iter, int* its) {
     const unsigned nb = nblk(L.n);
-    const unsigned gb = nb < (unsigned)CG_BLOCKS ? nb : (unsigned)CG_BLOCKS;
+    const unsigned gb = nb < (unsigned)CG_BLOCKS ? nb : (unsigned)CG_BLOCKS;  // k_cg_xr
+    unsigned ga = gb;                                                          // the product
+    if (DIM == 2) {
+      const long long tiles = (long long)((P.nx + CT_X - 1) / CT_X) * ((P.nz + CT_Z - 1) / CT_Z);
+      ga = tiles < CG_BLOCKS ? (unsigned)tiles : (unsigned)CG_BLOCKS;
+    }
     hipLaunchKernelGGL(k_fill0, dim3(nb), dim3(BS), 0, s, L.n, L.t);
     if (apply(L.t, L.b, 1) != hipSuccess) return ARS_EDEVICE;
     hipLaunchKernelGGL(k_neg, dim3(nb), dim3(BS), 0, s, L.n, L.b);
@@ -710,9 +818,14 @@ struct Imex {
     for (; it < max_iter; ++it) {
       double* po = pv[it & 1];
       double* pn = pv[(it + 1) & 1];
-      hipLaunchKernelGGL(k_cg_apply<DIM>, dim3(gb), dim3(BS), 0, s, P, d_dt, L.r, po, pn, L.rh, L.sv, L.t, L.v,
-                         part_rr, part_pq, L.sc, it);
-      hipLaunchKernelGGL(k_cg_xr, dim3(gb), dim3(BS), 0, s, L.n, pn, L.v, L.x, L.r, part_pq, part_rr, L.sc, it);
+      if (DIM == 2)
+        hipLaunchKernelGGL(k_cg_apply_2d, dim3(ga), dim3(BS), 0, s, P, d_dt, L.r, po, pn, L.rh, L.sv, L.t, L.v,
+                           part_rr, (int)gb, part_pq, L.sc, it);
+      else
+        hipLaunchKernelGGL(k_cg_apply<DIM>, dim3(ga), dim3(BS), 0, s, P, d_dt, L.r, po, pn, L.rh, L.sv, L.t, L.v,
+                           part_rr, (int)gb, part_pq, L.sc, it);
+      hipLaunchKernelGGL(k_cg_xr, dim3(gb), dim3(BS), 0, s, L.n, pn, L.v, L.x, L.r, part_pq, (int)ga, part_rr, L.sc,
+                         it);
       if (it % CG_CHECK == CG_CHECK - 1 || it + 1 == max_iter) {
         hipLaunchKernelGGL(k_cg_check, dim3(1), dim3(BS), 0, s, part_rr, (int)gb, L.sc);
         double rr = 0.0;
