@@ -385,13 +385,19 @@ class Solver:
                                   dt_sched.numel(), _ptr(dt_sched), self.stream), "ars_step_ref")
         return self
 
+    def imex_workspace(self):
+        """The IMEX step's device workspace (allocated on first use)."""
+        if self._wimex is None:
+            self._wimex = self.torch.empty(lib().ars_workspace_bytes_imex(self.ctx.h), dtype=self.torch.uint8,
+                                           device=self.device)
+        return self._wimex
+
     def step_imex(self, dt_sched, tol=1e-13, max_iter=2000):
         """Implicit acoustic steps (ars_step_imex), dt of step s =
         dt_sched[s]; returns the total solver iterations."""
         t = self.torch
         dt_sched = t.as_tensor(dt_sched, dtype=t.float64).to(self.device).contiguous()
-        if self._wimex is None:
-            self._wimex = t.empty(lib().ars_workspace_bytes_imex(self.ctx.h), dtype=t.uint8, device=self.device)
+        self.imex_workspace()
         its = C.c_int(0)
         _check(lib().ars_step_imex(self.ctx.h, _ptr(self.U), _ptr(self.tmp), _ptr(self.work), _ptr(self._wimex),
                                    int(dt_sched.numel()), _ptr(dt_sched), _ptr(self.t), float(tol), int(max_iter),
