@@ -187,12 +187,10 @@ int ars_init_state_host(const ars_ctx* ctx, int problem, const double* params, i
  * d_u0 (nullable): device initial velocity, dim fields in the momentum
  * layout; NULL is rest, and then the state equals ars_init_state with the
  * SplitMix64 perturbation replaced by dT.  Forms the base density column
- * (nz values) on the host, copies it to a device buffer the context owns
- * (allocated on the first call, on the current device; freed by
- * ars_destroy) and writes every cell on the device (synchronous on
- * `stream`; calls on one context must not overlap).  EINVAL for a
- * configuration without walls on the vertical axis or a NULL pointer,
- * ENOMEM when the column buffer cannot be allocated. */
+ * (nz values) on the host, stages it in d_state (the first nz doubles of
+ * the x-momentum field, overwritten afterwards) and writes every cell on
+ * the device; allocates nothing (synchronous on `stream`).  EINVAL for a
+ * configuration without walls on the vertical axis or a NULL pointer. */
 int ars_init_rb_dT(ars_ctx* ctx, const double* params, int n_params, const double* d_dT, const double* d_u0,
                    double* d_state, void* stream);
 /* Transpose of the map dT -> U^0 of ars_init_rb_dT at the state it built:

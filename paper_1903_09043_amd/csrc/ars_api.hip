@@ -97,19 +97,31 @@ ars::Control* ctl_of(void* w) { return (ars::Control*)w; }
 // U^0 of a Rayleigh-Benard base with a temperature perturbation field: the
 // density of d_state (the uploaded base) is kept, the energy is rebuilt from
 // the level's linear temperature (the formula of the host initial state);
-// rho of level k from the base column.
+// rho of level k from the base column, staged in the first nz doubles of
+// the x-momentum field (k_rb_mom overwrites them afterwards).
 template <int DIM>
-static __global__ void k_rb_dT(ars::Params P, double Tb, double Tt, double Lz, const double* __restrict__ col,
-                               const double* __restrict__ dT, const double* __restrict__ u0, double* __restrict__ U) {
+static __global__ void k_rb_dT(ars::Params P, double Tb, double Tt, double Lz, const double* __restrict__ dT,
+                               double* __restrict__ U) {
   const long long N = P.ncell;
   const long long plane = (long long)P.nx * P.ny;
+  const double* col = U + N;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (long long)gridDim.x * blockDim.x) {
     const int k = (int)(i / plane);
     const double zk = ((double)k + 0.5) * P.dx[2];
     const double T = Tb + (Tt - Tb) * (zk / Lz);
     const double rho = col[k];
     U[i] = rho;
-    double E = (rho * (T + dT[i])) / P.gm1;
+    U[(DIM + 1) * N + i] = (rho * (T + dT[i])) / P.gm1;
+  }
+}
+
+// Momenta m = rho u0 (0 without u0) and, with u0, the kinetic energy added
+// to E; runs after k_rb_dT.
+template <int DIM>
+static __global__ void k_rb_mom(ars::Params P, const double* __restrict__ u0, double* __restrict__ U) {
+  const long long N = P.ncell;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (long long)gridDim.x * blockDim.x) {
+    const double rho = U[i];
     double mm = 0.0;
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
@@ -117,8 +129,7 @@ static __global__ void k_rb_dT(ars::Params P, double Tb, double Tt, double Lz, c
       U[(1 + a) * N + i] = m;
       mm = mm + m * m;
     }
-    if (u0) E = E + (0.5 * mm) / rho;
-    U[(DIM + 1) * N + i] = E;
+    if (u0) U[(DIM + 1) * N + i] = U[(DIM + 1) * N + i] + (0.5 * mm) / rho;
   }
 }
 
@@ -223,10 +234,7 @@ int ars_create(const ars_config* cfg, ars_ctx** out) {
   return ARS_OK;
 }
 
-void ars_destroy(ars_ctx* c) {
-  if (c && c->d_col) (void)hipFree(c->d_col);
-  delete c;
-}
+void ars_destroy(ars_ctx* c) { delete c; }
 
 size_t ars_state_len(const ars_ctx* c) { return c ? c->len : 0; }
 
@@ -426,30 +434,22 @@ int ars_init_rb_dT(ars_ctx* ctx, const double* prm, int nprm, const double* d_dT
   for (int i = 0; i < nprm && i < 3; ++i) base[i] = prm[i];
   std::vector<double> Tcol, rcol;
   hydrostatic_column(ctx, false, base[0], base[1], base[2], Tcol, rcol);
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return ARS_EDEVICE;
-  if (ctx->d_col && ctx->d_col_dev != dev) {
-    (void)hipFree(ctx->d_col);
-    ctx->d_col = nullptr;
-  }
-  if (!ctx->d_col) {
-    if (hipMalloc((void**)&ctx->d_col, (size_t)ctx->P.nz * sizeof(double)) != hipSuccess) {
-      ctx->d_col = nullptr;
-      return ARS_ENOMEM;
-    }
-    ctx->d_col_dev = dev;
-  }
   hipStream_t s = (hipStream_t)stream;
-  if (hipMemcpyAsync(ctx->d_col, rcol.data(), (size_t)ctx->P.nz * sizeof(double), hipMemcpyHostToDevice, s) !=
+  // the column goes to the first nz doubles of the x-momentum field (the
+  // caller's buffer; nz <= ncell), which k_rb_mom overwrites once k_rb_dT
+  // has read it
+  const long long N = ctx->P.ncell;
+  if (hipMemcpyAsync(d_state + N, rcol.data(), (size_t)ctx->P.nz * sizeof(double), hipMemcpyHostToDevice, s) !=
       hipSuccess)
     return ARS_EDEVICE;
-  const unsigned nb = flat_blocks(ctx->P.ncell);
-  if (c.dim == 3)
-    hipLaunchKernelGGL(k_rb_dT<3>, dim3(nb), dim3(256), 0, s, ctx->P, base[0], base[1], c.L[z], ctx->d_col, d_dT,
-                       d_u0, d_state);
-  else
-    hipLaunchKernelGGL(k_rb_dT<2>, dim3(nb), dim3(256), 0, s, ctx->P, base[0], base[1], c.L[z], ctx->d_col, d_dT,
-                       d_u0, d_state);
+  const unsigned nb = flat_blocks(N);
+  if (c.dim == 3) {
+    hipLaunchKernelGGL(k_rb_dT<3>, dim3(nb), dim3(256), 0, s, ctx->P, base[0], base[1], c.L[z], d_dT, d_state);
+    hipLaunchKernelGGL(k_rb_mom<3>, dim3(nb), dim3(256), 0, s, ctx->P, d_u0, d_state);
+  } else {
+    hipLaunchKernelGGL(k_rb_dT<2>, dim3(nb), dim3(256), 0, s, ctx->P, base[0], base[1], c.L[z], d_dT, d_state);
+    hipLaunchKernelGGL(k_rb_mom<2>, dim3(nb), dim3(256), 0, s, ctx->P, d_u0, d_state);
+  }
   if (hipGetLastError() != hipSuccess) return ARS_EDEVICE;
   return check(hipStreamSynchronize(s));
 }

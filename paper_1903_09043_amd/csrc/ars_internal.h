@@ -96,8 +96,6 @@ struct ars_ctx {
   ars::Params P;
   ars::TileShape ts;
   size_t len;
-  double* d_col = nullptr;  // device copy of the RB base density column (nz doubles), owned
-  int d_col_dev = -1;       // the device it was allocated on
 };
 
 struct ars_batch {
