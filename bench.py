@@ -167,24 +167,26 @@ def timed(torch, fn, stream=None):
 
 def spectrum_leg(torch, S, n, reps=20):
     """Kinetic-energy spectrum of the middle horizontal plane of the stepped
-    state (ars_spectrum: dense DFT along x, then y, on the FP64 matrix
-    cores, then shell sums).  Off the step path.  Two counts of its work:
-    the dense DFT it executes (4 flops per (kx, x) pair of the row
-    transforms and 8 per (ky, y) pair of the column transforms, for each of
-    the 3 components) and the transform's own work as an FFT (5 N log2 N
-    flops per complex 2D transform of N points, 3 transforms); only the
-    latter is the transform's roofline figure, and it is tiny: a dense DFT
-    on matrix cores is the choice for one plane, not a fast transform."""
+    state (ars_spectrum), off the step path.  A power-of-two plane takes the
+    radix-2 FFT path (rows, then tiles of columns, in LDS), any other the
+    dense DFT on the FP64 matrix cores.  Work counted as an FFT: 5 N log2 N
+    flops per complex 2D transform of N points, 3 transforms, against the
+    FP64 peak (vector and matrix: 78.6 TFLOP/s); for the dense path also the
+    DFT it executes (4 flops per (kx, x) pair of the row transforms and 8
+    per (ky, y) pair of the column transforms)."""
     import math
     S.spectrum()
     ms = timed(torch, lambda: [S.spectrum() for _ in range(reps)]) / reps
-    dense = 3 * n * n * (4 * n + 8 * n)
     fft = 3 * 5 * n * n * math.log2(n * n)
-    return {"plane": [n, n], "shells": int(S.spectrum().numel()), "ms_per_call": round(ms, 4),
-            "dense_dft_TFLOPs": round(dense / (ms * 1e-3) / 1e12, 3),
-            "mfma_frac_of_executed_dense_dft": round(dense / (ms * 1e-3) / 1e12 / FP64_MFMA_PEAK_TFS, 4),
-            "fft_equivalent_TFLOPs": round(fft / (ms * 1e-3) / 1e12, 4),
-            "peak_TFLOPs": FP64_MFMA_PEAK_TFS}
+    pow2 = n & (n - 1) == 0
+    out = {"plane": [n, n], "shells": int(S.spectrum().numel()), "ms_per_call": round(ms, 4),
+           "path": "radix-2 FFT in LDS" if pow2 else "dense DFT on the FP64 matrix cores",
+           "fft_equivalent_TFLOPs": round(fft / (ms * 1e-3) / 1e12, 4), "peak_TFLOPs": FP64_MFMA_PEAK_TFS}
+    if not pow2:
+        dense = 3 * n * n * (4 * n + 8 * n)
+        out["dense_dft_TFLOPs"] = round(dense / (ms * 1e-3) / 1e12, 3)
+        out["mfma_frac_of_executed_dense_dft"] = round(dense / (ms * 1e-3) / 1e12 / FP64_MFMA_PEAK_TFS, 4)
+    return out
 
 
 def imex_leg(torch, A, W, n=1024, Ma=1e-3, expl_steps=5000, tol=1e-10):

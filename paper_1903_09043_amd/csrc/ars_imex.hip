@@ -801,16 +801,15 @@ struct Imex {
     double bb = 0.0;
     if (read(SC_BB, &bb) != ARS_OK) return ARS_EDEVICE;
     const double target = tol * tol * (bb > 0.0 ? bb : 1.0);
-    dot(L.r, L.r, SC_RR);
+    dot(L.r, L.r, SC_CG_RR);  // (r, r) of iteration 0
     double rr0 = 0.0;
-    if (read(SC_RR, &rr0) != ARS_OK) return ARS_EDEVICE;
+    if (read(SC_CG_RR, &rr0) != ARS_OK) return ARS_EDEVICE;
     if (!std::isfinite(rr0)) return ARS_ENOCONV;
     if (rr0 <= target) {
       if (its) *its = 0;
       return ARS_OK;
     }
     hipLaunchKernelGGL(k_cg_coef<DIM>, dim3(nblk(P.ncell)), dim3(BS), 0, s, P, L.G, L.W, L.rh, L.sv, L.t);
-    dot(L.r, L.r, SC_CG_RR);  // (r, r) of iteration 0
     double* const part_pq = L.part;
     double* const part_rr = L.part + (CG_BLOCKS > DOT_BLOCKS ? CG_BLOCKS : DOT_BLOCKS);
     double* pv[2] = {L.p, L.b};  // p = 0 on entry, so the first p is r

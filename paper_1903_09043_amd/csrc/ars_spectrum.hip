@@ -8,7 +8,11 @@
 // j - n), N the cell count of the plane; sum_s E(s) is then the plane mean of
 // rho |u|^2 / 2 (Parseval).  In 2D the plane is a line along x.
 //
-// The transform is a dense DFT, rows then columns, and a DFT is a matrix
+// When both sides are powers of two the transform is a radix-2 FFT, rows
+// then columns, each transform staged in LDS (bit-reversed load, log2 n
+// butterfly stages with a barrier each; the column kernel takes a tile of
+// adjacent columns so its loads are row segments, and forms |Y|^2).
+// Otherwise it is a dense DFT, rows then columns, and a DFT is a matrix
 // product: the row transform is W (n_y x n_x) times the n_x x n_x twiddle
 // matrix, the column transform the n_y x n_y twiddle matrix times X, so
 // both run on the FP64 matrix cores (v_mfma_f64_16x16x4f64: one wave
@@ -215,6 +219,106 @@ __global__ void __launch_bounds__(256) k_spec_shells(Params P, const double* __r
   if (threadIdx.x == 0) E[s] = red[0] / (2.0 * (double)N * (double)N);
 }
 
+// ---------------------------------------------------------------- FFT path
+constexpr int FFT_LDS_DOUBLES = 8192;  // 64 KB of dynamic LDS
+
+__device__ __forceinline__ int bit_reverse(int x, int logn) {
+  return logn ? (int)(__brev((unsigned)x) >> (32 - logn)) : 0;
+}
+
+// tw[j] = exp(-2 pi i j / n) for j < n / 2: cos in tw[0..n/2), -sin in
+// tw[n/2..n).
+__device__ __forceinline__ void fill_half_twiddles(double* tw, int n) {
+  const int h = n / 2;
+  for (int j = threadIdx.x; j < h; j += blockDim.x) {
+    double sn, cs;
+    sincospi(2.0 * (double)j / (double)n, &sn, &cs);
+    tw[j] = cs;
+    tw[h + j] = -sn;
+  }
+}
+
+// cw interleaved n-point transforms in LDS (element y of transform cc at
+// y * cw + cc, loaded in bit-reversed order): the radix-2 stages, each a
+// set of butterflies X_i, X_j <- X_i + w X_j, X_i - w X_j with
+// w = exp(-2 pi i k / len), then a barrier.
+__device__ void fft_stages(double* re, double* im, const double* tw, int n, int cw) {
+  const int h = n / 2;
+  for (int half = 1; half < n; half <<= 1) {
+    const int len = 2 * half, step = n / len;
+    for (int b = threadIdx.x; b < cw * h; b += blockDim.x) {
+      const int cc = b % cw, t = b / cw;
+      const int k = t % half, i = (t / half) * len + k;
+      const int a = i * cw + cc, c2 = (i + half) * cw + cc;
+      const double wr = tw[k * step], wi = tw[h + k * step];
+      const double xr = re[c2], xi = im[c2];
+      const double tr = wr * xr - wi * xi;
+      const double ti = wr * xi + wi * xr;
+      const double ar = re[a], ai = im[a];
+      re[a] = ar + tr;
+      im[a] = ai + ti;
+      re[c2] = ar - tr;
+      im[c2] = ai - ti;
+    }
+    __syncthreads();
+  }
+}
+
+// Row transforms: block (row y, component c).
+__global__ void __launch_bounds__(256) k_fft_rows(Params P, int logx, const double* __restrict__ W,
+                                                  double* __restrict__ Xr, double* __restrict__ Xi) {
+  extern __shared__ double sm[];
+  const int n = P.nx, y = blockIdx.x, c = blockIdx.y;
+  double* tw = sm;
+  double* re = sm + n;
+  double* im = re + n;
+  fill_half_twiddles(tw, n);
+  const long long o = ((long long)c * P.ny + y) * n;
+  for (int x = threadIdx.x; x < n; x += blockDim.x) {
+    const int j = bit_reverse(x, logx);
+    re[j] = W[o + x];
+    im[j] = 0.0;
+  }
+  __syncthreads();
+  fft_stages(re, im, tw, n, 1);
+  for (int k = threadIdx.x; k < n; k += blockDim.x) {
+    Xr[o + k] = re[k];
+    Xi[o + k] = im[k];
+  }
+}
+
+// Column transforms and power: block (cw adjacent columns from k0, component
+// c); Pc[c](ky, k) = |Y_c(ky, k)|^2.
+__global__ void __launch_bounds__(256) k_fft_cols(Params P, int logy, int cw, const double* __restrict__ Xr,
+                                                  const double* __restrict__ Xi, double* __restrict__ Pc) {
+  extern __shared__ double sm[];
+  const int nx = P.nx, n = P.ny, c = blockIdx.y, k0 = blockIdx.x * cw;
+  double* tw = sm;
+  double* re = sm + n;
+  double* im = re + n * cw;
+  fill_half_twiddles(tw, n);
+  const long long o = (long long)c * n * nx;
+  for (int e = threadIdx.x; e < cw * n; e += blockDim.x) {
+    const int y = e / cw, cc = e - y * cw, k = k0 + cc;
+    const int j = bit_reverse(y, logy) * cw + cc;
+    const bool in = k < nx;
+    re[j] = in ? Xr[o + (long long)y * nx + k] : 0.0;
+    im[j] = in ? Xi[o + (long long)y * nx + k] : 0.0;
+  }
+  __syncthreads();
+  fft_stages(re, im, tw, n, cw);
+  for (int e = threadIdx.x; e < cw * n; e += blockDim.x) {
+    const int ky = e / cw, cc = e - ky * cw, k = k0 + cc;
+    if (k < nx) Pc[o + (long long)ky * nx + k] = re[e] * re[e] + im[e] * im[e];
+  }
+}
+
+static int log2_exact(int n) {
+  int l = 0;
+  while ((1 << l) < n) ++l;
+  return (1 << l) == n ? l : -1;
+}
+
 int spectrum_shells(const Params& P) {
   const double hx = (double)(P.nx / 2), hy = (double)(P.ny / 2);
   return (int)llrint(sqrt(hx * hx + hy * hy)) + 1;
@@ -236,9 +340,21 @@ hipError_t launch_spectrum(const Params& P, const double* U, int kz, double* E, 
   long long nb = (N * P.dim + 255) / 256;
   if (nb > 4096) nb = 4096;
   hipLaunchKernelGGL(k_spec_w, dim3((unsigned)nb), dim3(256), 0, s, P, U, kz, Wp);
-  const dim3 g((unsigned)((P.nx + 63) / 64), (unsigned)((P.ny + 15) / 16), (unsigned)P.dim);
-  hipLaunchKernelGGL(k_spec_rows, g, dim3(256), (size_t)2 * P.nx * sizeof(double), s, P, Wp, Xr, Xi);
-  hipLaunchKernelGGL(k_spec_cols, g, dim3(256), (size_t)2 * P.ny * sizeof(double), s, P, Xr, Xi, Pc);
+  const int lx = log2_exact(P.nx), ly = log2_exact(P.ny);
+  if (lx >= 0 && ly >= 0) {
+    // rows: n/2 twiddles + n complex; columns: cw of them beside the
+    // twiddles, cw a power of two up to 16 within the 64 KB
+    int cw = 16;
+    while (cw > 1 && P.ny + 2 * cw * P.ny > FFT_LDS_DOUBLES) cw /= 2;
+    hipLaunchKernelGGL(k_fft_rows, dim3((unsigned)P.ny, (unsigned)P.dim), dim3(256),
+                       (size_t)3 * P.nx * sizeof(double), s, P, lx, Wp, Xr, Xi);
+    hipLaunchKernelGGL(k_fft_cols, dim3((unsigned)((P.nx + cw - 1) / cw), (unsigned)P.dim), dim3(256),
+                       (size_t)(P.ny + 2 * cw * P.ny) * sizeof(double), s, P, ly, cw, Xr, Xi, Pc);
+  } else {
+    const dim3 g((unsigned)((P.nx + 63) / 64), (unsigned)((P.ny + 15) / 16), (unsigned)P.dim);
+    hipLaunchKernelGGL(k_spec_rows, g, dim3(256), (size_t)2 * P.nx * sizeof(double), s, P, Wp, Xr, Xi);
+    hipLaunchKernelGGL(k_spec_cols, g, dim3(256), (size_t)2 * P.ny * sizeof(double), s, P, Xr, Xi, Pc);
+  }
   hipLaunchKernelGGL(k_spec_shells, dim3((unsigned)spectrum_shells(P)), dim3(256), 0, s, P, Pc, E);
   return hipGetLastError();
 }

@@ -2,9 +2,11 @@
 oracle's FFT spectrum, on seeded synthetic states.
 
 Acceptance: |E_gpu(s) - E_oracle(s)| <= 1e-12 * sum_s E_oracle + 1e-10 |E_oracle(s)|
-per shell.  The GPU path is a direct DFT and the oracle an FFT, so the two
-differ only by rounding: a sum of n products carries an error of a few n eps
-relative to the field's energy, below 1e-12 for n <= 2048.
+per shell.  The GPU path is a radix-2 FFT when both sides are powers of two
+and a direct DFT otherwise, the oracle an FFT, so the two differ only by
+rounding: a sum of n products carries an error of a few n eps relative to
+the field's energy (log2 n eps for the FFT), below 1e-12 for n <= 2048.
+The sizes below take both paths.
 """
 import sys
 
@@ -66,6 +68,10 @@ def check(g, o):
     (2, [257, 9], 4, "white"),           # 2D: a line
     (2, [2048, 5], 2, "white"),          # 2D: the longest line
     (2, [1, 4], 3, "white"),             # a single cell
+    (3, [64, 32, 4], 2, "white"),        # powers of two: the FFT path, 16-column tiles
+    (3, [2, 4, 3], 1, "white"),          # the FFT path at its smallest transforms
+    (3, [16, 1, 3], 1, "white"),         # the FFT path with a one-cell side
+    (2, [256, 5], 1, "smooth"),          # 2D line on the FFT path
 ])
 def test_spectrum_vs_oracle(A, dim, n, kz, kind):
     say("spectrum", dim, n, kz, kind)
