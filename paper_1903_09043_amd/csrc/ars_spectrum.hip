@@ -343,8 +343,10 @@ hipError_t launch_spectrum(const Params& P, const double* U, int kz, double* E, 
   const int lx = log2_exact(P.nx), ly = log2_exact(P.ny);
   if (lx >= 0 && ly >= 0) {
     // rows: n/2 twiddles + n complex; columns: cw of them beside the
-    // twiddles, cw a power of two up to 16 within the 64 KB
-    int cw = 16;
+    // twiddles, cw = 4 (measured at 256^2: 31.9 us a call against 33.5,
+    // 32.6 and 36.0 with 1, 2 and 8 columns; wider tiles leave too few
+    // workgroups) or fewer within the 64 KB
+    int cw = 4;
     while (cw > 1 && P.ny + 2 * cw * P.ny > FFT_LDS_DOUBLES) cw /= 2;
     hipLaunchKernelGGL(k_fft_rows, dim3((unsigned)P.ny, (unsigned)P.dim), dim3(256),
                        (size_t)3 * P.nx * sizeof(double), s, P, lx, Wp, Xr, Xi);

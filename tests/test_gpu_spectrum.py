@@ -68,7 +68,7 @@ def check(g, o):
     (2, [257, 9], 4, "white"),           # 2D: a line
     (2, [2048, 5], 2, "white"),          # 2D: the longest line
     (2, [1, 4], 3, "white"),             # a single cell
-    (3, [64, 32, 4], 2, "white"),        # powers of two: the FFT path, 16-column tiles
+    (3, [64, 32, 4], 2, "white"),        # powers of two: the FFT path (4-column tiles)
     (3, [2, 4, 3], 1, "white"),          # the FFT path at its smallest transforms
     (3, [16, 1, 3], 1, "white"),         # the FFT path with a one-cell side
     (2, [256, 5], 1, "smooth"),          # 2D line on the FFT path
