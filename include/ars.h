@@ -249,7 +249,7 @@ int ars_step_sched(ars_ctx* ctx, double* d_state, double* d_tmp, void* d_work, i
  * store a choice of d_out.  EINVAL for a NULL pointer, n_steps < 1,
  * d_a == d_b, d_in equal to d_a or d_b, d_out equal to d_a or d_b, or
  * d_out == d_in with n_steps == 1 (a step cannot run in place).
- * Asynchronous; *d_t advanced. */
+ * Asynchronous; *d_t advanced by the dts used (d_t may be NULL). */
 int ars_step_sched_to(ars_ctx* ctx, const double* d_in, double* d_a, double* d_b, double* d_out, void* d_work,
                       int n_steps, const double* d_dt_sched, double* d_t, void* stream);
 
