@@ -264,8 +264,10 @@ int ars_step_sched_to(ars_ctx* ctx, const double* d_in, double* d_a, double* d_b
  *   u_{d,i} = u^n_{d,i} - (dt/dx_d) tau_i ([Pi*]_{d,i} - S-bar_{d,i})
  *   Pi_i    = p_i - rho_i c_i^2 sum_d (dt/dx_d) [u*]_{d,i}
  * u is eliminated (its rows are explicit in Pi) and the system for Pi,
- * rows scaled by 1 / (rho c^2), is solved by BiCGSTAB to a relative
- * residual tol.  The acoustic dissipation of Pi* acts on u^n: with the
+ * rows scaled by 1 / (rho c^2), is solved to a relative residual tol: by
+ * conjugate gradients when every axis is periodic or walled at both ends
+ * (the operator is then symmetric positive definite), else (outflow) by
+ * BiCGSTAB.  The acoustic dissipation of Pi* acts on u^n: with the
  * low-Mach correction (theta ~ Ma) steps far above the acoustic limit are
  * stable, without it (theta = 1) only steps near it.  The
  * implicit (u*, Pi*) then enter the acoustic cell values, transport,

@@ -24,8 +24,8 @@
 // faces for a, S, theta, then the implicit faces, L, b~, fluxes), padded
 // extensions of Pi and of the velocities it gives, and the vectors of an
 // unpreconditioned Krylov solver on the N unknowns Pi: conjugate gradients
-// when every side is periodic (the operator is then symmetric positive
-// definite), BiCGSTAB otherwise.  The operator is applied
+// when every axis is periodic or walled at both ends (the operator is then
+// symmetric positive definite), BiCGSTAB otherwise (outflow).  The operator is applied
 // matrix-free: one kernel extends Pi to the ghost cells, one forms the
 // velocities of every padded cell from the Pi* of its two faces per axis
 // (ghosts by the boundary rules), one forms every row from the u* of the
@@ -401,12 +401,16 @@ __global__ void k_bicg_scalars(double* __restrict__ sc) {
   }
 }
 
-// Conjugate gradients (every side periodic: the eliminated operator is
-// symmetric positive definite, diag(1/(rho c^2)) + lambda^2 K^T tau K +
-// lambda G^T (1/(2a)) G with K the central difference of the two face
-// averages and G the face difference; walls and outflow copies break the
-// symmetry and keep BiCGSTAB).  With no ghost rule left but the periodic
-// image, the operator is a star stencil of radius 2 on the unknowns, so an
+// Conjugate gradients (every axis periodic or walled at both ends: the
+// eliminated operator is symmetric positive definite, diag(1/(rho c^2)) +
+// lambda^2 K^T tau K + lambda G^T (1/(2a)) G with K the central difference
+// of the two face averages and G the face difference.  At a wall the ghost
+// Pi is the wall cell's, so the wall face's Pi* is that cell's Pi, and the
+// wall face's u* is 0; the ghost velocity feeds nothing else, and the
+// operator stays symmetric.  Outflow copies make u* at the boundary face
+// the edge cell's velocity, which breaks the symmetry: BiCGSTAB there.)
+// The operator is a star stencil of radius 2 on the unknowns (neighbour
+// indices wrapped on periodic axes, clamped on walled ones), so an
 // iteration is two streaming kernels: (1) p = r + beta p_old and q = A p
 // on the fly (p_old and r read with periodic wrap), with the block sums of
 // (p, q); (2) x += alpha p, r -= alpha q, with those of (r, r).  Each
@@ -434,13 +438,21 @@ __global__ void k_cg_coef(Params P, RefGrid G, const double* __restrict__ W, dou
   irc2[c] = 1.0 / (W[R_RC * n + q] * W[R_C * n + q]);
 }
 
-// Index offsets of the periodic neighbours k - 2, k - 1, k + 1, k + 2 of
-// coordinate k on an axis of m >= 2 cells and stride st.
-__device__ __forceinline__ void wrap_offsets(int k, int m, int st, int& om2, int& om1, int& op1, int& op2) {
-  om2 = (k >= 2 ? -2 : m - 2) * st;
-  om1 = (k >= 1 ? -1 : m - 1) * st;
-  op1 = (k + 1 < m ? 1 : 1 - m) * st;
-  op2 = (k + 2 < m ? 2 : 2 - m) * st;
+// Index offsets of the neighbours k - 2, k - 1, k + 1, k + 2 of coordinate
+// k on an axis of m >= 2 cells and stride st: periodic images, or on a
+// walled axis the nearest interior cell (the ghost Pi is the wall cell's).
+__device__ __forceinline__ void nb_offsets(int k, int m, int st, bool wall, int& om2, int& om1, int& op1, int& op2) {
+  if (wall) {
+    om2 = ((k >= 2 ? k - 2 : 0) - k) * st;
+    om1 = ((k >= 1 ? k - 1 : 0) - k) * st;
+    op1 = ((k + 1 < m ? k + 1 : m - 1) - k) * st;
+    op2 = ((k + 2 < m ? k + 2 : m - 1) - k) * st;
+  } else {
+    om2 = (k >= 2 ? -2 : m - 2) * st;
+    om1 = (k >= 1 ? -1 : m - 1) * st;
+    op1 = (k + 1 < m ? 1 : 1 - m) * st;
+    op2 = (k + 2 < m ? 2 : 2 - m) * st;
+  }
 }
 
 // Block sum of s in a fixed order (a butterfly within each wave, then the
@@ -492,7 +504,8 @@ __global__ __launch_bounds__(BS) void k_cg_apply(Params P, const double* __restr
                                                  const double* __restrict__ tau, const double* __restrict__ irc,
                                                  const double* __restrict__ irc2, double* __restrict__ q,
                                                  const double* __restrict__ part_rr, int nb_rr,
-                                                 double* __restrict__ part_pq, double* __restrict__ sc, int it) {
+                                                 double* __restrict__ part_pq, double* __restrict__ sc, int it,
+                                                 int wallmask) {
   const double beta = cg_beta(part_rr, nb_rr, sc, it);
   const double dt = *d_dt;
   const int axes[3] = {0, DIM == 3 ? 1 : 2, 2};
@@ -520,8 +533,9 @@ __global__ __launch_bounds__(BS) void k_cg_apply(Params P, const double* __restr
 #pragma unroll
     for (int t = 0; t < DIM; ++t) {
       const int a = axes[t];
+      const bool wall = (wallmask >> a) & 1;
       int om2, om1, op1, op2;
-      wrap_offsets(crd[a], ext[a], str[a], om2, om1, op1, op2);
+      nb_offsets(crd[a], ext[a], str[a], wall, om2, om1, op1, op2);
       const double Pm2 = r[c + om2] + beta * pold[c + om2];
       const double Pm1 = r[c + om1] + beta * pold[c + om1];
       const double Pp1 = r[c + op1] + beta * pold[c + op1];
@@ -531,9 +545,11 @@ __global__ __launch_bounds__(BS) void k_cg_apply(Params P, const double* __restr
       const double um = -(lam[t] * tau[c + om1]) * (0.5 * (P0 - Pm2));
       const double uc = -(lam[t] * t0) * (0.5 * (Pp1 - Pm1));
       const double up = -(lam[t] * tau[c + op1]) * (0.5 * (Pp2 - P0));
-      // u* of the faces c - e | c and c | c + e
-      const double usm = 0.5 * (um + uc) - (P0 - Pm1) * (hK * dmin2(irc[c + om1], i0));
-      const double usp = 0.5 * (uc + up) - (Pp1 - P0) * (hK * dmin2(i0, irc[c + op1]));
+      // u* of the faces c - e | c and c | c + e (0 on a wall face)
+      double usm = 0.5 * (um + uc) - (P0 - Pm1) * (hK * dmin2(irc[c + om1], i0));
+      double usp = 0.5 * (uc + up) - (Pp1 - P0) * (hK * dmin2(i0, irc[c + op1]));
+      if (wall && crd[a] == 0) usm = 0.0;
+      if (wall && crd[a] == ext[a] - 1) usp = 0.0;
       div = div + lam[t] * (usp - usm);
     }
     const double y = P0 * irc2[c] + div;
@@ -562,7 +578,7 @@ __global__ __launch_bounds__(BS) void k_cg_apply_2d(Params P, const double* __re
                                                     const double* __restrict__ irc, const double* __restrict__ irc2,
                                                     double* __restrict__ q, const double* __restrict__ part_rr,
                                                     int nb_rr, double* __restrict__ part_pq, double* __restrict__ sc,
-                                                    int it) {
+                                                    int it, int wallmask) {
   __shared__ double sP[CP_Z][CP_X];
   __shared__ double sT[CC_Z][CC_X];
   __shared__ double sI[CC_Z][CC_X];
@@ -572,6 +588,7 @@ __global__ __launch_bounds__(BS) void k_cg_apply_2d(Params P, const double* __re
   const double dt = *d_dt;
   const double lx = dt / P.dx[0], lz = dt / P.dx[2], hK = P.hK;
   const int nx = P.nx, nz = P.nz;
+  const bool wx = wallmask & 1, wz = (wallmask >> 2) & 1;
   const int tx = (nx + CT_X - 1) / CT_X;
   const int tiles = tx * ((nz + CT_Z - 1) / CT_Z);
   const unsigned G = gridDim.x, b = blockIdx.x;
@@ -581,13 +598,18 @@ __global__ __launch_bounds__(BS) void k_cg_apply_2d(Params P, const double* __re
   double s = 0.0;
   for (int t = t0; t < t1; ++t) {
     const int x0 = (t % tx) * CT_X, z0 = (t / tx) * CT_Z;
-    // periodic images of the tile's columns and rows (halo 2)
+    // the cells behind the tile's halo columns and rows (halo 2): periodic
+    // images, or on a walled axis the nearest interior cell
     if (tid < CP_X) {
-      int g = (x0 + tid - 2) % nx;
-      colm[tid] = g < 0 ? g + nx : g;
+      const int v = x0 + tid - 2;
+      int g = v % nx;
+      g = g < 0 ? g + nx : g;
+      colm[tid] = wx ? (v < 0 ? 0 : (v < nx ? v : nx - 1)) : g;
     } else if (tid < CP_X + CP_Z) {
-      int g = (z0 + (tid - CP_X) - 2) % nz;
-      rowm[tid - CP_X] = (g < 0 ? g + nz : g) * nx;
+      const int v = z0 + (tid - CP_X) - 2;
+      int g = v % nz;
+      g = g < 0 ? g + nz : g;
+      rowm[tid - CP_X] = (wz ? (v < 0 ? 0 : (v < nz ? v : nz - 1)) : g) * nx;
     }
     __syncthreads();
     for (int e = tid; e < CP_X * CP_Z; e += BS) {
@@ -617,8 +639,10 @@ __global__ __launch_bounds__(BS) void k_cg_apply_2d(Params P, const double* __re
           const double um = -(lx * sT[j + 1][i]) * (0.5 * (P0 - Pm2));
           const double uc = -(lx * t0c) * (0.5 * (Pp1 - Pm1));
           const double up = -(lx * sT[j + 1][i + 2]) * (0.5 * (Pp2 - P0));
-          const double usm = 0.5 * (um + uc) - (P0 - Pm1) * (hK * dmin2(sI[j + 1][i], i0));
-          const double usp = 0.5 * (uc + up) - (Pp1 - P0) * (hK * dmin2(i0, sI[j + 1][i + 2]));
+          double usm = 0.5 * (um + uc) - (P0 - Pm1) * (hK * dmin2(sI[j + 1][i], i0));
+          double usp = 0.5 * (uc + up) - (Pp1 - P0) * (hK * dmin2(i0, sI[j + 1][i + 2]));
+          if (wx && gx == 0) usm = 0.0;  // wall faces carry no flux
+          if (wx && gx == nx - 1) usp = 0.0;
           div = div + lx * (usp - usm);
         }
         {  // z
@@ -626,8 +650,10 @@ __global__ __launch_bounds__(BS) void k_cg_apply_2d(Params P, const double* __re
           const double um = -(lz * sT[j][i + 1]) * (0.5 * (P0 - Pm2));
           const double uc = -(lz * t0c) * (0.5 * (Pp1 - Pm1));
           const double up = -(lz * sT[j + 2][i + 1]) * (0.5 * (Pp2 - P0));
-          const double usm = 0.5 * (um + uc) - (P0 - Pm1) * (hK * dmin2(sI[j][i + 1], i0));
-          const double usp = 0.5 * (uc + up) - (Pp1 - P0) * (hK * dmin2(i0, sI[j + 2][i + 1]));
+          double usm = 0.5 * (um + uc) - (P0 - Pm1) * (hK * dmin2(sI[j][i + 1], i0));
+          double usp = 0.5 * (uc + up) - (Pp1 - P0) * (hK * dmin2(i0, sI[j + 2][i + 1]));
+          if (wz && gz == 0) usm = 0.0;
+          if (wz && gz == nz - 1) usp = 0.0;
           div = div + lz * (usp - usm);
         }
         const int c = gz * nx + gx;
@@ -784,6 +810,9 @@ struct Imex {
   // t: 1/(rho c^2)) and b, once the first residual is formed, the second p.
   int solve_cg(double tol, int max_iter, int* its) {
     const unsigned nb = nblk(L.n);
+    // bit a: the physical axis a is walled at both ends
+    const int wallmask = (P.bcx[0] == BC_WALL ? 1 : 0) | (DIM == 3 && P.bcy[0] == BC_WALL ? 2 : 0) |
+                         (P.bcz[0] == BC_WALL ? 4 : 0);
     const unsigned gb = nb < (unsigned)CG_BLOCKS ? nb : (unsigned)CG_BLOCKS;  // k_cg_xr
     unsigned ga = gb;                                                          // the product
     if (DIM == 2) {
@@ -819,10 +848,10 @@ struct Imex {
       double* pn = pv[(it + 1) & 1];
       if (DIM == 2)
         hipLaunchKernelGGL(k_cg_apply_2d, dim3(ga), dim3(BS), 0, s, P, d_dt, L.r, po, pn, L.rh, L.sv, L.t, L.v,
-                           part_rr, (int)gb, part_pq, L.sc, it);
+                           part_rr, (int)gb, part_pq, L.sc, it, wallmask);
       else
         hipLaunchKernelGGL(k_cg_apply<DIM>, dim3(ga), dim3(BS), 0, s, P, d_dt, L.r, po, pn, L.rh, L.sv, L.t, L.v,
-                           part_rr, (int)gb, part_pq, L.sc, it);
+                           part_rr, (int)gb, part_pq, L.sc, it, wallmask);
       hipLaunchKernelGGL(k_cg_xr, dim3(gb), dim3(BS), 0, s, L.n, pn, L.v, L.x, L.r, part_pq, (int)ga, part_rr, L.sc,
                          it);
       if (it % CG_CHECK == CG_CHECK - 1 || it + 1 == max_iter) {
@@ -885,9 +914,14 @@ static int imex_steps(const Params& P, double* d_state, double* d_tmp, Control* 
     M.d_dt = d_dt_sched + st;
     if (launch_ref_forward(P, src, M.L.W, M.d_dt, s) != hipSuccess) return ARS_EDEVICE;
     int its = 0;
-    const bool periodic = P.bcx[0] == BC_PERIODIC && P.bcz[0] == BC_PERIODIC && (DIM == 2 || P.bcy[0] == BC_PERIODIC) &&
-                          P.nx >= 2 && P.nz >= 2 && (DIM == 2 || P.ny >= 2) && P.ncell < (1LL << 31) - (long long)BS;
-    const int rc = periodic ? M.solve_cg(tol, max_iter, &its) : M.solve(tol, max_iter, &its);
+    // conjugate gradients where the operator is symmetric: every axis
+    // periodic or walled at both ends
+    auto sym = [](const int* bc) {
+      return (bc[0] == BC_PERIODIC && bc[1] == BC_PERIODIC) || (bc[0] == BC_WALL && bc[1] == BC_WALL);
+    };
+    const bool symmetric = sym(P.bcx) && sym(P.bcz) && (DIM == 2 || sym(P.bcy)) && P.nx >= 2 && P.nz >= 2 &&
+                           (DIM == 2 || P.ny >= 2) && P.ncell < (1LL << 31) - (long long)BS;
+    const int rc = symmetric ? M.solve_cg(tol, max_iter, &its) : M.solve(tol, max_iter, &its);
     total += its;
     if (rc != ARS_OK) {
       if (h_iters) *h_iters = total;

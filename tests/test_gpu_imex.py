@@ -2,8 +2,8 @@
 
 The oracle solves the implicit system for (Pi, u) with a direct sparse
 solver, the GPU the eliminated system for Pi to a relative residual of
-1e-13 (conjugate gradients when every side is periodic, BiCGSTAB
-otherwise); the states are compared with the scale-aware 1e-12 measure of
+1e-13 (conjugate gradients when every axis is periodic or walled, as in
+every case here but the outflow one, BiCGSTAB otherwise); the states are compared with the scale-aware 1e-12 measure of
 tests/parity.py.  Without the low-Mach correction the acoustic
 dissipation (taken at t^n) limits the step to about the acoustic one, so
 those cases run at 0.8 times the explicit step.
