@@ -196,6 +196,7 @@ def imex_leg(torch, A, W, n=1024, Ma=1e-3, expl_steps=5000, tol=1e-10):
     the transport + diffusive CFL step (dt_mode 2, CFL 0.4: about 440 times
     the acoustic one)."""
     cfg, prob, prm, seed = W.gresho(n=n, Ma=Ma, low_mach=1)
+    A.Solver(cfg).init(prob, prm, seed).step(20)  # the explicit kernels loaded before the timed run
     E = A.Solver(cfg).init(prob, prm, seed)
     d0 = E.diagnostics()
     expl_ms = timed(torch, lambda: E.step(expl_steps))
@@ -205,6 +206,10 @@ def imex_leg(torch, A, W, n=1024, Ma=1e-3, expl_steps=5000, tol=1e-10):
     dt_cfl = S2.dt.item()
     nst = max(1, int(np.ceil(t_end / dt_cfl)))
     sched = torch.full((nst,), t_end / nst, dtype=torch.float64, device="cuda")
+    # one IMEX step on a scratch solver first: the timed run then finds its
+    # kernels loaded, as the explicit run (timed after its own first steps
+    # in the main leg) does
+    A.Solver(cfg).init(prob, prm, seed).step_imex(sched[:1], tol=tol, max_iter=20000)
     S = A.Solver(cfg).init(prob, prm, seed)
     S.imex_workspace()  # allocated before the timed region, as the explicit run's buffers are
     its = {}
