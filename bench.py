@@ -231,6 +231,16 @@ def imex_leg(torch, A, W, n=1024, Ma=1e-3, expl_steps=5000, tol=1e-10):
             "unknowns": 3 * n * n}
 
 
+def recomputed_steps(A, n, s):
+    """Forward steps the adjoint sweep recomputes: the plan's advances after
+    its first adjoint step (its forward sweep before that is the forward
+    run itself)."""
+    from paper_1903_09043_amd.adjoint import OP_ADJOINT, OP_ADVANCE
+    plan, _ = A.revolve_plan(n, s)
+    first = next(i for i, (op, _, _) in enumerate(plan) if op == OP_ADJOINT)
+    return sum(arg - step for op, step, arg in plan[first:] if op == OP_ADVANCE)
+
+
 def adjoint_leg(torch, A, W, nsteps=200, slots=16, reps=10, end_to_end=True, k=20):
     """Adjoint/forward ratio on the 3D RB 128^3 workload: per step (k
     consecutive adjoint steps vs k consecutive fused steps at the same
@@ -286,6 +296,19 @@ def adjoint_leg(torch, A, W, nsteps=200, slots=16, reps=10, end_to_end=True, k=2
     first_ms = timed(torch, grad)
     grad_ms = sorted(timed(torch, grad) for _ in range(3))[1]
     ok = bool(torch.isfinite(x.grad).all().item()) and mu.grad is not None
+    g16 = (x.grad.clone(), mu.grad.clone(), ka.grad.clone())
+    # the same gradient with every state kept (nsteps slots: 200 x 84 MB of
+    # the 288 GB HBM), so nothing is recomputed
+    pb_all = RBProblem(cfg, prob, prm, nsteps, nsteps)
+
+    def grad_all():
+        x.grad = mu.grad = ka.grad = None
+        J = rb_kinetic_energy(x, mu, ka, pb_all)
+        J.backward()
+    grad_all()
+    all_ms = sorted(timed(torch, grad_all) for _ in range(3))[1]
+    same = bool(torch.equal(x.grad, g16[0]) and torch.equal(mu.grad, g16[1]) and torch.equal(ka.grad, g16[2]))
+    del pb_all
     return {"workload": f"3D Rayleigh-Benard 128^3, Ra=1e5, Pr=1, {nsteps} steps, {slots} revolve slots, "
                         f"J = final kinetic energy, gradient w.r.t. dT0 (128^3 field), mu, kappa",
             "step_ms_forward": round(f_ms, 4), "step_ms_adjoint": round(a_ms, 4),
@@ -293,7 +316,11 @@ def adjoint_leg(torch, A, W, nsteps=200, slots=16, reps=10, end_to_end=True, k=2
             "forward_run_ms": round(fwd_ms, 2), "gradient_ms": round(grad_ms, 2),
             "gradient_ms_first_call": round(first_ms, 2),
             "ratio_end_to_end": round(grad_ms / fwd_ms, 3),
-            "recomputed_forward_steps": int(A.revolve_cost(nsteps, slots)), "gradient_finite": ok}
+            "plan_forward_steps": int(A.revolve_cost(nsteps, slots)),
+            "recomputed_forward_steps": recomputed_steps(A, nsteps, slots), "gradient_finite": ok,
+            "store_all": {"slots": nsteps, "snapshot_GB": round(nsteps * S.U.numel() * 8 / 1e9, 1),
+                          "gradient_ms": round(all_ms, 2), "ratio_end_to_end": round(all_ms / fwd_ms, 3),
+                          "bitwise_equal_to_16_slots": same}}
 
 
 def small_configs_leg(torch, A, W):

@@ -240,6 +240,16 @@ int ars_step_noalloc(ars_ctx* ctx, double* d_state, int n_steps, double* d_t, do
 int ars_step_sched(ars_ctx* ctx, double* d_state, double* d_tmp, void* d_work, int n_steps,
                    const double* d_dt_sched, double* d_t, void* stream);
 
+/* ars_step's n_steps >= 1 steps (CFL dt on the device, *d_dt in and out,
+ * optional dt log) out of place, with no copy: step 1 reads d_in (never
+ * written), the intermediate states alternate between the scratch states
+ * d_a and d_b, and the last step writes d_out; the same argument rules and
+ * errors as ars_step_sched_to below (d_dt must not be NULL).  For the
+ * forward sweep of a checkpointing schedule, whose stores are then choices
+ * of d_out.  Asynchronous. */
+int ars_step_to(ars_ctx* ctx, const double* d_in, double* d_a, double* d_b, double* d_out, void* d_work,
+                int n_steps, double* d_t, double* d_dt, double* d_dt_log, void* stream);
+
 /* The same n_steps >= 1 steps out of place, with no copy: step 1 reads
  * d_in (never written), the intermediate states alternate between the
  * scratch states d_a and d_b (steps 1, 3, ... write d_a, steps 2, 4, ...

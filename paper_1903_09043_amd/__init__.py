@@ -84,6 +84,7 @@ SIGNATURES = [
     ("ars_step_noalloc", C.c_int, [_VP, _VP, C.c_int, _VP, _VP, _VP, _VP]),
     ("ars_step_sched", C.c_int, [_VP, _VP, _VP, _VP, C.c_int, _VP, _VP, _VP]),
     ("ars_step_sched_to", C.c_int, [_VP, _VP, _VP, _VP, _VP, _VP, C.c_int, _VP, _VP, _VP]),
+    ("ars_step_to", C.c_int, [_VP, _VP, _VP, _VP, _VP, _VP, C.c_int, _VP, _VP, _VP, _VP]),
     ("ars_workspace_bytes_ref", C.c_size_t, [_VP]),
     ("ars_workspace_bytes_imex", C.c_size_t, [_VP]),
     ("ars_step_imex", C.c_int, [_VP, _VP, _VP, _VP, _VP, C.c_int, _VP, _VP, C.c_double, C.c_int,
@@ -363,6 +364,17 @@ class Solver:
         _check(lib().ars_step_sched(self.ctx.h, _ptr(self.U), _ptr(self.tmp), _ptr(self.work), dt_sched.numel(),
                                     _ptr(dt_sched), _ptr(self.t), self.stream), "ars_step_sched")
         return self
+
+    def step_to(self, U_in, U_out, a, b, n, dt_log=None):
+        """n CFL steps from U_in (read only) into U_out with the scratch
+        states a, b and no copy (ars_step_to); self.U is not touched,
+        self.t and self.dt are advanced, dt_log (n doubles) receives the
+        dts."""
+        L = self.ctx.state_len
+        _check(lib().ars_step_to(self.ctx.h, self._arg(U_in, L, "U_in"), self._arg(a, L, "a"), self._arg(b, L, "b"),
+                                 self._arg(U_out, L, "U_out"), _ptr(self.work), int(n), _ptr(self.t), _ptr(self.dt),
+                                 self._arg(dt_log, int(n), "dt_log"), self.stream), "ars_step_to")
+        return U_out
 
     def step_sched_to(self, U_in, U_out, a, b, dt_sched):
         """len(dt_sched) steps from U_in (read only) into U_out with the

@@ -73,34 +73,72 @@ class RBProblem:
         return self.build(self._base, dT0).clone()
 
 
-def run_plan(S, plan, snaps, log, lam, lam_next, pg):
-    """Execute a revolve plan without state copies: the current state is
-    wherever it was last written (a snapshot or one of four scratch
-    states); a restore only selects its snapshot, an advance runs out of
-    place (ars_step_sched_to) with its last step written straight into the
-    snapshot a following store names, and the adjoint step reads the
-    current state in place.  lam and lam_next alternate; returns the one
-    that holds the last adjoint."""
-    # four scratch states: with the current state and the output among
-    # them, two remain for the advance's ping-pong
-    scratch = [S.U, S.tmp, torch.empty_like(S.U), torch.empty_like(S.U)]
+def scratch_states(S):
+    """Four scratch states for the executors below (the solver's state and
+    scratch and two more): with the current state and an advance's output
+    among them, two remain for its ping-pong."""
+    return [S.U, S.tmp, torch.empty_like(S.U), torch.empty_like(S.U)]
+
+
+def _advance(S, plan, i, cur, snaps, scratch, log, adaptive):
+    """The advance plan[i] out of place from cur, its last step written
+    straight into the snapshot a following store names (that store is then
+    done: the returned index points at it); adaptive: CFL steps that log
+    their dt into log, else the logged dts.  Returns (index, output)."""
+    _, step, arg = plan[i]
+    nxt = plan[i + 1] if i + 1 < len(plan) else None
+    out = None
+    if nxt is not None and nxt[0] == OP_STORE and (snaps[nxt[2]] is not cur or arg - step >= 2):
+        out = snaps[nxt[2]]
+        i += 1
+    free = [b for b in scratch if b is not cur and b is not out]
+    if out is None:
+        out = free.pop()
+    if adaptive:
+        S.step_to(cur, out, free[0], free[1], arg - step, dt_log=log[step:arg])
+    else:
+        S.step_sched_to(cur, out, free[0], free[1], log[step:arg])
+    return i, out
+
+
+def run_to_first_adjoint(S, plan, snaps, log, scratch, adaptive):
+    """The plan's forward sweep, every operation before its first adjoint
+    step, without state copies (a restore selects its snapshot, a store is
+    the preceding advance's last write).  Returns the index of that adjoint
+    operation and the buffer holding its state (step n - 1)."""
     cur = snaps[0]
     i = 0
+    while plan[i][0] != OP_ADJOINT:
+        op, step, arg = plan[i]
+        if op == OP_RESTORE:
+            cur = snaps[arg]
+        elif op == OP_ADVANCE and arg > step:
+            i, cur = _advance(S, plan, i, cur, snaps, scratch, log, adaptive)
+        elif op == OP_STORE and snaps[arg] is not cur:
+            snaps[arg].copy_(cur)
+            cur = snaps[arg]
+        i += 1
+    return i, cur
+
+
+def run_plan(S, plan, snaps, log, lam, lam_next, pg, start=0, cur=None, scratch=None):
+    """Execute a revolve plan from operation `start` (the state of that
+    point in `cur`, default snapshot 0) without state copies: the current
+    state is wherever it was last written (a snapshot or one of the scratch
+    states); a restore only selects its snapshot, an advance runs out of
+    place (ars_step_sched_to, the logged dts) with its last step written
+    straight into the snapshot a following store names, and the adjoint
+    step reads the current state in place.  lam and lam_next alternate;
+    returns the one that holds the last adjoint."""
+    scratch = scratch_states(S) if scratch is None else scratch
+    cur = snaps[0] if cur is None else cur
+    i = start
     while i < len(plan):
         op, step, arg = plan[i]
         if op == OP_RESTORE:
             cur = snaps[arg]
         elif op == OP_ADVANCE and arg > step:
-            nxt = plan[i + 1] if i + 1 < len(plan) else None
-            out = None
-            if nxt is not None and nxt[0] == OP_STORE and (snaps[nxt[2]] is not cur or arg - step >= 2):
-                out = snaps[nxt[2]]
-                i += 1  # the store is this advance's last write
-            free = [b for b in scratch if b is not cur and b is not out]
-            if out is None:
-                out = free.pop()
-            S.step_sched_to(cur, out, free[0], free[1], log[step:arg])
-            cur = out
+            i, cur = _advance(S, plan, i, cur, snaps, scratch, log, False)
         elif op == OP_STORE:
             if snaps[arg] is not cur:
                 snaps[arg].copy_(cur)
@@ -117,23 +155,35 @@ class _RBObjective(torch.autograd.Function):
     def forward(ctx, dT0, mu, kappa, problem):
         S = problem.solver(mu.item(), kappa.item())
         U0 = problem.build(S, dT0).clone()
-        n = problem.nsteps
-        if problem.dt_sched is not None:
-            log = problem.dt_sched.to(problem.device, torch.float64).contiguous()
-            S.step_sched(log)
-        else:
+        n, s = problem.nsteps, problem.slots
+        plan, _ = revolve_plan(n, s)
+        snaps = [U0] + [torch.empty_like(U0) for _ in range(s - 1)]
+        scratch = scratch_states(S)
+        adaptive = problem.dt_sched is None
+        if adaptive:
             log = torch.zeros(n, dtype=torch.float64, device=problem.device)
-            S.step(n, dt_log=log)
-        grad = torch.empty_like(S.U)
-        if problem.objective == "kinetic_energy":
-            J = S.kinetic_energy(grad=grad).clone()
         else:
-            J = S.nusselt(0 if problem.objective == "nu_bot" else 1, grad=grad).clone()
+            log = problem.dt_sched.to(problem.device, torch.float64).contiguous()
+        # the plan's forward sweep is the forward run itself (its CFL dts
+        # logged), so the adjoint sweep starts at its first adjoint step
+        start, cur = run_to_first_adjoint(S, plan, snaps, log, scratch, adaptive)
+        free = [b for b in scratch if b is not cur]
+        Un = free[0]
+        if adaptive:
+            S.step_to(cur, Un, free[1], free[2], 1, dt_log=log[n - 1:n])
+        else:
+            S.step_sched_to(cur, Un, free[1], free[2], log[n - 1:n])
+        grad = torch.empty_like(U0)
+        if problem.objective == "kinetic_energy":
+            J = S.kinetic_energy(U=Un, grad=grad).clone()
+        else:
+            J = S.nusselt(0 if problem.objective == "nu_bot" else 1, U=Un, grad=grad).clone()
         rc, cell = S.fault()
         if rc != 0:
             raise ArsError(rc, f"forward run (fault at cell {cell})")
         ctx.problem = problem
         ctx.S = S
+        ctx.run = (plan, snaps, scratch, start, cur)
         ctx.save_for_backward(U0, log, grad)
         return J.reshape(())
 
@@ -141,13 +191,12 @@ class _RBObjective(torch.autograd.Function):
     def backward(ctx, gJ):
         problem, S = ctx.problem, ctx.S
         U0, log, gradN = ctx.saved_tensors
-        n, s = problem.nsteps, problem.slots
-        plan, _ = revolve_plan(n, s)
-        snaps = [U0] + [torch.empty_like(U0) for _ in range(s - 1)]
+        plan, snaps, scratch, start, cur = ctx.run
         lam = gradN * gJ.to(gradN.dtype)
         lam_next = torch.empty_like(lam)
         pg = torch.zeros(2, dtype=torch.float64, device=problem.device)
-        lam = run_plan(S, plan, snaps, log, lam, lam_next, pg)
+        lam = run_plan(S, plan, snaps, log, lam, lam_next, pg, start=start, cur=cur, scratch=scratch)
+        ctx.run = None
         g_dT = S.init_rb_dT_adjoint(U0, lam)
         return g_dT, pg[0].reshape(()), pg[1].reshape(()), None
 

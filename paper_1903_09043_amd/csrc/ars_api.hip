@@ -527,6 +527,31 @@ int ars_step_sched(ars_ctx* ctx, double* d_state, double* d_tmp, void* d_work, i
   return ARS_OK;
 }
 
+int ars_step_to(ars_ctx* ctx, const double* d_in, double* d_a, double* d_b, double* d_out, void* d_work, int n,
+                double* d_t, double* d_dt, double* d_dt_log, void* stream) {
+  if (!ctx || !d_in || !d_a || !d_b || !d_out || !d_work || !d_dt || n < 1 || d_a == d_b || d_in == d_a ||
+      d_in == d_b || d_out == d_a || d_out == d_b || (n == 1 && d_out == d_in))
+    return ARS_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  ars::Control* ctl = ctl_of(d_work);
+  if (ars::launch_ctl_prep(ctl, 1, s) != hipSuccess) return ARS_EDEVICE;
+  const double* src = d_in;
+  for (int st = 0; st < n; ++st) {
+    double* dst = st + 1 == n ? d_out : (st % 2 == 0 ? d_a : d_b);
+    ars::StepIO io{};
+    io.rate_in = st == 0 ? nullptr : &ctl->lammax[st % 3];
+    io.dt_in = d_dt;
+    io.rate_out = &ctl->lammax[(st + 1) % 3];
+    io.clear_slot = &ctl->lammax[(st + 2) % 3];
+    io.t = d_t;
+    io.dt_log = d_dt_log ? d_dt_log + st : nullptr;
+    io.ctl = ctl;
+    if (ars::launch_step_fused(ctx->P, src, dst, io, ctx->ts, s) != hipSuccess) return ARS_EDEVICE;
+    src = dst;
+  }
+  return check(ars::launch_dt_finish(ctx->P, ctl, n % 3, d_dt, s));
+}
+
 int ars_step_sched_to(ars_ctx* ctx, const double* d_in, double* d_a, double* d_b, double* d_out, void* d_work,
                       int n, const double* d_dt_sched, double* d_t, void* stream) {
   if (!ctx || !d_in || !d_a || !d_b || !d_out || !d_work || !d_dt_sched || n < 1 || d_a == d_b || d_in == d_a ||

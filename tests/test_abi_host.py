@@ -173,6 +173,11 @@ def test_step_sched_to_rejects_aliasing():
     assert f(ctx.h, i, a, b, o, w, 0, d, None, None) == A.EINVAL   # no step
     assert f(ctx.h, i, a, b, o, None, 2, d, None, None) == A.EINVAL  # no workspace
     assert f(ctx.h, i, a, b, o, w, 2, None, None, None) == A.EINVAL  # no schedule
+    g = A.lib().ars_step_to  # the same rules for the CFL-step form, which also needs d_dt
+    assert g(ctx.h, i, a, a, o, w, 2, None, d, None, None) == A.EINVAL   # a == b
+    assert g(ctx.h, i, a, b, i, w, 1, None, d, None, None) == A.EINVAL   # one step in place
+    assert g(ctx.h, i, a, b, a, w, 2, None, d, None, None) == A.EINVAL   # out == a
+    assert g(ctx.h, i, a, b, o, w, 2, None, None, None, None) == A.EINVAL  # no dt
 
 
 def test_spectrum_host_side():

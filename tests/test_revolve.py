@@ -79,6 +79,13 @@ class _LabelSolver:
             b.fill_(float("nan"))
         U_out.fill_(start + n)
 
+    def step_to(self, U_in, U_out, a, b, n, dt_log=None):
+        """CFL steps: the same rules, and each step logs its index as dt."""
+        start = U_in.item()
+        self.step_sched_to(U_in, U_out, a, b, self.torch.zeros(n, dtype=self.torch.float64))
+        if dt_log is not None:
+            dt_log.copy_(self.torch.arange(start, start + n, dtype=self.torch.float64))
+
     def step_adjoint(self, U_n, lam, dt, lam_n=None, param_grad=None):
         self.seen.append((int(dt[0].item()), U_n.item()))
         lam_n.copy_(lam + 1)
@@ -102,3 +109,30 @@ def test_copy_free_plan_executor(n, s):
     assert S.seen == [(k, float(k)) for k in range(n - 1, -1, -1)]
     assert out.item() == n
     assert U0.item() == 0.0
+
+
+@pytest.mark.parametrize("n,s", [(200, 16), (50, 4), (10, 3), (7, 7), (30, 1), (5, 2), (1, 1)])
+def test_forward_sweep_then_adjoint_sweep(n, s):
+    """As the autograd objective runs it: the plan's forward sweep with CFL
+    steps that log their dts (run_to_first_adjoint), state n from state
+    n - 1 for the objective, then the adjoint sweep from the first adjoint
+    step on the logged dts: every adjoint step sees its own state, and the
+    log holds every step's dt."""
+    import torch
+    from paper_1903_09043_amd.adjoint import run_plan, run_to_first_adjoint, scratch_states
+    plan, _ = A.revolve_plan(n, s)
+    S = _LabelSolver(torch)
+    U0 = torch.zeros(1, dtype=torch.float64)
+    snaps = [U0] + [torch.full((1,), float("nan"), dtype=torch.float64) for _ in range(s - 1)]
+    scratch = scratch_states(S)
+    log = torch.full((n,), float("nan"), dtype=torch.float64)
+    start, cur = run_to_first_adjoint(S, plan, snaps, log, scratch, True)
+    assert plan[start][0] == 3 and plan[start][1] == n - 1 and cur.item() == n - 1
+    free = [b for b in scratch if b is not cur]
+    S.step_to(cur, free[0], free[1], free[2], 1, dt_log=log[n - 1:n])
+    assert free[0].item() == n and cur.item() == n - 1
+    assert torch.equal(log, torch.arange(n, dtype=torch.float64))
+    lam = torch.zeros(1, dtype=torch.float64)
+    out = run_plan(S, plan, snaps, log, lam, torch.empty_like(lam), None, start=start, cur=cur, scratch=scratch)
+    assert S.seen == [(k, float(k)) for k in range(n - 1, -1, -1)]
+    assert out.item() == n and U0.item() == 0.0
