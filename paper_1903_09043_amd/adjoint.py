@@ -8,9 +8,13 @@ from the Rayleigh-Benard base state heated by the temperature perturbation
 Nusselt number at the bottom / top wall); its backward returns
 dJ/d(dT0), dJ/dmu and dJ/dkappa.  The time step of every step is the one the
 forward run chose (the schedule is recorded and frozen: dt = CFL / max rate
-is not differentiated).  Intermediate states are not kept: the backward
+is not differentiated).  Intermediate states are not all kept: the run
 follows a binomial checkpointing plan (``ars_revolve_plan``) over
-``problem.slots`` state snapshots, recomputing forward steps between them.
+``problem.slots`` state snapshots.  The forward pass is the plan's forward
+sweep (the snapshots written as the run goes), and the backward resumes the
+plan at its first adjoint step, recomputing forward steps between
+snapshots; no state is copied (out-of-place steps write each snapshot
+directly, a restore only selects one).
 
 Everything numerical runs in libars.so (forward steps, adjoint steps,
 objective and its gradient); this module only sequences the calls.  Rayleigh
