@@ -810,7 +810,9 @@ struct Imex {
   // t: 1/(rho c^2)) and b, once the first residual is formed, the second p.
   int solve_cg(double tol, int max_iter, int* its) {
     const unsigned nb = nblk(L.n);
-    // bit a: the physical axis a is walled at both ends
+    // bit a: the physical axis a is walled at both ends (a configuration
+    // admits walls on the vertical axis only; the products take the mask
+    // per axis all the same)
     const int wallmask = (P.bcx[0] == BC_WALL ? 1 : 0) | (DIM == 3 && P.bcy[0] == BC_WALL ? 2 : 0) |
                          (P.bcz[0] == BC_WALL ? 4 : 0);
     const unsigned gb = nb < (unsigned)CG_BLOCKS ? nb : (unsigned)CG_BLOCKS;  // k_cg_xr
