@@ -54,6 +54,8 @@ CASES = {
     # name: (setup, flow amplitude, dt multiple of the explicit CFL step, steps)
     "rb2d_walls": (lambda: W.rb([24, 12], [2.0, 1.0], Ra=1e4, seed=3, amp=1e-2), 1e-2, 4.0, 4),
     "rb2d_thetaoff": (lambda: W.rb([20, 10], [2.0, 1.0], Ra=1e4, seed=1, amp=1e-2, low_mach=0), 1e-2, 0.8, 4),
+    # two ragged x tiles and three ragged z tiles of the 2D LDS product, walls at both ends
+    "rb2d_walls_ragged_tiles": (lambda: W.rb([70, 37], [2.0, 1.0], Ra=1e4, seed=4, amp=1e-2), 1e-2, 4.0, 3),
     "rb3d_walls": (lambda: W.rb([9, 7, 8], [1.0, 1.0, 1.0], Ra=1e5, seed=2, amp=1e-2), 1e-2, 3.0, 3),
     "gresho_on": (lambda: W.gresho(n=32, Ma=1e-2, low_mach=1), 0.0, 8.0, 4),
     "gresho_off": (lambda: W.gresho(n=24, Ma=1e-2, low_mach=0), 0.0, 0.8, 4),
