@@ -68,7 +68,9 @@ struct ImexLayout {
   double* sv;
   double* t;
   double* b;
-  double* part;     // partial sums (one per block of a reduction; CG: two sets)
+  double* r2;       // CG, 2D: the second residual and product of the ping-pong
+  double* q2;
+  double* part;     // partial sums (one per block of a reduction; CG: up to two sets of four)
   double* sc;       // scalars
 };
 
@@ -94,7 +96,9 @@ ImexLayout layout_of(const Params& P, void* work) {
   L.sv = take(L.n);
   L.t = take(L.n);
   L.b = take(L.n);
-  L.part = take(2 * (CG_BLOCKS > DOT_BLOCKS ? CG_BLOCKS : DOT_BLOCKS));
+  L.r2 = take(L.n);
+  L.q2 = take(L.n);
+  L.part = take(8 * (CG_BLOCKS > DOT_BLOCKS ? CG_BLOCKS : DOT_BLOCKS));
   L.sc = take(SC_N);
   return L;
 }
@@ -410,15 +414,17 @@ __global__ void k_bicg_scalars(double* __restrict__ sc) {
 // operator stays symmetric.  Outflow copies make u* at the boundary face
 // the edge cell's velocity, which breaks the symmetry: BiCGSTAB there.)
 // The operator is a star stencil of radius 2 on the unknowns (neighbour
-// indices wrapped on periodic axes, clamped on walled ones), so an
+// indices wrapped on periodic axes, clamped on walled ones).  In 3D an
 // iteration is two streaming kernels: (1) p = r + beta p_old and q = A p
-// on the fly (p_old and r read with periodic wrap), with the block sums of
-// (p, q); (2) x += alpha p, r -= alpha q, with those of (r, r).  Each
-// kernel starts by adding the other's block sums itself, every block in the
-// same fixed order (so every block forms the same alpha or beta bit for bit,
-// and no one-block launch sits between them).  A last-block-arrives
-// reduction would need device-scope fences (one per block, an L2 write-back
-// each on a part whose XCDs have L2s of their own), which cost far more.
+// on the fly, with the block sums of (p, q); (2) x += alpha p,
+// r -= alpha q, with those of (r, r).  In 2D it is one kernel
+// (k_cg_iter_2d, through an LDS tile): the previous iteration's x, r
+// updates are done on the fly as well.  Each kernel starts by adding the
+// block sums it needs itself, every block in the same fixed order (so every
+// block forms the same alpha and beta bit for bit, and no one-block launch
+// sits between kernels).  A last-block-arrives reduction would need
+// device-scope fences (one per block, an L2 write-back each on a part whose
+// XCDs have L2s of their own), which cost far more.
 
 // Coefficients of the homogeneous operator per interior cell: tau, 1/(rho c)
 // and 1/(rho c^2) (the rows' scale), out of the padded workspace.
@@ -561,30 +567,80 @@ __global__ __launch_bounds__(BS) void k_cg_apply(Params P, const double* __restr
   if (threadIdx.x == 0) part_pq[blockIdx.x] = tot;
 }
 
-// The same product for 2D, through LDS: a tile of CT_X x CT_Z cells
-// stages p (formed from r and p_old) with its periodic halo of 2, and tau
-// and 1/(rho c) with their halo of 1, so each value is read from memory
-// once per tile instead of once per stencil point (29 loads a cell become
-// about 6).  Tiles in row-major order, a contiguous run per block and the
-// blocks of one XCD together, as above.
+// The 2D product goes through LDS: a tile of CT_X x CT_Z cells stages p
+// with its halo of 2 (periodic images or, on a walled axis, the wall cell),
+// and tau and 1/(rho c) with their halo of 1, so each value is read from
+// memory once per tile instead of once per stencil point (29 loads a cell
+// become about 8).  Tiles in row-major order, a contiguous run per block
+// and the blocks of one XCD together, as above.
 constexpr int CT_X = 64, CT_Z = 16;
 constexpr int CP_X = CT_X + 4, CP_Z = CT_Z + 4;  // p with halo 2
 constexpr int CC_X = CT_X + 2, CC_Z = CT_Z + 2;  // tau, 1/(rho c) with halo 1
 static_assert((CT_X * CT_Z) % BS == 0 && CT_X % 64 == 0, "tile rows are whole waves");
 
-__global__ __launch_bounds__(BS) void k_cg_apply_2d(Params P, const double* __restrict__ d_dt,
-                                                    const double* __restrict__ r, const double* __restrict__ pold,
-                                                    double* __restrict__ pnew, const double* __restrict__ tau,
-                                                    const double* __restrict__ irc, const double* __restrict__ irc2,
-                                                    double* __restrict__ q, const double* __restrict__ part_rr,
-                                                    int nb_rr, double* __restrict__ part_pq, double* __restrict__ sc,
-                                                    int it, int wallmask) {
+// One whole CG iteration in 2D, i >= 0, in one kernel.  From the previous
+// iteration's r, q = A p and p (stencil reads through the LDS tile) and the
+// block sums of its (p, q), (r, q), (q, q), (r, r): alpha = (r, r) / (p, q),
+// the new (r, r) = (r, r) - 2 alpha (r, q) + alpha^2 (q, q) (the expansion
+// of |r - alpha q|^2 over one step from exact sums: no drift accumulates),
+// beta = new (r, r) / (r, r); then at every cell r' = r - alpha q,
+// p' = r' + beta p, x += alpha p (own cells), q' = A p', and the block sums
+// of (p', q'), (r', q'), (q', q') and the exact (r', r').  Iteration 0 takes
+// alpha = beta = 0 (r' = r, p' = r).  Four sums per block in the layout
+// part[k * pstride + block].
+__device__ __forceinline__ void block_sum4(double (&v)[4]) {
+  __shared__ double sh4[4][BS / 64];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) v[k] = v[k] + __shfl_xor(v[k], m, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) sh4[k][threadIdx.x >> 6] = v[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    double t = sh4[k][0];
+#pragma unroll
+    for (int w = 1; w < BS / 64; ++w) t = t + sh4[k][w];
+    v[k] = t;
+  }
+}
+
+enum { CGS_PQ = 0, CGS_RQ, CGS_QQ, CGS_RR };
+
+__global__ __launch_bounds__(BS) void k_cg_iter_2d(Params P, const double* __restrict__ d_dt,
+                                                   const double* __restrict__ rin, const double* __restrict__ qin,
+                                                   const double* __restrict__ pin, double* __restrict__ rout,
+                                                   double* __restrict__ qout, double* __restrict__ pout,
+                                                   double* __restrict__ x, const double* __restrict__ tau,
+                                                   const double* __restrict__ irc, const double* __restrict__ irc2,
+                                                   const double* __restrict__ pprev, double* __restrict__ pcur,
+                                                   int pstride, double* __restrict__ sc, int it, int wallmask) {
   __shared__ double sP[CP_Z][CP_X];
   __shared__ double sT[CC_Z][CC_X];
   __shared__ double sI[CC_Z][CC_X];
+  __shared__ double sR[CT_Z][CT_X];
   __shared__ int colm[CP_X];
   __shared__ int rowm[CP_Z];
-  const double beta = cg_beta(part_rr, nb_rr, sc, it);
+  double alpha = 0.0, beta = 0.0;
+  if (it > 0) {
+    double v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      double a = 0.0;
+      for (int i = threadIdx.x; i < (int)gridDim.x; i += BS) a = a + pprev[k * pstride + i];
+      v[k] = a;
+    }
+    block_sum4(v);
+    const double rr = v[CGS_RR];
+    alpha = v[CGS_PQ] != 0.0 ? rr / v[CGS_PQ] : 0.0;
+    const double rrn = (rr - 2.0 * alpha * v[CGS_RQ]) + (alpha * alpha) * v[CGS_QQ];
+    beta = rr != 0.0 ? rrn / rr : 0.0;
+    __syncthreads();
+  }
   const double dt = *d_dt;
   const double lx = dt / P.dx[0], lz = dt / P.dx[2], hK = P.hK;
   const int nx = P.nx, nz = P.nz;
@@ -595,11 +651,9 @@ __global__ __launch_bounds__(BS) void k_cg_apply_2d(Params P, const double* __re
   const unsigned lw = (G % 8 == 0) ? (b % 8) * (G / 8) + b / 8 : b;
   const int t0 = (int)((long long)tiles * lw / G), t1 = (int)((long long)tiles * (lw + 1) / G);
   const int tid = threadIdx.x;
-  double s = 0.0;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
   for (int t = t0; t < t1; ++t) {
     const int x0 = (t % tx) * CT_X, z0 = (t / tx) * CT_Z;
-    // the cells behind the tile's halo columns and rows (halo 2): periodic
-    // images, or on a walled axis the nearest interior cell
     if (tid < CP_X) {
       const int v = x0 + tid - 2;
       int g = v % nx;
@@ -615,9 +669,17 @@ __global__ __launch_bounds__(BS) void k_cg_apply_2d(Params P, const double* __re
     for (int e = tid; e < CP_X * CP_Z; e += BS) {
       const int j = e / CP_X, i = e - j * CP_X;
       const int idx = rowm[j] + colm[i];
-      const double v = r[idx] + beta * pold[idx];
-      sP[j][i] = v;
-      if (j >= 2 && j < CT_Z + 2 && i >= 2 && i < CT_X + 2 && x0 + i - 2 < nx && z0 + j - 2 < nz) pnew[idx] = v;
+      const double pp = pin[idx];
+      const double rv = rin[idx] - alpha * qin[idx];
+      const double pv = rv + beta * pp;
+      sP[j][i] = pv;
+      if (j >= 2 && j < CT_Z + 2 && i >= 2 && i < CT_X + 2 && x0 + i - 2 < nx && z0 + j - 2 < nz) {
+        rout[idx] = rv;
+        pout[idx] = pv;
+        x[idx] = x[idx] + alpha * pp;
+        sR[j - 2][i - 2] = rv;
+        acc[CGS_RR] = acc[CGS_RR] + rv * rv;
+      }
     }
     for (int e = tid; e < CC_X * CC_Z; e += BS) {
       const int j = e / CC_X, i = e - j * CC_X;
@@ -641,7 +703,7 @@ __global__ __launch_bounds__(BS) void k_cg_apply_2d(Params P, const double* __re
           const double up = -(lx * sT[j + 1][i + 2]) * (0.5 * (Pp2 - P0));
           double usm = 0.5 * (um + uc) - (P0 - Pm1) * (hK * dmin2(sI[j + 1][i], i0));
           double usp = 0.5 * (uc + up) - (Pp1 - P0) * (hK * dmin2(i0, sI[j + 1][i + 2]));
-          if (wx && gx == 0) usm = 0.0;  // wall faces carry no flux
+          if (wx && gx == 0) usm = 0.0;
           if (wx && gx == nx - 1) usp = 0.0;
           div = div + lx * (usp - usm);
         }
@@ -658,14 +720,26 @@ __global__ __launch_bounds__(BS) void k_cg_apply_2d(Params P, const double* __re
         }
         const int c = gz * nx + gx;
         const double y = P0 * irc2[c] + div;
-        q[c] = y;
-        s = s + P0 * y;
+        qout[c] = y;
+        acc[CGS_PQ] = acc[CGS_PQ] + P0 * y;
+        acc[CGS_RQ] = acc[CGS_RQ] + sR[j][i] * y;
+        acc[CGS_QQ] = acc[CGS_QQ] + y * y;
       }
     }
     __syncthreads();  // the next tile overwrites the LDS
   }
-  const double tot = block_sum(s);
-  if (threadIdx.x == 0) part_pq[blockIdx.x] = tot;
+  block_sum4(acc);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) pcur[k * pstride + blockIdx.x] = acc[k];
+  }
+}
+
+// (r, r) of the last fused 2D iteration, for the host's convergence test.
+__global__ __launch_bounds__(BS) void k_cg_check_rr(const double* __restrict__ rr_parts, int nb,
+                                                    double* __restrict__ sc) {
+  const double rr = sum_parts(rr_parts, nb);
+  if (threadIdx.x == 0) sc[SC_CG_CHK] = rr;
 }
 
 // alpha = (r, r) / (p, q), every block adding the block sums of (p, q) in
@@ -841,6 +915,15 @@ struct Imex {
       return ARS_OK;
     }
     hipLaunchKernelGGL(k_cg_coef<DIM>, dim3(nblk(P.ncell)), dim3(BS), 0, s, P, L.G, L.W, L.rh, L.sv, L.t);
+    if constexpr (DIM == 2) {
+      return iterate_2d(target, max_iter, its, ga, wallmask);
+    } else {
+      return iterate_3d(target, max_iter, its, ga, gb, wallmask);
+    }
+  }
+
+  // 3D: two kernels an iteration (k_cg_apply, k_cg_xr).
+  int iterate_3d(double target, int max_iter, int* its, unsigned ga, unsigned gb, int wallmask) {
     double* const part_pq = L.part;
     double* const part_rr = L.part + (CG_BLOCKS > DOT_BLOCKS ? CG_BLOCKS : DOT_BLOCKS);
     double* pv[2] = {L.p, L.b};  // p = 0 on entry, so the first p is r
@@ -848,16 +931,47 @@ struct Imex {
     for (; it < max_iter; ++it) {
       double* po = pv[it & 1];
       double* pn = pv[(it + 1) & 1];
-      if (DIM == 2)
-        hipLaunchKernelGGL(k_cg_apply_2d, dim3(ga), dim3(BS), 0, s, P, d_dt, L.r, po, pn, L.rh, L.sv, L.t, L.v,
-                           part_rr, (int)gb, part_pq, L.sc, it, wallmask);
-      else
-        hipLaunchKernelGGL(k_cg_apply<DIM>, dim3(ga), dim3(BS), 0, s, P, d_dt, L.r, po, pn, L.rh, L.sv, L.t, L.v,
-                           part_rr, (int)gb, part_pq, L.sc, it, wallmask);
+      hipLaunchKernelGGL(k_cg_apply<3>, dim3(ga), dim3(BS), 0, s, P, d_dt, L.r, po, pn, L.rh, L.sv, L.t, L.v,
+                         part_rr, (int)gb, part_pq, L.sc, it, wallmask);
       hipLaunchKernelGGL(k_cg_xr, dim3(gb), dim3(BS), 0, s, L.n, pn, L.v, L.x, L.r, part_pq, (int)ga, part_rr, L.sc,
                          it);
       if (it % CG_CHECK == CG_CHECK - 1 || it + 1 == max_iter) {
         hipLaunchKernelGGL(k_cg_check, dim3(1), dim3(BS), 0, s, part_rr, (int)gb, L.sc);
+        double rr = 0.0;
+        if (read(SC_CG_CHK, &rr) != ARS_OK) return ARS_EDEVICE;
+        if (!std::isfinite(rr)) return ARS_ENOCONV;
+        if (rr <= target) {
+          ++it;
+          break;
+        }
+      }
+    }
+    if (its) *its = it;
+    if (it >= max_iter) {
+      double rr = 0.0;
+      if (read(SC_CG_CHK, &rr) != ARS_OK) return ARS_EDEVICE;
+      if (!(rr <= target)) return ARS_ENOCONV;
+    }
+    return hipGetLastError() == hipSuccess ? ARS_OK : ARS_EDEVICE;
+  }
+
+  // 2D: one kernel an iteration (k_cg_iter_2d).  Iteration i reads the
+  // residual, product and direction of set (i + 1) & 1 and writes set i & 1
+  // (set 1 starts as r0, 0, 0: k_bicg_start zeroed p and v), and its four
+  // block sums go to sum set i & 1.
+  int iterate_2d(double target, int max_iter, int* its, unsigned ga, int wallmask) {
+    const int ps = CG_BLOCKS > DOT_BLOCKS ? CG_BLOCKS : DOT_BLOCKS;
+    double* R[2] = {L.r2, L.r};
+    double* Q[2] = {L.q2, L.v};
+    double* Pv[2] = {L.b, L.p};
+    double* S[2] = {L.part, L.part + 4 * ps};
+    int it = 0;
+    for (; it < max_iter; ++it) {
+      const int o = it & 1, in = o ^ 1;
+      hipLaunchKernelGGL(k_cg_iter_2d, dim3(ga), dim3(BS), 0, s, P, d_dt, R[in], Q[in], Pv[in], R[o], Q[o], Pv[o],
+                         L.x, L.rh, L.sv, L.t, S[in], S[o], ps, L.sc, it, wallmask);
+      if (it % CG_CHECK == CG_CHECK - 1 || it + 1 == max_iter) {
+        hipLaunchKernelGGL(k_cg_check_rr, dim3(1), dim3(BS), 0, s, S[o] + CGS_RR * ps, (int)ga, L.sc);
         double rr = 0.0;
         if (read(SC_CG_CHK, &rr) != ARS_OK) return ARS_EDEVICE;
         if (!std::isfinite(rr)) return ARS_ENOCONV;
@@ -900,8 +1014,8 @@ size_t imex_workspace_bytes(const Params& P) {
   const long long n = P.ncell;
   auto al = [](size_t b) { return ((b + 255) / 256) * 256; };
   size_t s = al((size_t)R_NFIELD * G.npad * sizeof(double)) + al((size_t)(P.dim + 1) * G.npad * sizeof(double));
-  s += 8 * al((size_t)n * sizeof(double));
-  s += al(2 * (CG_BLOCKS > DOT_BLOCKS ? CG_BLOCKS : DOT_BLOCKS) * sizeof(double)) + al(SC_N * sizeof(double));
+  s += 10 * al((size_t)n * sizeof(double));
+  s += al(8 * (CG_BLOCKS > DOT_BLOCKS ? CG_BLOCKS : DOT_BLOCKS) * sizeof(double)) + al(SC_N * sizeof(double));
   return s;
 }
 
