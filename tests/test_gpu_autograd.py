@@ -79,6 +79,31 @@ def test_step_sched_to_equals_step_sched(T):
     assert T.equal(buf, want[2])
 
 
+def test_step_to_equals_step(T):
+    """ars_step_to (CFL steps out of place; the objective's forward sweep)
+    gives the states, dt log, t and next dt of ars_step bit for bit."""
+    pb, cfg = make_problem(T, 3)
+    S = pb.solver(cfg["mu"], cfg["kappa"])
+    U0 = pb.build(S, T.zeros(pb.rho.shape, dtype=T.float64, device="cuda")).clone()
+    dt0 = S.compute_dt().clone()
+    a, b, out = (T.empty_like(U0) for _ in range(3))
+    for n in (1, 2, 3):
+        S.U.copy_(U0)
+        S.t.zero_()
+        S.dt.copy_(dt0)
+        log_ref = T.zeros(n, dtype=T.float64, device="cuda")
+        S.step(n, dt_log=log_ref)
+        want, t_ref, dt_ref = S.U.clone(), S.t.clone(), S.dt.clone()
+        S.t.zero_()
+        S.dt.copy_(dt0)
+        log = T.zeros(n, dtype=T.float64, device="cuda")
+        S.step_to(U0, out, a, b, n, dt_log=log)
+        T.cuda.synchronize()
+        same = T.equal(out, want) and T.equal(log, log_ref) and T.equal(S.t, t_ref) and T.equal(S.dt, dt_ref)
+        say("step_to", n, "bitwise", same)
+        assert same
+
+
 @pytest.mark.parametrize("energy_form", [0, 1])
 def test_gradient_vs_central_differences(T, energy_form):
     """Both energy forms (the relaxed total energy and App. B)."""
