@@ -19,8 +19,8 @@
 // accumulates a 16 x 16 tile over K in steps of 4).  The twiddle matrices
 // are never stored: entry (k, x) is read from an LDS table of
 // exp(-2 pi i j / n) at j = k x mod n, the exponent carried exactly in
-// integers.  Shell sums visit the plane in a fixed order and reduce
-// through a fixed tree: the result is deterministic.
+// integers.  Shell sums visit the plane in a fixed order and add the
+// threads' sums in a fixed order: the result is deterministic.
 #include "ars_dev.h"
 #include "ars_internal.h"
 
@@ -194,9 +194,9 @@ __device__ __forceinline__ double row_pair(const double* __restrict__ Pc, long l
 // i.e. (2s - 1)^2 < 4 |k|^2 < (2s + 1)^2 (4 |k|^2 is even, so no bound is
 // ever met exactly), and stores the sum / (2 N^2).  Thread t takes the rows
 // t, t + 256, ...; in a row it walks only the |kx| of the annulus, in
-// increasing order; a fixed tree then adds the threads: deterministic.
+// increasing order; the threads are added in a fixed order: deterministic.
 __global__ void __launch_bounds__(256) k_spec_shells(Params P, const double* __restrict__ Pc, double* __restrict__ E) {
-  __shared__ double red[256];
+  __shared__ double red[4];
   const int nx = P.nx, ny = P.ny, s = blockIdx.x;
   const long long N = (long long)nx * ny;
   const long long hi = (2LL * s + 1) * (2LL * s + 1);
@@ -210,13 +210,12 @@ __global__ void __launch_bounds__(256) k_spec_shells(Params P, const double* __r
     const long long ka = lo - r < 0 ? 0 : kmax_below(lo - r + 1) + 1;  // 4 kx^2 > lo - r
     for (long long k = ka; k <= kb; ++k) acc += row_pair(Pc, N, P.dim, (long long)y * nx, nx, k);
   }
-  red[threadIdx.x] = acc;
+  // fixed order: a butterfly within each wave, then the four waves in order
+#pragma unroll
+  for (int m = 32; m > 0; m >>= 1) acc = acc + __shfl_xor(acc, m, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
   __syncthreads();
-  for (int h = 128; h >= 1; h >>= 1) {
-    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) E[s] = red[0] / (2.0 * (double)N * (double)N);
+  if (threadIdx.x == 0) E[s] = (((red[0] + red[1]) + red[2]) + red[3]) / (2.0 * (double)N * (double)N);
 }
 
 // ---------------------------------------------------------------- FFT path
